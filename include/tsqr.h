@@ -1,0 +1,171 @@
+/*
+ * tsqr.h -- C ABI of libtsqr: randomized XR-preconditioned CholeskyQR of a tall and
+ * skinny FP64 matrix (Fan, Guo, Lin, "A Novel Randomized XR-Based Preconditioned
+ * CholeskyQR Algorithm", arXiv 2111.11148) on one AMD Instinct MI355X (gfx950).
+ *
+ * Problem (paper Section 1, QR equation; Section 2 opening): given a full-rank
+ * A (m x n, m >= n), return the thin factorization A = Q R with Q^T Q = I (m x n) and R
+ * upper triangular (n x n) with a positive diagonal.
+ *
+ * Conventions for every entry point
+ *   - matrices are column-major with a leading dimension: element (i, j) of X is
+ *     X[i + j*ldx] (LAPACK convention); leading dimensions are counted in elements;
+ *   - every matrix, workspace and info pointer is a DEVICE pointer owned by the caller;
+ *     the library keeps no pointer after the call returns;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream); all work is
+ *     enqueued on it in order and the host does not wait for it;
+ *   - return value: 0 on success; -i if the i-th argument (1-based) is invalid, detected
+ *     before any work is enqueued; TSQR_ERR_HIP if a HIP call fails; TSQR_ERR_WORKSPACE if
+ *     the workspace is too small; TSQR_ERR_UNSUPPORTED for sizes this build does not
+ *     implement;
+ *   - numerical breakdown is reported asynchronously through `d_info` (device int):
+ *     0 = success; 1000*stage + k = zero, non-positive or NaN pivot at column k (1-based)
+ *     of stage 1 (the sketch factor R0), 2 (first Cholesky R1) or 3 (second Cholesky R2).
+ *     After a breakdown every entry of Q and R is NaN.  Only the first breakdown is kept.
+ *
+ * The Gaussian sketch S (s x m) of paper Section 2.3 is S = Z / sqrt(s) with Z(i, j) ~
+ * N(0,1) regenerated on the fly and never stored.  Stream: key = (low, high) 32-bit
+ * halves of `seed`; one Philox4x32-10 call (Salmon et al., SC'11) with counter
+ * (low32(p), high32(p), i, 0) yields Z(i, 4p .. 4p+3): words (w0, w1) give columns 4p and
+ * 4p+1, (w2, w3) give 4p+2 and 4p+3 by the Box-Muller transform of the 24-bit uniforms
+ * u = ((wa >> 8) + 1) 2^-24 and t = (wb >> 8) 2^-24: rad = sqrt(-2 ln u),
+ * (rad cos 2 pi t, rad sin 2 pi t).  The device evaluates the transform in single precision
+ * (entries of Z are FP32 numbers, exact in FP64); the integer stream is bit-exact.
+ */
+#ifndef TSQR_H
+#define TSQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TSQR_OK 0
+#define TSQR_ERR_HIP (-100)
+#define TSQR_ERR_WORKSPACE (-101)
+#define TSQR_ERR_UNSUPPORTED (-102)
+
+#define TSQR_VARIANT_RQR 0 /* R0 from Householder QR of the sketch */
+#define TSQR_VARIANT_RLU 1 /* R0 from partial-pivot LU of the sketch */
+
+/* ------------------------------------------------------------------------------------
+ * Whole factorization
+ * ------------------------------------------------------------------------------------ */
+
+/* rQR-CholeskyQR (paper Algorithm rQR-CholeskyQR with the Gaussian sketch of Section 2.3)
+ * followed by one more CholeskyQR pass (paper Algorithm CholeskyQR2, second line):
+ *   B = S A (s x n);  R0 = R factor of B (Householder, diag > 0);  A1 = A R0^{-1};
+ *   R1 = chol(A1^T A1);  Q1 = A1 R1^{-1};  R2 = chol(Q1^T Q1);  Q = Q1 R2^{-1};
+ *   R = R2 (R1 R0).
+ * m, n        : rows and columns of A, 1 <= n <= m.                       (args 1, 2)
+ * A, lda      : input, read only, lda >= m.                               (args 3, 4)
+ * sketch_rows : s, rows of the sketch, n <= s <= 8192 (the paper uses 2n). (arg 5)
+ * seed        : sketch seed (see the stream definition above).            (arg 6)
+ * Q           : output m x n with leading dimension m; must not overlap A. (arg 7)
+ * R           : output n x n upper (strict lower part zeroed), leading dimension n;
+ *               NULL skips forming R (the R-less variant of the paper's footnote to
+ *               Algorithm CholeskyQR2).                                    (arg 8)
+ * stream      : HIP stream.                                                (arg 9)
+ * Scratch memory is taken from HIP's stream-ordered allocator on `stream`; breakdown
+ * is visible only as NaN in Q and R (use tsqr_rxr_cholqr_ws for an info word). */
+int tsqr_rqr_cholqr(int64_t m, int64_t n, const double* A, int64_t lda, int64_t sketch_rows,
+                    uint64_t seed, double* Q, double* R, void* stream);
+
+/* rLU-CholeskyQR (paper Algorithm rLU-CholeskyQR): as tsqr_rqr_cholqr with R0 taken from
+ * Gaussian elimination with partial pivoting of B (pivot = first largest |b_ik|),
+ * R0 = diag(sign u_kk) U.  Same arguments and codes. */
+int tsqr_rlu_cholqr(int64_t m, int64_t n, const double* A, int64_t lda, int64_t sketch_rows,
+                    uint64_t seed, double* Q, double* R, void* stream);
+
+/* Bytes of device workspace needed by tsqr_rxr_cholqr_ws for these sizes (0 if the sizes
+ * are invalid). */
+size_t tsqr_workspace_bytes(int64_t m, int64_t n, int64_t sketch_rows);
+
+/* Explicit-workspace form (no allocation inside; suitable for stream capture of the
+ * kernels, reuse across calls and info reporting):
+ *   variant (1): TSQR_VARIANT_RQR or TSQR_VARIANT_RLU;
+ *   m, n, A, lda, sketch_rows, seed (2-7): as above;
+ *   extra_pass (8): nonzero runs the extra CholeskyQR pass (R = R2 R1 R0), zero stops
+ *     after the first pass (Q = Q1, R = R1 R0, the paper's algorithm as printed);
+ *   Q, ldq (9, 10): output, ldq >= m, must not overlap A;
+ *   R, ldr (11, 12): output or NULL, ldr >= n;
+ *   work, work_bytes (13, 14): device workspace of at least tsqr_workspace_bytes() bytes,
+ *     256-byte aligned; its contents on entry are ignored;
+ *   d_info (15): device int written with the breakdown code, or NULL;
+ *   stream (16). */
+int tsqr_rxr_cholqr_ws(int variant, int64_t m, int64_t n, const double* A, int64_t lda,
+                       int64_t sketch_rows, uint64_t seed, int extra_pass, double* Q,
+                       int64_t ldq, double* R, int64_t ldr, void* work, size_t work_bytes,
+                       int* d_info, void* stream);
+
+/* ------------------------------------------------------------------------------------
+ * Steps of the method, one entry point per step (used for step-wise validation)
+ * ------------------------------------------------------------------------------------ */
+
+/* Sketch (paper Section 2.3, Gaussian ensemble): B = S A, B is s x n (ldb >= s).  The
+ * sum over the m rows is split into row blocks whose partial sums are added in a fixed
+ * order (deterministic).  Workspace: tsqr_sketch_workspace_bytes(m, n, s). */
+size_t tsqr_sketch_workspace_bytes(int64_t m, int64_t n, int64_t s);
+int tsqr_sketch(int64_t m, int64_t n, const double* A, int64_t lda, int64_t s, uint64_t seed,
+                double* B, int64_t ldb, void* work, size_t work_bytes, void* stream);
+
+/* R factor of the s x n sketch (paper Algorithms rQR/rLU-CholeskyQR, step 2):
+ * variant TSQR_VARIANT_RQR = Householder QR (LAPACK reflector convention), RLU = partial
+ * pivot LU; the result is sign-normalised, R0 = diag(sign d_k) * (R or U), and written as
+ * an n x n upper matrix (strict lower part zeroed, ldr >= n).  A zero or NaN diagonal at
+ * column k sets *d_info = 1000 + k (if *d_info was 0) and R0(k,k) = NaN.
+ * Workspace: at least s*n doubles (scratch of the large-size variant). */
+int tsqr_sketch_factor(int variant, int64_t s, int64_t n, const double* B, int64_t ldb,
+                       double* R0, int64_t ldr, int* d_info, void* work, size_t work_bytes,
+                       void* stream);
+
+/* Right-side upper triangular solve X = Y T^{-1} by blocked substitution (paper
+ * Algorithm CholeskyQR, step 3; row-wise backward stable, no explicit inverse).
+ * Y, X: m x n (ldy, ldx >= m); X may be the same buffer as Y with ldx == ldy (in place);
+ * T: n x n upper, only its upper triangle is read.  n <= 256. */
+int tsqr_trsm(int64_t m, int64_t n, const double* Y, int64_t ldy, const double* T, int64_t ldt,
+              double* X, int64_t ldx, void* stream);
+
+/* Gram matrix W = X^T X (paper Algorithm CholeskyQR, step 1), both triangles written
+ * (ldw >= n).  Split over row blocks, fixed-order reduction.  n <= 256.
+ * Workspace: tsqr_gram_workspace_bytes(m, n). */
+size_t tsqr_gram_workspace_bytes(int64_t m, int64_t n);
+int tsqr_gram(int64_t m, int64_t n, const double* X, int64_t ldx, double* W, int64_t ldw,
+              void* work, size_t work_bytes, void* stream);
+
+/* Cholesky W = R^T R (paper Algorithm CholeskyQR, step 2): reads the upper triangle of
+ * W, writes upper R (strict lower part zeroed).  A pivot that is not positive (or NaN)
+ * at column k sets *d_info = 1000*stage + k (if *d_info was 0) and makes R NaN from
+ * column k on.  Workspace: at least n*n doubles (scratch of the large-size variant). */
+int tsqr_potrf(int64_t n, const double* W, int64_t ldw, double* R, int64_t ldr, int stage,
+               int* d_info, void* work, size_t work_bytes, void* stream);
+
+/* C = A B for upper triangular n x n A and B (R-factor assembly, paper Algorithm
+ * rQR-CholeskyQR step 5 and Algorithm CholeskyQR2 step 3).  C must not overlap A or B. */
+int tsqr_trmm_upper(int64_t n, const double* A, int64_t lda, const double* B, int64_t ldb,
+                    double* C, int64_t ldc, void* stream);
+
+/* ------------------------------------------------------------------------------------
+ * Generator access (validation of the sketch stream)
+ * ------------------------------------------------------------------------------------ */
+
+/* d_out[4e .. 4e+3] = Philox4x32-10(counter d_ctr[4e .. 4e+3], key (low32(seed),
+ * high32(seed))) for e < count.  Device pointers. */
+int tsqr_philox4x32_10(int64_t count, const uint32_t* d_ctr, uint64_t seed, uint32_t* d_out,
+                       void* stream);
+
+/* Z(i0 + a, j0 + b) -> Zout[a + b*ldz] for a < ni, b < nj: the N(0,1) entries of the
+ * sketch before the 1/sqrt(s) scaling, exactly as the sketch kernel generates them. */
+int tsqr_sketch_normals(uint64_t seed, int64_t i0, int64_t ni, int64_t j0, int64_t nj,
+                        double* Zout, int64_t ldz, void* stream);
+
+/* Library identification string (static storage). */
+const char* tsqr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSQR_H */

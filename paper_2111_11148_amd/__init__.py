@@ -1,0 +1,272 @@
+"""Randomized XR-preconditioned CholeskyQR on AMD Instinct MI355X (gfx950).
+
+Thin Python binding of ``libtsqr.so`` (C ABI in ``include/tsqr.h``).  Every function here
+only marshals arguments: it checks dtypes, devices and column-major strides of torch
+tensors and passes their device pointers and the current HIP stream to the library.
+All arithmetic runs in the library's HIP kernels; there is no fallback path, and a
+missing or unloadable library raises.
+
+Matrices are column-major: an m x n matrix is a float64 CUDA tensor of shape (m, n) with
+strides (1, ld), ld >= m (see :func:`colmajor`).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtsqr.so")
+
+RQR = 0
+RLU = 1
+TSQR_ERR_HIP = -100
+TSQR_ERR_WORKSPACE = -101
+TSQR_ERR_UNSUPPORTED = -102
+
+_lib = None
+
+_i64, _u64, _int, _vp, _sz = (ctypes.c_int64, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p,
+                              ctypes.c_size_t)
+_SIGS = {
+    "tsqr_rqr_cholqr": (_int, [_i64, _i64, _vp, _i64, _i64, _u64, _vp, _vp, _vp]),
+    "tsqr_rlu_cholqr": (_int, [_i64, _i64, _vp, _i64, _i64, _u64, _vp, _vp, _vp]),
+    "tsqr_workspace_bytes": (_sz, [_i64, _i64, _i64]),
+    "tsqr_rxr_cholqr_ws": (_int, [_int, _i64, _i64, _vp, _i64, _i64, _u64, _int, _vp, _i64, _vp,
+                                  _i64, _vp, _sz, _vp, _vp]),
+    "tsqr_sketch_workspace_bytes": (_sz, [_i64, _i64, _i64]),
+    "tsqr_sketch": (_int, [_i64, _i64, _vp, _i64, _i64, _u64, _vp, _i64, _vp, _sz, _vp]),
+    "tsqr_sketch_factor": (_int, [_int, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _sz, _vp]),
+    "tsqr_trsm": (_int, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp]),
+    "tsqr_gram_workspace_bytes": (_sz, [_i64, _i64]),
+    "tsqr_gram": (_int, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp]),
+    "tsqr_potrf": (_int, [_i64, _vp, _i64, _vp, _i64, _int, _vp, _vp, _sz, _vp]),
+    "tsqr_trmm_upper": (_int, [_i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp]),
+    "tsqr_philox4x32_10": (_int, [_i64, _vp, _u64, _vp, _vp]),
+    "tsqr_sketch_normals": (_int, [_u64, _i64, _i64, _i64, _i64, _vp, _i64, _vp]),
+    "tsqr_version": (ctypes.c_char_p, []),
+}
+
+
+class TsqrError(RuntimeError):
+    """A libtsqr call returned a nonzero status."""
+
+
+def load() -> ctypes.CDLL:
+    """Load libtsqr.so (built by ``paper_2111_11148_amd.build``); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def version() -> str:
+    return load().tsqr_version().decode()
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != 0:
+        raise TsqrError(f"{what} failed with status {rc}")
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _mat(t: torch.Tensor, name: str, rows: int | None = None, cols: int | None = None) -> int:
+    """Validate a column-major FP64 device matrix; return its leading dimension."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch.Tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name}: expected float64, got {t.dtype}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name}: expected a GPU tensor")
+    if t.dim() != 2:
+        raise ValueError(f"{name}: expected a matrix")
+    if rows is not None and t.shape[0] != rows or cols is not None and t.shape[1] != cols:
+        raise ValueError(f"{name}: expected shape ({rows}, {cols}), got {tuple(t.shape)}")
+    r, c = t.shape
+    if c > 1 and r > 1 and t.stride(0) != 1:
+        raise ValueError(f"{name}: expected column-major strides (1, ld)")
+    ld = t.stride(1) if c > 1 else max(r, 1)
+    if ld < r:
+        raise ValueError(f"{name}: leading dimension {ld} < rows {r}")
+    return int(ld)
+
+
+def colmajor(m: int, n: int, ld: int | None = None, device="cuda", dtype=torch.float64,
+             fill=None) -> torch.Tensor:
+    """Uninitialised (or filled) m x n column-major tensor with leading dimension ld."""
+    ld = m if ld is None else ld
+    buf = torch.empty((n, ld), device=device, dtype=dtype)
+    if fill is not None:
+        buf.fill_(fill)
+    return buf.t()[:m]
+
+
+def to_device_colmajor(A, ld: int | None = None, device="cuda") -> torch.Tensor:
+    """Copy a host matrix (NumPy or torch) into a column-major device tensor."""
+    At = torch.as_tensor(A, dtype=torch.float64)
+    m, n = At.shape
+    out = colmajor(m, n, ld, device=device)
+    out.copy_(At)
+    return out
+
+
+# ------------------------------------------------------------------ whole method ----
+def workspace_bytes(m: int, n: int, sketch_rows: int) -> int:
+    return int(load().tsqr_workspace_bytes(m, n, sketch_rows))
+
+
+def alloc_workspace(m: int, n: int, sketch_rows: int, device="cuda") -> torch.Tensor:
+    nbytes = workspace_bytes(m, n, sketch_rows)
+    if nbytes == 0:
+        raise ValueError("invalid sizes for the workspace")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def rxr_cholqr(A: torch.Tensor, sketch_rows: int, seed: int, variant: int = RQR,
+               extra_pass: bool = True, Q: torch.Tensor | None = None,
+               R: torch.Tensor | None = None, want_r: bool = True,
+               workspace: torch.Tensor | None = None, info: torch.Tensor | None = None,
+               stream=None):
+    """Randomized XR-preconditioned CholeskyQR (explicit-workspace entry point).
+
+    Returns (Q, R, info) with info a 1-element int32 device tensor (0 = success)."""
+    lda = _mat(A, "A")
+    m, n = A.shape
+    if Q is None:
+        Q = colmajor(m, n, device=A.device)
+    ldq = _mat(Q, "Q", m, n)
+    if R is None and want_r:
+        R = colmajor(n, n, device=A.device)
+    ldr = _mat(R, "R", n, n) if R is not None else n
+    if workspace is None:
+        workspace = alloc_workspace(m, n, sketch_rows, device=A.device)
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    rc = load().tsqr_rxr_cholqr_ws(variant, m, n, A.data_ptr(), lda, sketch_rows, seed,
+                                   int(bool(extra_pass)), Q.data_ptr(), ldq,
+                                   R.data_ptr() if R is not None else None, ldr,
+                                   workspace.data_ptr(), workspace.numel(), info.data_ptr(),
+                                   _stream(stream))
+    _check(rc, "tsqr_rxr_cholqr_ws")
+    return Q, R, info
+
+
+def rqr_cholqr(A: torch.Tensor, sketch_rows: int, seed: int, stream=None):
+    """Plain form of the C ABI (stream-ordered scratch allocation, extra pass on)."""
+    lda = _mat(A, "A")
+    m, n = A.shape
+    Q = colmajor(m, n, device=A.device)
+    R = colmajor(n, n, device=A.device)
+    _check(load().tsqr_rqr_cholqr(m, n, A.data_ptr(), lda, sketch_rows, seed, Q.data_ptr(),
+                                  R.data_ptr(), _stream(stream)), "tsqr_rqr_cholqr")
+    return Q, R
+
+
+def rlu_cholqr(A: torch.Tensor, sketch_rows: int, seed: int, stream=None):
+    lda = _mat(A, "A")
+    m, n = A.shape
+    Q = colmajor(m, n, device=A.device)
+    R = colmajor(n, n, device=A.device)
+    _check(load().tsqr_rlu_cholqr(m, n, A.data_ptr(), lda, sketch_rows, seed, Q.data_ptr(),
+                                  R.data_ptr(), _stream(stream)), "tsqr_rlu_cholqr")
+    return Q, R
+
+
+# ------------------------------------------------------------------------- steps ----
+def sketch(A: torch.Tensor, s: int, seed: int, stream=None) -> torch.Tensor:
+    lda = _mat(A, "A")
+    m, n = A.shape
+    B = colmajor(s, n, device=A.device)
+    nbytes = int(load().tsqr_sketch_workspace_bytes(m, n, s))
+    work = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=A.device)
+    _check(load().tsqr_sketch(m, n, A.data_ptr(), lda, s, seed, B.data_ptr(), s,
+                              work.data_ptr(), nbytes, _stream(stream)), "tsqr_sketch")
+    return B
+
+
+def sketch_factor(B: torch.Tensor, variant: int = RQR, stream=None):
+    ldb = _mat(B, "B")
+    s, n = B.shape
+    R0 = colmajor(n, n, device=B.device)
+    info = torch.zeros(1, dtype=torch.int32, device=B.device)
+    work = torch.empty(s * n, dtype=torch.float64, device=B.device)
+    _check(load().tsqr_sketch_factor(variant, s, n, B.data_ptr(), ldb, R0.data_ptr(), n,
+                                     info.data_ptr(), work.data_ptr(), work.numel() * 8,
+                                     _stream(stream)), "tsqr_sketch_factor")
+    return R0, info
+
+
+def trsm(Y: torch.Tensor, T: torch.Tensor, X: torch.Tensor | None = None, stream=None):
+    ldy = _mat(Y, "Y")
+    m, n = Y.shape
+    ldt = _mat(T, "T", n, n)
+    if X is None:
+        X = colmajor(m, n, device=Y.device)
+    ldx = _mat(X, "X", m, n)
+    _check(load().tsqr_trsm(m, n, Y.data_ptr(), ldy, T.data_ptr(), ldt, X.data_ptr(), ldx,
+                            _stream(stream)), "tsqr_trsm")
+    return X
+
+
+def gram(X: torch.Tensor, stream=None) -> torch.Tensor:
+    ldx = _mat(X, "X")
+    m, n = X.shape
+    W = colmajor(n, n, device=X.device)
+    nbytes = int(load().tsqr_gram_workspace_bytes(m, n))
+    work = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=X.device)
+    _check(load().tsqr_gram(m, n, X.data_ptr(), ldx, W.data_ptr(), n, work.data_ptr(), nbytes,
+                            _stream(stream)), "tsqr_gram")
+    return W
+
+
+def potrf(W: torch.Tensor, stage: int = 2, stream=None):
+    ldw = _mat(W, "W")
+    n = W.shape[0]
+    R = colmajor(n, n, device=W.device)
+    info = torch.zeros(1, dtype=torch.int32, device=W.device)
+    work = torch.empty(n * n, dtype=torch.float64, device=W.device)
+    _check(load().tsqr_potrf(n, W.data_ptr(), ldw, R.data_ptr(), n, stage, info.data_ptr(),
+                             work.data_ptr(), work.numel() * 8, _stream(stream)), "tsqr_potrf")
+    return R, info
+
+
+def trmm_upper(A: torch.Tensor, B: torch.Tensor, stream=None) -> torch.Tensor:
+    lda = _mat(A, "A")
+    n = A.shape[0]
+    ldb = _mat(B, "B", n, n)
+    C = colmajor(n, n, device=A.device)
+    _check(load().tsqr_trmm_upper(n, A.data_ptr(), lda, B.data_ptr(), ldb, C.data_ptr(), n,
+                                  _stream(stream)), "tsqr_trmm_upper")
+    return C
+
+
+def philox4x32_10(ctr: torch.Tensor, seed: int, stream=None) -> torch.Tensor:
+    """ctr: (count, 4) int32 device tensor holding the counter words (bit patterns)."""
+    if ctr.dtype != torch.int32 or ctr.device.type != "cuda" or ctr.dim() != 2 or ctr.shape[1] != 4:
+        raise ValueError("ctr must be a (count, 4) int32 GPU tensor")
+    ctr = ctr.contiguous()
+    out = torch.empty_like(ctr)
+    _check(load().tsqr_philox4x32_10(ctr.shape[0], ctr.data_ptr(), seed, out.data_ptr(),
+                                     _stream(stream)), "tsqr_philox4x32_10")
+    return out
+
+
+def sketch_normals(seed: int, i0: int, ni: int, j0: int, nj: int, device="cuda",
+                   stream=None) -> torch.Tensor:
+    Z = colmajor(ni, nj, device=device)
+    _check(load().tsqr_sketch_normals(seed, i0, ni, j0, nj, Z.data_ptr(), max(ni, 1),
+                                      _stream(stream)), "tsqr_sketch_normals")
+    return Z

@@ -1,0 +1,360 @@
+// C ABI of libtsqr (declared in include/tsqr.h): argument validation, workspace layout
+// and the stream-ordered sequence of kernels of randomized XR-preconditioned CholeskyQR.
+#include <math.h>
+#include <string.h>
+
+#include <mutex>
+
+#include "../../include/tsqr.h"
+#include "tsqr_launch.hpp"
+
+namespace tsqr {
+
+int device_cu_count() {
+  static std::mutex mu;
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  std::lock_guard<std::mutex> g(mu);
+  if (!cache[dev]) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+    cache[dev] = cus;
+  }
+  return cache[dev];
+}
+
+namespace {
+
+constexpr int64_t kMaxSketchRows = 8192;
+constexpr int64_t kMaxN = 256;  // widest n of the tall-skinny kernels in this build
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t info, B, R0, R1, R2, R10, W, fac, part, total;
+  SketchPlan sp;
+  GramPlan gp;
+};
+
+Layout make_layout(int64_t m, int64_t n, int64_t s) {
+  Layout L{};
+  L.sp = plan_sketch(m, (int)n, (int)s);
+  L.gp = plan_gram(m, (int)n);
+  const size_t nn = (size_t)n * n * sizeof(double);
+  size_t off = 0;
+  L.info = off; off += 256;
+  L.B = off; off += align256((size_t)s * n * sizeof(double));
+  L.R0 = off; off += align256(nn);
+  L.R1 = off; off += align256(nn);
+  L.R2 = off; off += align256(nn);
+  L.R10 = off; off += align256(nn);
+  L.W = off; off += align256(nn);
+  L.fac = off; off += align256((size_t)(s > n ? s : n) * n * sizeof(double));
+  L.part = off;
+  const size_t part = L.sp.part_doubles > L.gp.part_doubles ? L.sp.part_doubles : L.gp.part_doubles;
+  off += align256(part * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+inline bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + bbytes && pb < pa + abytes;
+}
+
+inline size_t span_bytes(int64_t rows, int64_t cols, int64_t ld) {
+  return ((size_t)(cols - 1) * (size_t)ld + (size_t)rows) * sizeof(double);
+}
+
+#define TSQR_CHECK(expr)                   \
+  do {                                     \
+    if ((expr) != hipSuccess) return TSQR_ERR_HIP; \
+  } while (0)
+
+int run_chain(int variant, int64_t m, int64_t n, const double* A, int64_t lda, int64_t s,
+              uint64_t seed, int extra_pass, double* Q, int64_t ldq, double* R, int64_t ldr,
+              void* work, int* d_info, hipStream_t st) {
+  const Layout L = make_layout(m, n, s);
+  char* base = (char*)work;
+  int* info = d_info ? d_info : (int*)(base + L.info);
+  double* B = (double*)(base + L.B);
+  double* R0 = (double*)(base + L.R0);
+  double* R1 = (double*)(base + L.R1);
+  double* R2 = (double*)(base + L.R2);
+  double* R10 = (double*)(base + L.R10);
+  double* W = (double*)(base + L.W);
+  double* fac = (double*)(base + L.fac);
+  double* part = (double*)(base + L.part);
+  const int ni = (int)n, si = (int)s;
+
+  TSQR_CHECK(launch_set_int(info, 0, st));
+  // B = S A  (paper Section 2.3)
+  TSQR_CHECK(launch_sketch(L.sp, m, ni, A, lda, si, seed, part, st));
+  TSQR_CHECK(launch_sketch_reduce(L.sp, si, ni, part, 1.0 / sqrt((double)s), B, s, st));
+  // R0 = R factor of B
+  TSQR_CHECK(launch_sketch_factor(variant, si, ni, B, s, R0, n, info, fac, st));
+  // A1 = A R0^{-1} (into Q), W1 = A1^T A1, R1 = chol(W1), Q1 = A1 R1^{-1}
+  TSQR_CHECK(launch_trsm(m, ni, A, lda, R0, n, Q, ldq, st));
+  TSQR_CHECK(launch_gram(L.gp, m, ni, Q, ldq, part, st));
+  TSQR_CHECK(launch_gram_reduce(L.gp, ni, part, W, n, st));
+  TSQR_CHECK(launch_potrf(ni, W, n, R1, n, 2, info, fac, st));
+  TSQR_CHECK(launch_trsm(m, ni, Q, ldq, R1, n, Q, ldq, st));
+  if (extra_pass) {
+    // W2 = Q1^T Q1, R2 = chol(W2), Q = Q1 R2^{-1}
+    TSQR_CHECK(launch_gram(L.gp, m, ni, Q, ldq, part, st));
+    TSQR_CHECK(launch_gram_reduce(L.gp, ni, part, W, n, st));
+    TSQR_CHECK(launch_potrf(ni, W, n, R2, n, 3, info, fac, st));
+    TSQR_CHECK(launch_trsm(m, ni, Q, ldq, R2, n, Q, ldq, st));
+  }
+  if (R) {
+    if (extra_pass) {
+      TSQR_CHECK(launch_trmm_upper(ni, R1, n, R0, n, R10, n, st));
+      TSQR_CHECK(launch_trmm_upper(ni, R2, n, R10, n, R, ldr, st));
+    } else {
+      TSQR_CHECK(launch_trmm_upper(ni, R1, n, R0, n, R, ldr, st));
+    }
+  }
+  TSQR_CHECK(launch_poison(info, m, ni, Q, ldq, R, ldr, st));
+  return TSQR_OK;
+}
+
+// Validation shared by the plain and workspace forms; returns 0 or the code of the first
+// invalid argument expressed in the plain form's numbering (caller remaps).
+enum ArgErr { E_OK = 0, E_M, E_N, E_A, E_LDA, E_S, E_Q, E_LDQ, E_R, E_LDR };
+
+ArgErr validate(int64_t m, int64_t n, const double* A, int64_t lda, int64_t s, const double* Q,
+                int64_t ldq, const double* R, int64_t ldr) {
+  if (n < 1) return E_N;
+  if (m < 1 || m < n) return E_M;
+  if (!A) return E_A;
+  if (lda < m) return E_LDA;
+  if (s < n || s > kMaxSketchRows) return E_S;
+  if (!Q) return E_Q;
+  if (ldq < m) return E_LDQ;
+  if (overlaps(A, span_bytes(m, n, lda), Q, span_bytes(m, n, ldq))) return E_Q;
+  if (R) {
+    if (ldr < n) return E_LDR;
+    if (overlaps(R, span_bytes(n, n, ldr), Q, span_bytes(m, n, ldq)) ||
+        overlaps(R, span_bytes(n, n, ldr), A, span_bytes(m, n, lda)))
+      return E_R;
+  }
+  return E_OK;
+}
+
+int plain_form(int variant, int64_t m, int64_t n, const double* A, int64_t lda, int64_t s,
+               uint64_t seed, double* Q, double* R, void* stream) {
+  const ArgErr e = validate(m, n, A, lda, s, Q, m, R, n);
+  switch (e) {
+    case E_OK: break;
+    case E_M: return -1;
+    case E_N: return -2;
+    case E_A: return -3;
+    case E_LDA: return -4;
+    case E_S: return -5;
+    case E_Q: case E_LDQ: return -7;
+    case E_R: case E_LDR: return -8;
+  }
+  if (n > kMaxN) return TSQR_ERR_UNSUPPORTED;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t bytes = make_layout(m, n, s).total;
+  void* work = nullptr;
+  if (hipMallocAsync(&work, bytes, st) != hipSuccess) return TSQR_ERR_HIP;
+  const int rc = run_chain(variant, m, n, A, lda, s, seed, 1, Q, m, R, n, work, nullptr, st);
+  if (hipFreeAsync(work, st) != hipSuccess && rc == TSQR_OK) return TSQR_ERR_HIP;
+  return rc;
+}
+
+}  // namespace
+}  // namespace tsqr
+
+using namespace tsqr;
+
+extern "C" {
+
+const char* tsqr_version(void) { return "libtsqr 0.1 (gfx950, FP64 MFMA)"; }
+
+int tsqr_rqr_cholqr(int64_t m, int64_t n, const double* A, int64_t lda, int64_t sketch_rows,
+                    uint64_t seed, double* Q, double* R, void* stream) {
+  return plain_form(TSQR_VARIANT_RQR, m, n, A, lda, sketch_rows, seed, Q, R, stream);
+}
+
+int tsqr_rlu_cholqr(int64_t m, int64_t n, const double* A, int64_t lda, int64_t sketch_rows,
+                    uint64_t seed, double* Q, double* R, void* stream) {
+  return plain_form(TSQR_VARIANT_RLU, m, n, A, lda, sketch_rows, seed, Q, R, stream);
+}
+
+size_t tsqr_workspace_bytes(int64_t m, int64_t n, int64_t sketch_rows) {
+  if (n < 1 || m < n || sketch_rows < n || sketch_rows > kMaxSketchRows) return 0;
+  return make_layout(m, n, sketch_rows).total;
+}
+
+int tsqr_rxr_cholqr_ws(int variant, int64_t m, int64_t n, const double* A, int64_t lda,
+                       int64_t sketch_rows, uint64_t seed, int extra_pass, double* Q,
+                       int64_t ldq, double* R, int64_t ldr, void* work, size_t work_bytes,
+                       int* d_info, void* stream) {
+  if (variant != TSQR_VARIANT_RQR && variant != TSQR_VARIANT_RLU) return -1;
+  const ArgErr e = validate(m, n, A, lda, sketch_rows, Q, ldq, R, ldr);
+  switch (e) {
+    case E_OK: break;
+    case E_M: return -2;
+    case E_N: return -3;
+    case E_A: return -4;
+    case E_LDA: return -5;
+    case E_S: return -6;
+    case E_Q: return -9;
+    case E_LDQ: return -10;
+    case E_R: return -11;
+    case E_LDR: return -12;
+  }
+  if (!work) return -13;
+  if (n > kMaxN) return TSQR_ERR_UNSUPPORTED;
+  if (work_bytes < make_layout(m, n, sketch_rows).total) return TSQR_ERR_WORKSPACE;
+  return run_chain(variant, m, n, A, lda, sketch_rows, seed, extra_pass, Q, ldq, R, ldr, work,
+                   d_info, (hipStream_t)stream);
+}
+
+size_t tsqr_sketch_workspace_bytes(int64_t m, int64_t n, int64_t s) {
+  if (m < 1 || n < 1 || s < 1) return 0;
+  return plan_sketch(m, (int)n, (int)s).part_doubles * sizeof(double);
+}
+
+int tsqr_sketch(int64_t m, int64_t n, const double* A, int64_t lda, int64_t s, uint64_t seed,
+                double* B, int64_t ldb, void* work, size_t work_bytes, void* stream) {
+  if (m < 1) return -1;
+  if (n < 1) return -2;
+  if (!A) return -3;
+  if (lda < m) return -4;
+  if (s < 1 || s > kMaxSketchRows) return -5;
+  if (!B) return -7;
+  if (ldb < s) return -8;
+  if (!work) return -9;
+  const SketchPlan p = plan_sketch(m, (int)n, (int)s);
+  if (work_bytes < p.part_doubles * sizeof(double)) return TSQR_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  if (launch_sketch(p, m, (int)n, A, lda, (int)s, seed, (double*)work, st) != hipSuccess)
+    return TSQR_ERR_HIP;
+  if (launch_sketch_reduce(p, (int)s, (int)n, (double*)work, 1.0 / sqrt((double)s), B, ldb, st) !=
+      hipSuccess)
+    return TSQR_ERR_HIP;
+  return TSQR_OK;
+}
+
+int tsqr_sketch_factor(int variant, int64_t s, int64_t n, const double* B, int64_t ldb,
+                       double* R0, int64_t ldr, int* d_info, void* work, size_t work_bytes,
+                       void* stream) {
+  if (variant != TSQR_VARIANT_RQR && variant != TSQR_VARIANT_RLU) return -1;
+  if (s < n || s > kMaxSketchRows) return -2;
+  if (n < 1) return -3;
+  if (!B) return -4;
+  if (ldb < s) return -5;
+  if (!R0) return -6;
+  if (ldr < n) return -7;
+  if (!work || work_bytes < (size_t)s * n * sizeof(double)) return TSQR_ERR_WORKSPACE;
+  if (launch_sketch_factor(variant, (int)s, (int)n, B, ldb, R0, ldr, d_info, (double*)work,
+                           (hipStream_t)stream) != hipSuccess)
+    return TSQR_ERR_HIP;
+  return TSQR_OK;
+}
+
+int tsqr_trsm(int64_t m, int64_t n, const double* Y, int64_t ldy, const double* T, int64_t ldt,
+              double* X, int64_t ldx, void* stream) {
+  if (m < 0) return -1;
+  if (n < 1) return -2;
+  if (!Y) return -3;
+  if (ldy < m || ldy < 1) return -4;
+  if (!T) return -5;
+  if (ldt < n) return -6;
+  if (!X) return -7;
+  if (ldx < m || ldx < 1) return -8;
+  if (X != Y && overlaps(X, span_bytes(m > 0 ? m : 1, n, ldx), Y, span_bytes(m > 0 ? m : 1, n, ldy)))
+    return -7;
+  if (X == Y && ldx != ldy) return -8;
+  if (n > kMaxN) return TSQR_ERR_UNSUPPORTED;
+  if (launch_trsm(m, (int)n, Y, ldy, T, ldt, X, ldx, (hipStream_t)stream) != hipSuccess)
+    return TSQR_ERR_HIP;
+  return TSQR_OK;
+}
+
+size_t tsqr_gram_workspace_bytes(int64_t m, int64_t n) {
+  if (m < 1 || n < 1) return 0;
+  return plan_gram(m, (int)n).part_doubles * sizeof(double);
+}
+
+int tsqr_gram(int64_t m, int64_t n, const double* X, int64_t ldx, double* W, int64_t ldw,
+              void* work, size_t work_bytes, void* stream) {
+  if (m < 1) return -1;
+  if (n < 1) return -2;
+  if (!X) return -3;
+  if (ldx < m) return -4;
+  if (!W) return -5;
+  if (ldw < n) return -6;
+  if (!work) return -7;
+  if (n > kMaxN) return TSQR_ERR_UNSUPPORTED;
+  const GramPlan p = plan_gram(m, (int)n);
+  if (work_bytes < p.part_doubles * sizeof(double)) return TSQR_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  if (launch_gram(p, m, (int)n, X, ldx, (double*)work, st) != hipSuccess) return TSQR_ERR_HIP;
+  if (launch_gram_reduce(p, (int)n, (double*)work, W, ldw, st) != hipSuccess) return TSQR_ERR_HIP;
+  return TSQR_OK;
+}
+
+int tsqr_potrf(int64_t n, const double* W, int64_t ldw, double* R, int64_t ldr, int stage,
+               int* d_info, void* work, size_t work_bytes, void* stream) {
+  if (n < 1 || n > kMaxSketchRows) return -1;
+  if (!W) return -2;
+  if (ldw < n) return -3;
+  if (!R) return -4;
+  if (ldr < n) return -5;
+  if (stage < 1 || stage > 9) return -6;
+  if (!work || work_bytes < (size_t)n * n * sizeof(double)) return TSQR_ERR_WORKSPACE;
+  if (launch_potrf((int)n, W, ldw, R, ldr, stage, d_info, (double*)work, (hipStream_t)stream) !=
+      hipSuccess)
+    return TSQR_ERR_HIP;
+  return TSQR_OK;
+}
+
+int tsqr_trmm_upper(int64_t n, const double* A, int64_t lda, const double* B, int64_t ldb,
+                    double* C, int64_t ldc, void* stream) {
+  if (n < 1) return -1;
+  if (!A) return -2;
+  if (lda < n) return -3;
+  if (!B) return -4;
+  if (ldb < n) return -5;
+  if (!C) return -6;
+  if (ldc < n) return -7;
+  if (overlaps(C, span_bytes(n, n, ldc), A, span_bytes(n, n, lda)) ||
+      overlaps(C, span_bytes(n, n, ldc), B, span_bytes(n, n, ldb)))
+    return -6;
+  if (launch_trmm_upper((int)n, A, lda, B, ldb, C, ldc, (hipStream_t)stream) != hipSuccess)
+    return TSQR_ERR_HIP;
+  return TSQR_OK;
+}
+
+int tsqr_philox4x32_10(int64_t count, const uint32_t* d_ctr, uint64_t seed, uint32_t* d_out,
+                       void* stream) {
+  if (count < 0) return -1;
+  if (count > 0 && !d_ctr) return -2;
+  if (count > 0 && !d_out) return -4;
+  if (launch_philox_words(count, d_ctr, seed, d_out, (hipStream_t)stream) != hipSuccess)
+    return TSQR_ERR_HIP;
+  return TSQR_OK;
+}
+
+int tsqr_sketch_normals(uint64_t seed, int64_t i0, int64_t ni, int64_t j0, int64_t nj,
+                        double* Zout, int64_t ldz, void* stream) {
+  if (i0 < 0 || i0 + ni > 0xffffffffLL) return -2;
+  if (ni < 0) return -3;
+  if (j0 < 0) return -4;
+  if (nj < 0) return -5;
+  if (ni * nj > 0 && !Zout) return -6;
+  if (ldz < ni || ldz < 1) return -7;
+  if (launch_sketch_normals(seed, i0, ni, j0, nj, Zout, ldz, (hipStream_t)stream) != hipSuccess)
+    return TSQR_ERR_HIP;
+  return TSQR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// Device-side building blocks shared by the HIP kernels of libtsqr (gfx950 / CDNA4).
+//
+//  * Philox4x32-10 counter-based generator and the Box-Muller map that define the
+//    Gaussian sketch S (stream layout documented in include/tsqr.h);
+//  * the FP64 MFMA 16x16x4 wrapper and its operand layouts;
+//  * wavefront (64-lane) reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tsqr {
+
+constexpr int kWave = 64;
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
+//   (c0,c1,c2,c3) -> (hi(M1*c2)^c1^k0, lo(M1*c2), hi(M0*c0)^c3^k1, lo(M0*c0)),
+// key bumped by the Weyl constants between rounds.
+// ---------------------------------------------------------------------------------
+struct U32x4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U32x4 philox4x32_10(U32x4 c, uint32_t k0, uint32_t k1) {
+  constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    if (round) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint32_t hi0 = __umulhi(M0, c.x), lo0 = M0 * c.x;
+    const uint32_t hi1 = __umulhi(M1, c.z), lo1 = M1 * c.z;
+    c = U32x4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+  }
+  return c;
+}
+
+// Box-Muller on 24-bit uniforms, evaluated in single precision with the hardware
+// transcendentals: u = ((wa>>8)+1) 2^-24 in (0,1], t = (wb>>8) 2^-24 in [0,1) are exact in
+// FP32; v_log_f32 is log2, v_sin_f32 / v_cos_f32 take their argument in turns
+// (sin(2 pi t)).  Returns (rad cos 2 pi t, rad sin 2 pi t).
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& z0, float& z1) {
+  const float u = (float)((wa >> 8) + 1u) * 0x1p-24f;
+  const float t = (float)(wb >> 8) * 0x1p-24f;
+  // -2 ln u = -2 ln(2) log2(u)
+  const float rad = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u));
+  z0 = rad * __builtin_amdgcn_cosf(t);
+  z1 = rad * __builtin_amdgcn_sinf(t);
+}
+
+// The four N(0,1) entries Z(i, 4p..4p+3) of the sketch (one Philox call).
+__device__ __forceinline__ void sketch_normals4(uint64_t p, uint32_t i, uint32_t k0, uint32_t k1,
+                                                float z[4]) {
+  const U32x4 w = philox4x32_10(U32x4{(uint32_t)p, (uint32_t)(p >> 32), i, 0u}, k0, k1);
+  box_muller(w.x, w.y, z[0], z[1]);
+  box_muller(w.z, w.w, z[2], z[3]);
+}
+
+// ---------------------------------------------------------------------------------
+// V_MFMA_F64_16X16X4_F64: D(16x16) = A(16x4) B(4x16) + C.  Lane l (0..63) supplies
+//   A[l%16][l/16] and B[l/16][l%16], and holds D[4*r + l/16][l%16] in register r = 0..3
+//   (measured on gfx950; note the row interleave of the accumulator).
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------------
+// Wavefront reductions (64 lanes, butterfly; every lane gets the result).
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+__device__ __forceinline__ int wave_id() { return (int)(threadIdx.x / kWave); }
+
+}  // namespace tsqr

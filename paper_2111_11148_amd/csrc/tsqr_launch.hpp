@@ -1,0 +1,71 @@
+// Host-side launchers of the libtsqr kernels (internal; the public interface is
+// include/tsqr.h).  Every launcher enqueues on `stream` and returns hipError_t.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace tsqr {
+
+// ---- tiled partial-sum geometry -----------------------------------------------------
+// Sketch partials: one (ceil(s/16) x ceil(n/16)) grid of 16x16 tiles per row block,
+// stored tile-natively (tile, lane, 4 registers) in FP64.
+struct SketchPlan {
+  int it_total, jt_total;  // 16-row tiles of B, 16-column tiles of B
+  int IT, JT, NW;          // i-tiles per wave, j-tiles per workgroup, waves per workgroup
+  int igroups, jgroups;    // workgroup grid in the i and j directions
+  int64_t rows_per_block;  // rows of A per workgroup (multiple of 32)
+  int kblocks;             // number of row blocks
+  size_t part_doubles;     // kblocks * it_total * jt_total * 256
+};
+SketchPlan plan_sketch(int64_t m, int n, int s);
+
+struct GramPlan {
+  int jt_total;  // 16-column tiles
+  int ntiles;    // upper-triangular tiles (jt_total*(jt_total+1)/2)
+  int64_t rows_per_block;
+  int kblocks;
+  size_t part_doubles;
+};
+GramPlan plan_gram(int64_t m, int n);
+
+// ---- launchers ----------------------------------------------------------------------
+hipError_t launch_sketch(const SketchPlan& p, int64_t m, int n, const double* A, int64_t lda,
+                         int s, uint64_t seed, double* part, hipStream_t st);
+// B(s x n, ld ldb) = scale * sum of the sketch partials
+hipError_t launch_sketch_reduce(const SketchPlan& p, int s, int n, const double* part,
+                                double scale, double* B, int64_t ldb, hipStream_t st);
+hipError_t launch_gram(const GramPlan& p, int64_t m, int n, const double* X, int64_t ldx,
+                       double* part, hipStream_t st);
+// W(n x n, ld ldw, both triangles) = sum of the Gram partials
+hipError_t launch_gram_reduce(const GramPlan& p, int n, const double* part, double* W,
+                              int64_t ldw, hipStream_t st);
+// X = Y T^{-1} (T upper n x n); X may alias Y
+hipError_t launch_trsm(int64_t m, int n, const double* Y, int64_t ldy, const double* T,
+                       int64_t ldt, double* X, int64_t ldx, hipStream_t st);
+// R0 from the s x n sketch: Householder (variant 0) or partial-pivot LU (variant 1);
+// `scratch` holds s*n doubles for the large-size fallback.
+hipError_t launch_sketch_factor(int variant, int s, int n, const double* B, int64_t ldb,
+                                double* R, int64_t ldr, int* info, double* scratch,
+                                hipStream_t st);
+// Cholesky of the symmetric W (both triangles stored) into upper R; info stage
+hipError_t launch_potrf(int n, const double* W, int64_t ldw, double* R, int64_t ldr, int stage,
+                        int* info, double* scratch, hipStream_t st);
+// C = A B for upper-triangular n x n matrices
+hipError_t launch_trmm_upper(int n, const double* A, int64_t lda, const double* B, int64_t ldb,
+                             double* C, int64_t ldc, hipStream_t st);
+// If *info != 0, fill Q (m x n) and R (n x n, optional) with NaN
+hipError_t launch_poison(const int* info, int64_t m, int n, double* Q, int64_t ldq, double* R,
+                         int64_t ldr, hipStream_t st);
+hipError_t launch_set_int(int* p, int v, hipStream_t st);
+
+// ---- test / debug kernels -------------------------------------------------------------
+hipError_t launch_philox_words(int64_t count, const uint32_t* ctr, uint64_t seed, uint32_t* out,
+                               hipStream_t st);
+hipError_t launch_sketch_normals(uint64_t seed, int64_t i0, int64_t ni, int64_t j0, int64_t nj,
+                                 double* Z, int64_t ldz, hipStream_t st);
+
+int device_cu_count();
+
+}  // namespace tsqr

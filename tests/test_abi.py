@@ -1,0 +1,90 @@
+"""The C ABI library loads, exports every function include/tsqr.h declares, and rejects
+invalid arguments synchronously with the documented LAPACK-style codes (host logic only:
+no kernel is launched by any call here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tsqr.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tsqr_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2111_11148_amd as tsqr
+
+    return tsqr.load()
+
+
+def test_header_declares_the_method_entry_points():
+    names = declared_functions()
+    for required in ("tsqr_rqr_cholqr", "tsqr_rlu_cholqr", "tsqr_rxr_cholqr_ws",
+                     "tsqr_workspace_bytes", "tsqr_sketch", "tsqr_sketch_factor", "tsqr_trsm",
+                     "tsqr_gram", "tsqr_potrf", "tsqr_trmm_upper"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert b"gfx950" in lib.tsqr_version()
+
+
+def test_plain_form_argument_codes(lib):
+    f = lib.tsqr_rqr_cholqr
+    A = ctypes.c_void_p(0x10000000)
+    Q = ctypes.c_void_p(0x20000000)
+    R = ctypes.c_void_p(0x30000000)
+    assert f(0, 1, A, 1, 1, 0, Q, R, None) == -1          # m < 1
+    assert f(4, 8, A, 4, 8, 0, Q, R, None) == -1          # m < n
+    assert f(8, 0, A, 8, 1, 0, Q, R, None) == -2          # n < 1
+    assert f(8, 4, None, 8, 8, 0, Q, R, None) == -3       # A NULL
+    assert f(8, 4, A, 7, 8, 0, Q, R, None) == -4          # lda < m
+    assert f(8, 4, A, 8, 3, 0, Q, R, None) == -5          # s < n (the paper needs l >= n)
+    assert f(8, 4, A, 8, 9000, 0, Q, R, None) == -5       # s above the supported maximum
+    assert f(8, 4, A, 8, 8, 0, None, R, None) == -7       # Q NULL
+    assert f(8, 4, A, 8, 8, 0, ctypes.c_void_p(0x10000008), R, None) == -7  # Q overlaps A
+    assert f(8, 4, A, 8, 8, 0, Q, ctypes.c_void_p(0x20000010), None) == -8  # R overlaps Q
+    assert lib.tsqr_rlu_cholqr(8, 4, A, 7, 8, 0, Q, R, None) == -4
+
+
+def test_workspace_form_argument_codes(lib):
+    f = lib.tsqr_rxr_cholqr_ws
+    A, Q, R, W = (ctypes.c_void_p(x) for x in (0x10000000, 0x20000000, 0x30000000, 0x40000000))
+    ok = dict(variant=0, m=64, n=8, A=A, lda=64, s=16, seed=1, extra=1, Q=Q, ldq=64, R=R, ldr=8,
+              work=W, wb=1, info=None, st=None)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return f(a["variant"], a["m"], a["n"], a["A"], a["lda"], a["s"], a["seed"], a["extra"],
+                 a["Q"], a["ldq"], a["R"], a["ldr"], a["work"], a["wb"], a["info"], a["st"])
+
+    assert call(variant=2) == -1
+    assert call(m=0) == -2
+    assert call(n=0) == -3
+    assert call(A=None) == -4
+    assert call(lda=10) == -5
+    assert call(s=7) == -6
+    assert call(Q=None) == -9
+    assert call(ldq=10) == -10
+    assert call(ldr=7) == -12
+    assert call(work=None) == -13
+    assert call() == -101  # TSQR_ERR_WORKSPACE: 1 byte is too small
+    assert call(m=1000, lda=1000, ldq=1000, n=300, s=600, ldr=300) == -102  # too wide
+
+
+def test_workspace_bytes_monotone(lib):
+    lib.tsqr_workspace_bytes.restype = ctypes.c_size_t
+    assert lib.tsqr_workspace_bytes(100, 0, 1) == 0
+    assert lib.tsqr_workspace_bytes(10, 20, 20) == 0
+    small = lib.tsqr_workspace_bytes(4096, 32, 64)
+    big = lib.tsqr_workspace_bytes(1 << 20, 128, 256)
+    assert 0 < small < big

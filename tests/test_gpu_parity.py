@@ -1,0 +1,288 @@
+"""GPU parity: every step of the HIP path against the FP64 CPU oracle, through the C ABI.
+
+Inputs come from the seeded generator (inputs/) only; expected values come from the
+oracle only.  Tolerances are derived from the arithmetic of each step (see the
+docstrings) and are written into each test.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2111_11148_amd as tsqr
+from inputs import gen_matrix
+from gpu_helpers import gpu_orthogonality, gpu_residual, host, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+EPS = 2.0 ** -52
+
+# Absolute error bound of one device normal: the device evaluates Box-Muller in FP32 with
+# the hardware log2 / sqrt / sin / cos (each within a few FP32 ulps), so an entry of
+# magnitude up to 6 carries at most ~16 ulp(FP32) of 6 = 6e-6; the bound adds margin.
+NORMAL_ABS_TOL = 2e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu(gpu_available):
+    tsqr.load()
+    torch.cuda.synchronize()
+    yield
+
+
+def dev(A, ld=None):
+    return tsqr.to_device_colmajor(A, ld=ld)
+
+
+# ------------------------------------------------------------------------ generator --
+def test_philox_words_bit_exact():
+    rng = np.random.default_rng(0)
+    ctr = rng.integers(0, 2**32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:4] = [[0, 0, 0, 0], [1, 0, 0, 0], [0xFFFFFFFF] * 4, [5, 6, 7, 8]]
+    for seed in (0, 11102, 0xDEADBEEF12345678):
+        got = tsqr.philox4x32_10(torch.from_numpy(ctr.view(np.int32)).cuda(), seed)
+        got = got.cpu().numpy().view(np.uint32)
+        key = [seed & 0xFFFFFFFF, seed >> 32]
+        exp = np.array([oracle.philox4x32_10(c, key) for c in ctr])
+        assert np.array_equal(got, exp)
+
+
+@pytest.mark.parametrize("i0,ni,j0,nj", [(0, 64, 0, 4096), (13, 7, 2**20 - 5, 37),
+                                         (0, 3, 2**33, 8)])
+def test_sketch_normals_match_oracle(i0, ni, j0, nj):
+    seed = 11101
+    Zg = host(tsqr.sketch_normals(seed, i0, ni, j0, nj))
+    Zo = oracle.sketch_normals(seed, i0, ni, j0, nj)
+    err = np.abs(Zg - Zo)
+    print(f"max |z_gpu - z_oracle| = {err.max():.3e}")
+    assert np.all(err <= NORMAL_ABS_TOL)
+    # the FP32 entries are exact in FP64
+    assert np.array_equal(Zg, Zg.astype(np.float32).astype(np.float64))
+
+
+# ---------------------------------------------------------------------------- sketch --
+@pytest.mark.parametrize("m,n,s", [(4096, 32, 64), (1000, 5, 7), (1027, 17, 40), (3000, 128, 256),
+                                   (777, 1, 1), (2050, 100, 100), (513, 64, 129), (4100, 200, 400)])
+def test_sketch_parity(m, n, s):
+    """|B_gpu - B_or| <= rs * (NORMAL_ABS_TOL sum_j |A_jc| + 4 m u sum_j |z_ij A_jc|)."""
+    A = gen_matrix(m, n, 1e6, 300 + m)
+    seed = 7 + n
+    Bg = host(tsqr.sketch(dev(A), s, seed))
+    Bo = oracle.sketch_apply(A, s, seed)
+    Z = oracle.sketch_normals(seed, 0, s, 0, m)
+    rs = 1.0 / math.sqrt(s)
+    tol = rs * (NORMAL_ABS_TOL * np.abs(A).sum(axis=0)[None, :] + 4 * m * U * (np.abs(Z) @ np.abs(A)))
+    assert np.all(np.abs(Bg - Bo) <= tol)
+
+
+def test_sketch_leading_dimension_and_determinism():
+    m, n, s = 2000, 24, 48
+    A = gen_matrix(m, n, 1e3, 5)
+    B1 = host(tsqr.sketch(dev(A), s, 3))
+    B2 = host(tsqr.sketch(dev(A, ld=m + 37), s, 3))
+    assert np.array_equal(B1, B2)  # fixed-order reduction, same blocking
+
+
+# ---------------------------------------------------------------------- small factors --
+@pytest.mark.parametrize("variant", [tsqr.RQR, tsqr.RLU])
+@pytest.mark.parametrize("s,n,kappa", [(64, 32, 1e4), (256, 128, 1e8), (40, 40, 1e3), (9, 1, 1.0),
+                                       (300, 150, 1e5), (512, 256, 1e6), (130, 65, 1e2)])
+def test_sketch_factor_parity(variant, s, n, kappa):
+    """R0 is the unique (sign-normalised) R or U factor: ||dR0||/||R0|| <= c n u kappa(B)."""
+    B = gen_matrix(s, n, kappa, 17 + s)
+    R0g, info = tsqr.sketch_factor(dev(B), variant)
+    assert int(info.item()) == 0
+    R0g = host(R0g)
+    if variant == tsqr.RQR:
+        R0o, inf_o = oracle.householder_r(B)
+    else:
+        R0o, _, inf_o = oracle.lu_r(B)
+    assert inf_o == 0
+    assert np.all(np.tril(R0g, -1) == 0) and np.all(np.diag(R0g) > 0)
+    growth = 1.0 if variant == tsqr.RQR else 10.0
+    assert rel_fro(R0g, R0o) <= 50 * n * EPS * kappa * growth
+
+
+def test_sketch_factor_breakdown():
+    B = gen_matrix(64, 8, 10.0, 1)
+    B[:, 3] = 0.0
+    for variant in (tsqr.RQR, tsqr.RLU):
+        R0, info = tsqr.sketch_factor(dev(B), variant)
+        assert int(info.item()) == 1004
+        assert np.isnan(host(R0)[3, 3])
+
+
+# ---------------------------------------------------------------------------- TRSM ----
+@pytest.mark.parametrize("m,n", [(4096, 32), (1000, 5), (1027, 17), (5000, 128), (333, 1),
+                                 (2049, 100), (700, 256), (64, 64)])
+def test_trsm_parity(m, n):
+    """Row-wise backward error |Y - X T| <= c n u |X||T| (as for the oracle's own solve),
+    and X agrees with the oracle within c n u cond(T)."""
+    Y = gen_matrix(m, n, 1e2, m + n)
+    Tm = gen_matrix(3 * n + 8, n, 1e3, n)
+    T, _ = oracle.householder_r(Tm)
+    Xg = host(tsqr.trsm(dev(Y), dev(T)))
+    Xo = oracle.trsm_ru(Y, T)
+    back = np.abs(Y - Xg @ T)
+    assert np.all(back <= 8 * n * U * (np.abs(Xg) @ np.abs(T)) + 1e-300)
+    assert rel_fro(Xg, Xo) <= 10 * n * EPS * 1e3
+
+
+def test_trsm_in_place_and_ld():
+    m, n = 3000, 64
+    Y = gen_matrix(m, n, 10.0, 1)
+    T, _ = oracle.householder_r(gen_matrix(200, n, 10.0, 2))
+    Yd = dev(Y, ld=m + 5)
+    Xo = host(tsqr.trsm(dev(Y), dev(T)))
+    tsqr.trsm(Yd, dev(T), X=Yd)
+    assert np.array_equal(host(Yd), Xo)
+
+
+# ---------------------------------------------------------------------------- Gram ----
+@pytest.mark.parametrize("m,n", [(4096, 32), (1000, 5), (1027, 17), (6000, 128), (129, 1),
+                                 (2049, 100), (1500, 256), (64, 64)])
+def test_gram_parity(m, n):
+    """|W_gpu - X^T X| <= 2 m u |X|^T |X| (any summation order), symmetric."""
+    X = gen_matrix(m, n, 1e4, 9 + n)
+    Wg = host(tsqr.gram(dev(X)))
+    Wo = oracle.gram(X)
+    assert np.all(np.abs(Wg - Wo) <= 2 * m * U * (np.abs(X).T @ np.abs(X)))
+    assert np.array_equal(Wg, Wg.T)
+
+
+# ------------------------------------------------------------------------ Cholesky ----
+@pytest.mark.parametrize("n", [1, 5, 16, 32, 64, 100, 128, 129, 256])
+def test_potrf_parity(n):
+    """R^T R = W to c n u ||W||; R agrees with the oracle within c n u cond(W)."""
+    X = gen_matrix(4 * n + 10, n, 30.0, n)
+    W = np.asfortranarray(X.T @ X)
+    Rg, info = tsqr.potrf(dev(W), stage=2)
+    assert int(info.item()) == 0
+    Rg = host(Rg)
+    Ro, io = oracle.cholesky_upper(W)
+    assert io == 0
+    assert np.all(np.tril(Rg, -1) == 0)
+    assert np.linalg.norm(Rg.T @ Rg - W) <= 20 * n * EPS * np.linalg.norm(W)
+    assert rel_fro(Rg, Ro) <= 20 * n * EPS * 900.0
+
+
+def test_potrf_breakdown_and_upper_only():
+    W = np.eye(6)
+    W[3, 3] = -1.0
+    W[5, 0] = 77.0  # lower garbage is ignored
+    R, info = tsqr.potrf(dev(np.asfortranarray(W)), stage=3)
+    assert int(info.item()) == 3004
+    Rh = host(R)
+    assert np.all(np.isnan(Rh[3:, 3:][np.triu_indices(3)]))
+    assert np.array_equal(Rh[:3, :3], np.eye(3))
+
+
+def test_trmm_parity():
+    rng = np.random.default_rng(0)
+    for n in (1, 7, 32, 128, 200):
+        A = np.asfortranarray(np.triu(rng.standard_normal((n, n))))
+        B = np.asfortranarray(np.triu(rng.standard_normal((n, n))))
+        Cg = host(tsqr.trmm_upper(dev(A), dev(B)))
+        Co = oracle.trmm_upper(A, B)
+        assert np.all(np.abs(Cg - Co) <= 2 * n * U * (np.abs(A) @ np.abs(B)))
+
+
+# ---------------------------------------------------------------------- end to end ----
+def _check_qr(A, Qd, Rd, Q, R, info, ortho_tol=1e-12, res_tol=1e-13):
+    assert int(info) == 0
+    assert np.all(np.tril(R, -1) == 0) and np.all(np.diag(R) > 0)
+    ortho = oracle.orthogonality(Q)
+    res = oracle.residual(A, Q, R)
+    assert ortho <= ortho_tol, ortho
+    assert res <= res_tol, res
+    return ortho, res
+
+
+@pytest.mark.parametrize("variant", [tsqr.RQR, tsqr.RLU])
+@pytest.mark.parametrize("m,n,s,kappa", [(4096, 32, 64, 1e10), (4096, 32, 64, 1e14),
+                                         (1000, 7, 14, 1e8), (1027, 17, 33, 1e12),
+                                         (6000, 128, 256, 1e14), (2500, 100, 200, 1e6),
+                                         (64, 64, 128, 1e4), (300, 1, 2, 1.0),
+                                         (3000, 256, 512, 1e12), (800, 20, 20, 1e3)])
+def test_end_to_end_parity(variant, m, n, s, kappa):
+    """Q, R of the GPU path: orthogonality <= 1e-12 and residual <= 1e-13 (the targets),
+    R upper with positive diagonal, and R within c kappa u of the oracle's R (both are
+    backward-stable routes to the unique thin QR; perturbation theory bounds the gap)."""
+    A = gen_matrix(m, n, kappa, 211101 + m + n)
+    seed = 11101 + n
+    Ad = dev(A)
+    Qd, Rd, info = tsqr.rxr_cholqr(Ad, s, seed, variant=variant, extra_pass=True)
+    Q, R = host(Qd), host(Rd)
+    ortho, res = _check_qr(A, Qd, Rd, Q, R, int(info.item()))
+    ref = oracle.rxr_cholqr(A, s, seed, variant=variant, extra_pass=True)
+    assert ref["info"] == 0
+    rd = rel_fro(R, ref["R"])
+    print(f"variant={variant} m={m} n={n} s={s} kappa={kappa:g}: ortho={ortho:.2e} "
+          f"res={res:.2e} relR={rd:.2e}")
+    assert rd <= 100 * n * EPS * kappa + 1e-14
+    if kappa <= 1e4:  # well-conditioned: Q agrees elementwise too
+        assert np.max(np.abs(Q - ref["Q"])) <= 100 * n * EPS * kappa
+
+
+def test_end_to_end_plain_forms_and_rless():
+    m, n, s = 4096, 32, 64
+    A = gen_matrix(m, n, 1e10, 211101)
+    Ad = dev(A)
+    for fn in (tsqr.rqr_cholqr, tsqr.rlu_cholqr):
+        Qd, Rd = fn(Ad, s, 11101)
+        _check_qr(A, Qd, Rd, host(Qd), host(Rd), 0)
+    # R-less: Q identical to the full call
+    Qa, Ra, _ = tsqr.rxr_cholqr(Ad, s, 11101)
+    Qb, Rb, _ = tsqr.rxr_cholqr(Ad, s, 11101, want_r=False)
+    assert Rb is None and torch.equal(Qa, Qb)
+
+
+def test_end_to_end_no_extra_pass_and_ld():
+    m, n, s = 5000, 48, 96
+    A = gen_matrix(m, n, 1e9, 3)
+    Qd, Rd, info = tsqr.rxr_cholqr(dev(A, ld=m + 11), s, 5, extra_pass=False)
+    Q, R = host(Qd), host(Rd)
+    assert int(info.item()) == 0
+    ref = oracle.rxr_cholqr(A, s, 5, extra_pass=False)
+    # one CholeskyQR pass on the preconditioned matrix: orthogonality ~ u cond(A1)^2
+    assert oracle.orthogonality(Q) <= 1e-13
+    assert oracle.residual(A, Q, R) <= 1e-13
+    assert rel_fro(R, ref["R"]) <= 100 * n * EPS * 1e9
+
+
+def test_end_to_end_deterministic():
+    A = gen_matrix(20000, 64, 1e12, 8)
+    Ad = dev(A)
+    Q1, R1, _ = tsqr.rxr_cholqr(Ad, 128, 9)
+    Q2, R2, _ = tsqr.rxr_cholqr(Ad, 128, 9)
+    assert torch.equal(Q1, Q2) and torch.equal(R1, R2)
+
+
+def test_end_to_end_breakdown_poisons():
+    A = gen_matrix(2048, 16, 1e3, 4)
+    A[:, 7] = 0.0
+    Qd, Rd, info = tsqr.rxr_cholqr(dev(A), 32, 1)
+    assert int(info.item()) == 1008
+    assert torch.isnan(Qd).all() and torch.isnan(Rd).all()
+    A2 = gen_matrix(2048, 16, 1e3, 4)
+    A2[100, 3] = np.nan
+    Qd2, Rd2, info2 = tsqr.rxr_cholqr(dev(A2), 32, 1)
+    assert int(info2.item()) != 0
+    assert torch.isnan(Qd2).all() and torch.isnan(Rd2).all()
+
+
+def test_gpu_metrics_helper_matches_oracle():
+    """The blocked FP64 metric of gpu_helpers agrees with the oracle's double-double one
+    within its own rounding: a diagonal entry of a 4096-row block Gram carries about
+    sqrt(4096) u, so the Frobenius norm over n diagonal entries about 2 sqrt(n) 64 u."""
+    n = 40
+    A = gen_matrix(9000, n, 1e8, 2)
+    Qd, Rd, _ = tsqr.rxr_cholqr(dev(A), 2 * n, 2)
+    Q, R = host(Qd), host(Rd)
+    o1, o2 = gpu_orthogonality(Qd), oracle.orthogonality(Q)
+    r1, r2 = gpu_residual(dev(A), Qd, Rd), oracle.residual(A, Q, R)
+    assert abs(o1 - o2) <= 2 * math.sqrt(n) * 64 * U
+    assert abs(r1 - r2) <= 0.05 * r2 + 64 * U
