@@ -1,0 +1,261 @@
+#!/usr/bin/env python3
+"""Throughput of randomized XR-preconditioned CholeskyQR on one MI355X.
+
+One step = one whole factorization (sketch B = S A, R0 from the sketch, A1 = A R0^{-1},
+Gram, Cholesky, Q1 = A1 R1^{-1}, the extra CholeskyQR pass and R = R2 R1 R0) of the
+tall128 workload: m = 2^20, n = 128, s = 256, FP64, singular values log-spaced from 1 to
+1e-14, rQR variant.  Inputs are resident in HBM before timing starts; workspace and
+outputs are preallocated, so the timed region allocates nothing.
+
+Printed: one JSON line with the throughput (GFLOP/s of the algorithmic flop count), the
+roofline of the dominant kernel (average duration from HIP events recorded on the
+library's stream during the timed steps), and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (vector = matrix)
+PEAK_HBM_GBS = 8000.0
+METRIC = "tall-skinny QR GFLOP/s + roofline %, m=2^20 n=128; mixed vs FP64 at ortho≤1e-12"
+
+# Kernel sources whose counter readings profiles/traffic_*.json refer to.
+KERNEL_SOURCES = {
+    "sketch": ["paper_2111_11148_amd/csrc/k_sketch.hip", "paper_2111_11148_amd/csrc/tsqr_device.hpp"],
+    "trsm_r0": ["paper_2111_11148_amd/csrc/k_tall.hip", "paper_2111_11148_amd/csrc/tsqr_device.hpp"],
+    "gram1": ["paper_2111_11148_amd/csrc/k_tall.hip", "paper_2111_11148_amd/csrc/tsqr_device.hpp"],
+}
+
+
+def flops(m: int, n: int, s: int, variant: str, extra_pass: bool) -> dict:
+    """Algorithmic flop counts per phase (multiply-add = 2 flops)."""
+    f = {
+        "sketch": 2.0 * s * m * n,                     # B = S A
+        "sketch_factor": (2.0 * n * n * (s - n / 3.0)) if variant == "rqr"
+        else (1.0 * n * n * (s - n / 3.0)),            # Householder QR or LU of B
+        "trsm": 1.0 * m * n * n,                       # one X = Y T^{-1}
+        "gram": 1.0 * m * n * (n + 1),                 # upper triangle of X^T X
+        "potrf": n ** 3 / 3.0,
+        "trmm": n ** 3 / 3.0,
+    }
+    passes = 2 if extra_pass else 1
+    total = (f["sketch"] + f["sketch_factor"] + (1 + passes) * f["trsm"] + passes * f["gram"]
+             + passes * f["potrf"] + passes * f["trmm"])
+    f["total"] = total
+    return f
+
+
+def source_hash(paths) -> str:
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed counter summary, or None when absent or
+    taken on a different version of the kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_sha") != source_hash(KERNEL_SOURCES[kernel]):
+        return None
+    return t.get("bytes_per_launch")
+
+
+def gpu_metrics(A, Q, R):
+    """Orthogonality and residual with blocked FP64 products on the device."""
+    import torch
+
+    m, n = A.shape
+    G = None
+    num = den = None
+    Rc = R.contiguous()
+    for r0 in range(0, m, 4096):
+        q = Q[r0:r0 + 4096].contiguous()
+        g = q.t().contiguous() @ q
+        G = g if G is None else G + g
+        a = A[r0:r0 + 4096]
+        e = a - q @ Rc
+        num = (e * e).sum() if num is None else num + (e * e).sum()
+        den = (a * a).sum() if den is None else den + (a * a).sum()
+    G -= torch.eye(n, dtype=G.dtype, device=G.device)
+    return float(torch.linalg.matrix_norm(G)), float(torch.sqrt(num) / torch.sqrt(den))
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--variant", choices=["rqr", "rlu"], default="rqr")
+    ap.add_argument("--cpu-sample-rows", type=int, default=1 << 20,
+                    help="rows of the workload the CPU oracle is timed on (default: all)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cache-dir", default=None,
+                    help="directory to keep the generated input matrix between runs")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a device-to-device copy of BYTES bytes (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; multi-GPU runs are not part of it "
+              "(use --gpus 1)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2111_11148_amd as tsqr
+    from inputs import WORKLOADS, gen_matrix
+
+    if args.copy_calibration:
+        nel = args.copy_calibration // 8
+        x = torch.ones(nel, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nel * 8}))
+        return 0
+
+    wl = WORKLOADS["tall128"]
+    m, n, s, kappa = wl.m, wl.n, wl.s, wl.kappas[0]
+    seed = wl.sketch_seed
+    variant = tsqr.RQR if args.variant == "rqr" else tsqr.RLU
+    extra_pass = wl.extra_pass
+
+    A_h = None
+    cache = None
+    if args.cache_dir:
+        os.makedirs(args.cache_dir, exist_ok=True)
+        cache = os.path.join(args.cache_dir, f"A_{wl.name}_{wl.gen_seeds[0]}.npy")
+        if os.path.exists(cache):
+            A_h = np.load(cache, mmap_mode="r")
+    if A_h is None:
+        t0 = time.perf_counter()
+        A_h = gen_matrix(m, n, kappa, wl.gen_seeds[0])
+        print(f"# generated A ({m}x{n}, kappa={kappa:g}) in {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+        if cache:
+            np.save(cache, np.asfortranarray(A_h))
+    A = tsqr.to_device_colmajor(np.asarray(A_h))
+    Q = tsqr.colmajor(m, n)
+    R = tsqr.colmajor(n, n)
+    work = tsqr.alloc_workspace(m, n, s)
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def step():
+        tsqr.rxr_cholqr(A, s, seed, variant=variant, extra_pass=extra_pass, Q=Q, R=R,
+                        workspace=work, info=info)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    tsqr.profile_start()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    recs = tsqr.profile_stop()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    print(f"# timed {args.steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
+
+    binfo = int(info.item())
+    ortho, res = gpu_metrics(A, Q, R)
+
+    # per-phase average durations (ms per launch) from the events of the timed steps
+    phase_tot, phase_cnt = {}, {}
+    for name, ms in recs:
+        phase_tot[name] = phase_tot.get(name, 0.0) + ms
+        phase_cnt[name] = phase_cnt.get(name, 0) + 1
+    phases = {k: phase_tot[k] / phase_cnt[k] for k in phase_tot}
+    per_step = {k: phase_tot[k] / args.steps for k in phase_tot}
+
+    F = flops(m, n, s, args.variant, extra_pass)
+    value = F["total"] / (ms_per_step * 1e-3) / 1e9
+
+    # dominant kernel: largest share of the step
+    dom = max(per_step, key=per_step.get)
+    dom_flops = {"sketch": F["sketch"], "trsm_r0": F["trsm"], "trsm_r1": F["trsm"],
+                 "trsm_r2": F["trsm"], "gram1": F["gram"], "gram2": F["gram"]}.get(dom)
+    roof = None
+    if dom_flops is not None:
+        achieved = dom_flops / (phases[dom] * 1e-3) / 1e12
+        traffic = load_traffic(dom, wl.name) if dom in KERNEL_SOURCES else None
+        roof = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3),
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
+                "avg_ms": round(phases[dom], 4)}
+
+    # step roofline: phases separated by global dependences add up; each phase is bound
+    # by max(flops / FP64 peak, algorithmic bytes / HBM bandwidth), with the algorithmic
+    # bytes of the method = one read of A per phase plus the final write of Q.
+    T = 8.0 * m * n
+    P, BW = PEAK_FP64_TFLOPS * 1e12, PEAK_HBM_GBS * 1e9
+    phase_fb = [(F["sketch"], T), (F["trsm"] + F["gram"], T)]
+    if extra_pass:
+        phase_fb += [(F["trsm"] + F["gram"], T), (F["trsm"], 2 * T)]
+    else:
+        phase_fb += [(F["trsm"], 2 * T)]
+    t_roof = sum(max(fl / P, by / BW) for fl, by in phase_fb)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        ms_ = min(args.cpu_sample_rows, m)
+        As = np.asfortranarray(np.asarray(A_h)[:ms_])
+        t0 = time.perf_counter()
+        r = oracle.rxr_cholqr(As, s, seed, variant=variant, extra_pass=extra_pass)
+        dt = time.perf_counter() - t0
+        Fs = flops(ms_, n, s, args.variant, extra_pass)["total"]
+        cpu = {"value": round(Fs / dt / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"first {ms_} rows of the same matrix (n={n}, s={s}), one full "
+                         f"factorization, {dt:.2f} s, info={r['info']}"}
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}-{args.variant}-fp64", "m": m, "n": n, "s": s,
+                   "kappa": kappa, "variant": args.variant, "extra_pass": extra_pass,
+                   "flops_per_step": F["total"]},
+        "roofline": roof,
+        "step_roofline_frac": round(t_roof * 1e3 / ms_per_step, 4),
+        "cpu_baseline": cpu,
+        "ortho": ortho,
+        "residual": res,
+        "info": binfo,
+        "phases_ms": {k: round(v, 4) for k, v in per_step.items()},
+    }
+    print(json.dumps(line), flush=True)
+    return 0 if binfo == 0 else 1
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -161,6 +161,22 @@ int tsqr_philox4x32_10(int64_t count, const uint32_t* d_ctr, uint64_t seed, uint
 int tsqr_sketch_normals(uint64_t seed, int64_t i0, int64_t ni, int64_t j0, int64_t nj,
                         double* Zout, int64_t ldz, void* stream);
 
+/* ------------------------------------------------------------------------------------
+ * Phase timing (tracing)
+ * ------------------------------------------------------------------------------------ */
+
+/* While enabled, the whole-factorization entry points record a pair of HIP events on
+ * their stream around every kernel they launch (named "sketch", "sketch_reduce",
+ * "sketch_qr" or "sketch_lu", "trsm_r0", "gram1", "gram1_reduce", "potrf1", "trsm_r1",
+ * "gram2", "gram2_reduce", "potrf2", "trsm_r2", "trmm", "poison").  tsqr_profile_start()
+ * clears the records and enables recording; tsqr_profile_stop() disables it, waits for
+ * the recorded events and returns the number of records (or TSQR_ERR_HIP);
+ * tsqr_profile_record(i) returns the i-th record's name (static storage) and duration in
+ * milliseconds (-1 if i is out of range).  Process-wide; not meant for concurrent use. */
+int tsqr_profile_start(void);
+int tsqr_profile_stop(void);
+int tsqr_profile_record(int i, const char** name, double* ms);
+
 /* Library identification string (static storage). */
 const char* tsqr_version(void);
 

@@ -46,6 +46,10 @@ _SIGS = {
     "tsqr_philox4x32_10": (_int, [_i64, _vp, _u64, _vp, _vp]),
     "tsqr_sketch_normals": (_int, [_u64, _i64, _i64, _i64, _i64, _vp, _i64, _vp]),
     "tsqr_version": (ctypes.c_char_p, []),
+    "tsqr_profile_start": (_int, []),
+    "tsqr_profile_stop": (_int, []),
+    "tsqr_profile_record": (_int, [_int, ctypes.POINTER(ctypes.c_char_p),
+                                   ctypes.POINTER(ctypes.c_double)]),
 }
 
 
@@ -120,6 +124,27 @@ def to_device_colmajor(A, ld: int | None = None, device="cuda") -> torch.Tensor:
     m, n = At.shape
     out = colmajor(m, n, ld, device=device)
     out.copy_(At)
+    return out
+
+
+# ------------------------------------------------------------------ phase timing ----
+def profile_start() -> None:
+    _check(load().tsqr_profile_start(), "tsqr_profile_start")
+
+
+def profile_stop():
+    """Stop recording; return [(phase name, milliseconds), ...] in launch order."""
+    lib = load()
+    count = lib.tsqr_profile_stop()
+    if count < 0:
+        raise TsqrError(f"tsqr_profile_stop failed with status {count}")
+    out = []
+    name = ctypes.c_char_p()
+    ms = ctypes.c_double()
+    for i in range(count):
+        _check(lib.tsqr_profile_record(i, ctypes.byref(name), ctypes.byref(ms)),
+               "tsqr_profile_record")
+        out.append((name.value.decode(), ms.value))
     return out
 
 

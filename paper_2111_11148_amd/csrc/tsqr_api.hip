@@ -4,6 +4,8 @@
 #include <string.h>
 
 #include <mutex>
+#include <utility>
+#include <vector>
 
 #include "../../include/tsqr.h"
 #include "tsqr_launch.hpp"
@@ -75,6 +77,52 @@ inline size_t span_bytes(int64_t rows, int64_t cols, int64_t ld) {
     if ((expr) != hipSuccess) return TSQR_ERR_HIP; \
   } while (0)
 
+// ---- phase timing: HIP events recorded on the caller's stream around each launch ----
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_live;
+std::vector<std::pair<const char*, double>> g_prof_done;
+std::vector<hipEvent_t> g_prof_pool;
+
+bool prof_on() {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  return g_prof_on;
+}
+
+hipEvent_t prof_event() {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  hipEvent_t e = nullptr;
+  if (!g_prof_pool.empty()) {
+    e = g_prof_pool.back();
+    g_prof_pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    e = nullptr;
+  }
+  return e;
+}
+
+void prof_push(const char* name, hipEvent_t a, hipEvent_t b) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof_live.push_back(ProfRec{name, a, b});
+}
+
+#define TSQR_PHASE(name, expr)                                               \
+  do {                                                                       \
+    hipEvent_t ev_a_ = nullptr, ev_b_ = nullptr;                             \
+    const bool on_ = prof_on();                                              \
+    if (on_ && (ev_a_ = prof_event())) (void)hipEventRecord(ev_a_, st);      \
+    const hipError_t err_ = (expr);                                          \
+    if (on_ && ev_a_ && (ev_b_ = prof_event())) {                            \
+      (void)hipEventRecord(ev_b_, st);                                       \
+      prof_push(name, ev_a_, ev_b_);                                         \
+    }                                                                        \
+    if (err_ != hipSuccess) return TSQR_ERR_HIP;                             \
+  } while (0)
+
 int run_chain(int variant, int64_t m, int64_t n, const double* A, int64_t lda, int64_t s,
               uint64_t seed, int extra_pass, double* Q, int64_t ldq, double* R, int64_t ldr,
               void* work, int* d_info, hipStream_t st) {
@@ -93,32 +141,34 @@ int run_chain(int variant, int64_t m, int64_t n, const double* A, int64_t lda, i
 
   TSQR_CHECK(launch_set_int(info, 0, st));
   // B = S A  (paper Section 2.3)
-  TSQR_CHECK(launch_sketch(L.sp, m, ni, A, lda, si, seed, part, st));
-  TSQR_CHECK(launch_sketch_reduce(L.sp, si, ni, part, 1.0 / sqrt((double)s), B, s, st));
+  TSQR_PHASE("sketch", launch_sketch(L.sp, m, ni, A, lda, si, seed, part, st));
+  TSQR_PHASE("sketch_reduce",
+             launch_sketch_reduce(L.sp, si, ni, part, 1.0 / sqrt((double)s), B, s, st));
   // R0 = R factor of B
-  TSQR_CHECK(launch_sketch_factor(variant, si, ni, B, s, R0, n, info, fac, st));
+  TSQR_PHASE(variant == 1 ? "sketch_lu" : "sketch_qr",
+             launch_sketch_factor(variant, si, ni, B, s, R0, n, info, fac, st));
   // A1 = A R0^{-1} (into Q), W1 = A1^T A1, R1 = chol(W1), Q1 = A1 R1^{-1}
-  TSQR_CHECK(launch_trsm(m, ni, A, lda, R0, n, Q, ldq, st));
-  TSQR_CHECK(launch_gram(L.gp, m, ni, Q, ldq, part, st));
-  TSQR_CHECK(launch_gram_reduce(L.gp, ni, part, W, n, st));
-  TSQR_CHECK(launch_potrf(ni, W, n, R1, n, 2, info, fac, st));
-  TSQR_CHECK(launch_trsm(m, ni, Q, ldq, R1, n, Q, ldq, st));
+  TSQR_PHASE("trsm_r0", launch_trsm(m, ni, A, lda, R0, n, Q, ldq, st));
+  TSQR_PHASE("gram1", launch_gram(L.gp, m, ni, Q, ldq, part, st));
+  TSQR_PHASE("gram1_reduce", launch_gram_reduce(L.gp, ni, part, W, n, st));
+  TSQR_PHASE("potrf1", launch_potrf(ni, W, n, R1, n, 2, info, fac, st));
+  TSQR_PHASE("trsm_r1", launch_trsm(m, ni, Q, ldq, R1, n, Q, ldq, st));
   if (extra_pass) {
     // W2 = Q1^T Q1, R2 = chol(W2), Q = Q1 R2^{-1}
-    TSQR_CHECK(launch_gram(L.gp, m, ni, Q, ldq, part, st));
-    TSQR_CHECK(launch_gram_reduce(L.gp, ni, part, W, n, st));
-    TSQR_CHECK(launch_potrf(ni, W, n, R2, n, 3, info, fac, st));
-    TSQR_CHECK(launch_trsm(m, ni, Q, ldq, R2, n, Q, ldq, st));
+    TSQR_PHASE("gram2", launch_gram(L.gp, m, ni, Q, ldq, part, st));
+    TSQR_PHASE("gram2_reduce", launch_gram_reduce(L.gp, ni, part, W, n, st));
+    TSQR_PHASE("potrf2", launch_potrf(ni, W, n, R2, n, 3, info, fac, st));
+    TSQR_PHASE("trsm_r2", launch_trsm(m, ni, Q, ldq, R2, n, Q, ldq, st));
   }
   if (R) {
     if (extra_pass) {
-      TSQR_CHECK(launch_trmm_upper(ni, R1, n, R0, n, R10, n, st));
-      TSQR_CHECK(launch_trmm_upper(ni, R2, n, R10, n, R, ldr, st));
+      TSQR_PHASE("trmm", launch_trmm_upper(ni, R1, n, R0, n, R10, n, st));
+      TSQR_PHASE("trmm", launch_trmm_upper(ni, R2, n, R10, n, R, ldr, st));
     } else {
-      TSQR_CHECK(launch_trmm_upper(ni, R1, n, R0, n, R, ldr, st));
+      TSQR_PHASE("trmm", launch_trmm_upper(ni, R1, n, R0, n, R, ldr, st));
     }
   }
-  TSQR_CHECK(launch_poison(info, m, ni, Q, ldq, R, ldr, st));
+  TSQR_PHASE("poison", launch_poison(info, m, ni, Q, ldq, R, ldr, st));
   return TSQR_OK;
 }
 
@@ -176,6 +226,43 @@ using namespace tsqr;
 extern "C" {
 
 const char* tsqr_version(void) { return "libtsqr 0.1 (gfx950, FP64 MFMA)"; }
+
+int tsqr_profile_start(void) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  for (auto& r : g_prof_live) {
+    g_prof_pool.push_back(r.a);
+    g_prof_pool.push_back(r.b);
+  }
+  g_prof_live.clear();
+  g_prof_done.clear();
+  g_prof_on = true;
+  return TSQR_OK;
+}
+
+int tsqr_profile_stop(void) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof_on = false;
+  g_prof_done.clear();
+  int rc = TSQR_OK;
+  for (auto& r : g_prof_live) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+      rc = TSQR_ERR_HIP;
+    g_prof_done.emplace_back(r.name, (double)ms);
+    g_prof_pool.push_back(r.a);
+    g_prof_pool.push_back(r.b);
+  }
+  g_prof_live.clear();
+  return rc == TSQR_OK ? (int)g_prof_done.size() : rc;
+}
+
+int tsqr_profile_record(int i, const char** name, double* ms) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  if (i < 0 || i >= (int)g_prof_done.size()) return -1;
+  if (name) *name = g_prof_done[i].first;
+  if (ms) *ms = g_prof_done[i].second;
+  return TSQR_OK;
+}
 
 int tsqr_rqr_cholqr(int64_t m, int64_t n, const double* A, int64_t lda, int64_t sketch_rows,
                     uint64_t seed, double* Q, double* R, void* stream) {
