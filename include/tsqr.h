@@ -121,12 +121,14 @@ int tsqr_sketch_factor(int variant, int64_t s, int64_t n, const double* B, int64
                        double* R0, int64_t ldr, int* d_info, void* work, size_t work_bytes,
                        void* stream);
 
-/* Right-side upper triangular solve X = Y T^{-1} by blocked substitution (paper
+/* Right-side upper triangular solve X = Y T^{-1} by row-wise substitution (paper
  * Algorithm CholeskyQR, step 3; row-wise backward stable, no explicit inverse).
  * Y, X: m x n (ldy, ldx >= m); X may be the same buffer as Y with ldx == ldy (in place);
- * T: n x n upper, only its upper triangle is read.  n <= 256. */
+ * T: n x n upper, only its upper triangle is read.  n <= 256.
+ * Workspace (args 9, 10): tsqr_trsm_workspace_bytes(n) bytes (a transposed copy of T). */
+size_t tsqr_trsm_workspace_bytes(int64_t n);
 int tsqr_trsm(int64_t m, int64_t n, const double* Y, int64_t ldy, const double* T, int64_t ldt,
-              double* X, int64_t ldx, void* stream);
+              double* X, int64_t ldx, void* work, size_t work_bytes, void* stream);
 
 /* Gram matrix W = X^T X (paper Algorithm CholeskyQR, step 1), both triangles written
  * (ldw >= n).  Split over row blocks, fixed-order reduction.  n <= 256.

@@ -38,7 +38,8 @@ _SIGS = {
     "tsqr_sketch_workspace_bytes": (_sz, [_i64, _i64, _i64]),
     "tsqr_sketch": (_int, [_i64, _i64, _vp, _i64, _i64, _u64, _vp, _i64, _vp, _sz, _vp]),
     "tsqr_sketch_factor": (_int, [_int, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _sz, _vp]),
-    "tsqr_trsm": (_int, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp]),
+    "tsqr_trsm_workspace_bytes": (_sz, [_i64]),
+    "tsqr_trsm": (_int, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp]),
     "tsqr_gram_workspace_bytes": (_sz, [_i64, _i64]),
     "tsqr_gram": (_int, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp]),
     "tsqr_potrf": (_int, [_i64, _vp, _i64, _vp, _i64, _int, _vp, _vp, _sz, _vp]),
@@ -241,8 +242,10 @@ def trsm(Y: torch.Tensor, T: torch.Tensor, X: torch.Tensor | None = None, stream
     if X is None:
         X = colmajor(m, n, device=Y.device)
     ldx = _mat(X, "X", m, n)
+    nbytes = int(load().tsqr_trsm_workspace_bytes(n))
+    work = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=Y.device)
     _check(load().tsqr_trsm(m, n, Y.data_ptr(), ldy, T.data_ptr(), ldt, X.data_ptr(), ldx,
-                            _stream(stream)), "tsqr_trsm")
+                            work.data_ptr(), nbytes, _stream(stream)), "tsqr_trsm")
     return X
 
 

@@ -113,19 +113,31 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_f64(
   }
 }
 
-// B(i, c) = scale * sum_kb part[kb][tile(i,c)][lane][reg], fixed order kb = 0, 1, ...
-__global__ void k_sketch_reduce(int kblocks, int it_total, int jt_total, int s, int n,
-                                const double* __restrict__ part, double scale,
-                                double* __restrict__ B, int64_t ldb) {
+// B(i, c) = scale * sum_kb part[kb][tile(i,c)][lane][reg].  A 256-thread block handles 16
+// consecutive partial entries; thread group g (16 of them) sums the row blocks kb = g,
+// g+16, ... in increasing order and the 16 group sums are added in group order, so the
+// result does not depend on timing (deterministic).
+__global__ __launch_bounds__(256) void k_sketch_reduce(int kblocks, int it_total, int jt_total,
+                                                       int s, int n,
+                                                       const double* __restrict__ part,
+                                                       double scale, double* __restrict__ B,
+                                                       int64_t ldb) {
+  __shared__ double red[16][17];
   const size_t E = (size_t)it_total * jt_total * 256;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < E;
-       e += (size_t)gridDim.x * blockDim.x) {
-    double acc = 0.0;
-    for (int kb = 0; kb < kblocks; ++kb) acc += part[(size_t)kb * E + e];
+  const int g = threadIdx.x / 16, o = threadIdx.x % 16;
+  const size_t e = (size_t)blockIdx.x * 16 + o;
+  double acc = 0.0;
+  if (e < E)
+    for (int kb = g; kb < kblocks; kb += 16) acc += part[(size_t)kb * E + e];
+  red[g][o] = acc;
+  __syncthreads();
+  if (g == 0 && e < E) {
+    double t = 0.0;
+    for (int k = 0; k < 16; ++k) t += red[k][o];
     const int tile = (int)(e / 256), lane = (int)((e / 4) % 64), r = (int)(e % 4);
     const int itg = tile / jt_total, jtg = tile % jt_total;
     const int i = 16 * itg + 4 * r + (lane >> 4), c = 16 * jtg + (lane & 15);
-    if (i < s && c < n) B[(int64_t)c * ldb + i] = scale * acc;
+    if (i < s && c < n) B[(int64_t)c * ldb + i] = scale * t;
   }
 }
 
@@ -209,8 +221,7 @@ hipError_t launch_sketch(const SketchPlan& p, int64_t m, int n, const double* A,
 hipError_t launch_sketch_reduce(const SketchPlan& p, int s, int n, const double* part,
                                 double scale, double* B, int64_t ldb, hipStream_t st) {
   const size_t E = (size_t)p.it_total * p.jt_total * 256;
-  int blocks = (int)((E + 255) / 256);
-  if (blocks > 4096) blocks = 4096;
+  const int blocks = (int)((E + 15) / 16);
   hipLaunchKernelGGL(k_sketch_reduce, dim3(blocks), dim3(256), 0, st, p.kblocks, p.it_total,
                      p.jt_total, s, n, part, scale, B, ldb);
   return hipGetLastError();

@@ -534,17 +534,29 @@ __global__ __launch_bounds__(kSmallThreads) void k_potrf_glb(int n, const double
 }
 
 // ============================================================ small products =========
-__global__ void k_trmm_upper(int n, const double* __restrict__ A, int64_t lda,
-                             const double* __restrict__ B, int64_t ldb, double* __restrict__ C,
-                             int64_t ldc) {
-  const int64_t total = (int64_t)n * n;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e % n), j = (int)(e / n);
-    double acc = 0.0;
-    for (int k = i; k <= j; ++k) acc += A[(int64_t)k * lda + i] * B[(int64_t)j * ldb + k];
-    C[(int64_t)j * ldc + i] = acc;
+// C = A B for upper-triangular A, B: one 16x16 output tile per workgroup, operands
+// staged through LDS in 16-wide chunks of the inner index (only k in [i0, j0+16)).
+__global__ __launch_bounds__(256) void k_trmm_upper(int n, const double* __restrict__ A,
+                                                    int64_t lda, const double* __restrict__ B,
+                                                    int64_t ldb, double* __restrict__ C,
+                                                    int64_t ldc) {
+  __shared__ double as[16][17], bs[16][17];
+  const int i0 = 16 * blockIdx.y, j0 = 16 * blockIdx.x;
+  const int ti = threadIdx.x % 16, tj = threadIdx.x / 16;
+  const int i = i0 + ti, j = j0 + tj;
+  double acc = 0.0;
+  if (i0 <= j0 + 15) {
+    for (int k0 = i0; k0 < j0 + 16 && k0 < n; k0 += 16) {
+      const int ka = k0 + tj, kb = k0 + ti;
+      as[ti][tj] = (i < n && ka < n && ka >= i) ? A[(int64_t)ka * lda + i] : 0.0;
+      bs[ti][tj] = (kb < n && j < n && kb <= j) ? B[(int64_t)j * ldb + kb] : 0.0;
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc += as[ti][k] * bs[k][tj];
+      __syncthreads();
+    }
   }
+  if (i < n && j < n) C[(int64_t)j * ldc + i] = (i <= j) ? acc : 0.0;
 }
 
 __global__ void k_poison(const int* __restrict__ info, int64_t m, int n, double* Q, int64_t ldq,
@@ -621,11 +633,8 @@ hipError_t launch_potrf(int n, const double* W, int64_t ldw, double* R, int64_t 
 
 hipError_t launch_trmm_upper(int n, const double* A, int64_t lda, const double* B, int64_t ldb,
                              double* C, int64_t ldc, hipStream_t st) {
-  const int64_t total = (int64_t)n * n;
-  int blocks = (int)((total + 255) / 256);
-  if (blocks > 2048) blocks = 2048;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_trmm_upper, dim3(blocks), dim3(256), 0, st, n, A, lda, B, ldb, C, ldc);
+  const int nb = (n + 15) / 16;
+  hipLaunchKernelGGL(k_trmm_upper, dim3(nb, nb), dim3(256), 0, st, n, A, lda, B, ldb, C, ldc);
   return hipGetLastError();
 }
 

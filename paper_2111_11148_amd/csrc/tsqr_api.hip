@@ -36,7 +36,7 @@ constexpr int64_t kMaxN = 256;  // widest n of the tall-skinny kernels in this b
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t info, B, R0, R1, R2, R10, W, fac, part, total;
+  size_t info, B, R0, R1, R2, R10, W, fac, Tt, part, total;
   SketchPlan sp;
   GramPlan gp;
 };
@@ -55,6 +55,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t s) {
   L.R10 = off; off += align256(nn);
   L.W = off; off += align256(nn);
   L.fac = off; off += align256((size_t)(s > n ? s : n) * n * sizeof(double));
+  L.Tt = off; off += align256(trsm_scratch_doubles((int)n) * sizeof(double));
   L.part = off;
   const size_t part = L.sp.part_doubles > L.gp.part_doubles ? L.sp.part_doubles : L.gp.part_doubles;
   off += align256(part * sizeof(double));
@@ -136,6 +137,7 @@ int run_chain(int variant, int64_t m, int64_t n, const double* A, int64_t lda, i
   double* R10 = (double*)(base + L.R10);
   double* W = (double*)(base + L.W);
   double* fac = (double*)(base + L.fac);
+  double* Tt = (double*)(base + L.Tt);
   double* part = (double*)(base + L.part);
   const int ni = (int)n, si = (int)s;
 
@@ -148,17 +150,17 @@ int run_chain(int variant, int64_t m, int64_t n, const double* A, int64_t lda, i
   TSQR_PHASE(variant == 1 ? "sketch_lu" : "sketch_qr",
              launch_sketch_factor(variant, si, ni, B, s, R0, n, info, fac, st));
   // A1 = A R0^{-1} (into Q), W1 = A1^T A1, R1 = chol(W1), Q1 = A1 R1^{-1}
-  TSQR_PHASE("trsm_r0", launch_trsm(m, ni, A, lda, R0, n, Q, ldq, st));
+  TSQR_PHASE("trsm_r0", launch_trsm(m, ni, A, lda, R0, n, Q, ldq, Tt, st));
   TSQR_PHASE("gram1", launch_gram(L.gp, m, ni, Q, ldq, part, st));
   TSQR_PHASE("gram1_reduce", launch_gram_reduce(L.gp, ni, part, W, n, st));
   TSQR_PHASE("potrf1", launch_potrf(ni, W, n, R1, n, 2, info, fac, st));
-  TSQR_PHASE("trsm_r1", launch_trsm(m, ni, Q, ldq, R1, n, Q, ldq, st));
+  TSQR_PHASE("trsm_r1", launch_trsm(m, ni, Q, ldq, R1, n, Q, ldq, Tt, st));
   if (extra_pass) {
     // W2 = Q1^T Q1, R2 = chol(W2), Q = Q1 R2^{-1}
     TSQR_PHASE("gram2", launch_gram(L.gp, m, ni, Q, ldq, part, st));
     TSQR_PHASE("gram2_reduce", launch_gram_reduce(L.gp, ni, part, W, n, st));
     TSQR_PHASE("potrf2", launch_potrf(ni, W, n, R2, n, 3, info, fac, st));
-    TSQR_PHASE("trsm_r2", launch_trsm(m, ni, Q, ldq, R2, n, Q, ldq, st));
+    TSQR_PHASE("trsm_r2", launch_trsm(m, ni, Q, ldq, R2, n, Q, ldq, Tt, st));
   }
   if (R) {
     if (extra_pass) {
@@ -347,8 +349,13 @@ int tsqr_sketch_factor(int variant, int64_t s, int64_t n, const double* B, int64
   return TSQR_OK;
 }
 
+size_t tsqr_trsm_workspace_bytes(int64_t n) {
+  if (n < 1 || n > kMaxN) return 0;
+  return trsm_scratch_doubles((int)n) * sizeof(double);
+}
+
 int tsqr_trsm(int64_t m, int64_t n, const double* Y, int64_t ldy, const double* T, int64_t ldt,
-              double* X, int64_t ldx, void* stream) {
+              double* X, int64_t ldx, void* work, size_t work_bytes, void* stream) {
   if (m < 0) return -1;
   if (n < 1) return -2;
   if (!Y) return -3;
@@ -361,7 +368,10 @@ int tsqr_trsm(int64_t m, int64_t n, const double* Y, int64_t ldy, const double* 
     return -7;
   if (X == Y && ldx != ldy) return -8;
   if (n > kMaxN) return TSQR_ERR_UNSUPPORTED;
-  if (launch_trsm(m, (int)n, Y, ldy, T, ldt, X, ldx, (hipStream_t)stream) != hipSuccess)
+  if (!work) return -9;
+  if (work_bytes < trsm_scratch_doubles((int)n) * sizeof(double)) return TSQR_ERR_WORKSPACE;
+  if (launch_trsm(m, (int)n, Y, ldy, T, ldt, X, ldx, (double*)work, (hipStream_t)stream) !=
+      hipSuccess)
     return TSQR_ERR_HIP;
   return TSQR_OK;
 }

@@ -41,9 +41,10 @@ hipError_t launch_gram(const GramPlan& p, int64_t m, int n, const double* X, int
 // W(n x n, ld ldw, both triangles) = sum of the Gram partials
 hipError_t launch_gram_reduce(const GramPlan& p, int n, const double* part, double* W,
                               int64_t ldw, hipStream_t st);
-// X = Y T^{-1} (T upper n x n); X may alias Y
+// X = Y T^{-1} (T upper n x n); X may alias Y; `scratch` holds trsm_scratch_doubles(n)
+size_t trsm_scratch_doubles(int n);
 hipError_t launch_trsm(int64_t m, int n, const double* Y, int64_t ldy, const double* T,
-                       int64_t ldt, double* X, int64_t ldx, hipStream_t st);
+                       int64_t ldt, double* X, int64_t ldx, double* scratch, hipStream_t st);
 // R0 from the s x n sketch: Householder (variant 0) or partial-pivot LU (variant 1);
 // `scratch` holds s*n doubles for the large-size fallback.
 hipError_t launch_sketch_factor(int variant, int s, int n, const double* B, int64_t ldb,
