@@ -101,6 +101,57 @@ int tsqr_rxr_cholqr_ws(int variant, int64_t m, int64_t n, const double* A, int64
                        int* d_info, void* stream);
 
 /* ------------------------------------------------------------------------------------
+ * Mixed precision
+ * ------------------------------------------------------------------------------------ */
+#define TSQR_LOWP_FP32 1 /* inputs rounded to FP32, FP32 matrix cores, FP32 accumulation */
+#define TSQR_LOWP_BF16 2 /* inputs rounded to BF16 (RNE of the FP32 value), FP32 accumulation */
+
+/* Randomized XR-preconditioned CholeskyQR with the data-heavy preconditioning steps in low
+ * precision and the orthogonalising passes in FP64 (the paper's framework, Section 2.2,
+ * with an inexact preconditioner as analysed in Appendix A):
+ *   B = S A in `lowp` (FP32 accumulation over at most 64 rows, FP64 partial sums);
+ *   R0 = R factor of B in FP64 (Householder or LU as `variant`);
+ *   R0^{-1} explicitly in FP64 (triangular solve of the identity), rounded to `lowp`;
+ *   A1 = A R0^{-1} and W1 = A1^T A1 in `lowp` (W1 summed in FP64);
+ *   R1 = chol(W1) in FP64; R01 = R1 R0 (or R0 alone if this Cholesky breaks down: the
+ *     low-precision factor is then discarded and the FP64 passes start from R0);
+ *   FP64 CholeskyQR passes on A R01^{-1}: Q1 = A R01^{-1} by FP64 substitution from the
+ *     FP64 A, W = Q1^T Q1, Rk = chol(W), Q = Q1 Rk^{-1}, R = Rk ... R01.
+ * fp64_passes (arg 9): 1, 2 or 3 fixed FP64 passes, or 0 = automatic: a further pass runs
+ *   while the Gram matrix of a pass's input deviates from I by more than 1/2 in Frobenius
+ *   norm (or a breakdown occurred), at most 3 passes.  The automatic mode waits on the
+ *   host once per pass for that decision; the fixed modes never wait.
+ * passes_out (arg 16): host int receiving the number of FP64 passes run, or NULL.
+ * lowp (arg 2): TSQR_LOWP_FP32 or TSQR_LOWP_BF16.  Other arguments as in
+ * tsqr_rxr_cholqr_ws (shifted by one position); info stages 3 and 4 are the FP64 passes.
+ * Workspace: tsqr_mixed_workspace_bytes(m, n, s, lowp) bytes. */
+size_t tsqr_mixed_workspace_bytes(int64_t m, int64_t n, int64_t sketch_rows, int lowp);
+int tsqr_rxr_cholqr_mixed_ws(int variant, int lowp, int64_t m, int64_t n, const double* A,
+                             int64_t lda, int64_t sketch_rows, uint64_t seed, int fp64_passes,
+                             double* Q, int64_t ldq, double* R, int64_t ldr, void* work,
+                             size_t work_bytes, int* d_info, int* passes_out, void* stream);
+
+/* Low-precision steps of the mixed variant (step-wise validation):
+ *   tsqr_sketch_lowp: B = S A (s x n FP64, ldb >= s) with the entries of S and A rounded
+ *     to `lowp`, FP32 accumulation over at most 64 rows, FP64 partial sums; workspace
+ *     tsqr_sketch_workspace_bytes(m, n, s).
+ *   tsqr_apply_rinv_lowp: X = r(Y) r(Rinv) for upper-triangular Rinv (n x n FP64, rounded
+ *     inside), FP32 accumulation; X (m x n, ldx >= m) holds FP32 or BF16 elements (2-byte
+ *     BF16 bit patterns); workspace tsqr_rinv_lowp_bytes(n, lowp).
+ *   tsqr_gram_lowp: W = X^T X (both triangles, FP64) for X in `lowp` elements as written
+ *     by tsqr_apply_rinv_lowp; FP32 accumulation over 64 rows, FP64 partial sums;
+ *     workspace tsqr_gram_workspace_bytes(m, n). */
+int tsqr_sketch_lowp(int lowp, int64_t m, int64_t n, const double* A, int64_t lda, int64_t s,
+                     uint64_t seed, double* B, int64_t ldb, void* work, size_t work_bytes,
+                     void* stream);
+size_t tsqr_rinv_lowp_bytes(int64_t n, int lowp);
+int tsqr_apply_rinv_lowp(int lowp, int64_t m, int64_t n, const double* Y, int64_t ldy,
+                         const double* Rinv, int64_t ldr, void* X, int64_t ldx, void* work,
+                         size_t work_bytes, void* stream);
+int tsqr_gram_lowp(int lowp, int64_t m, int64_t n, const void* X, int64_t ldx, double* W,
+                   int64_t ldw, void* work, size_t work_bytes, void* stream);
+
+/* ------------------------------------------------------------------------------------
  * Steps of the method, one entry point per step (used for step-wise validation)
  * ------------------------------------------------------------------------------------ */
 

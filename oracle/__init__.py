@@ -224,3 +224,89 @@ def residual(A: np.ndarray, Q: np.ndarray, R: np.ndarray) -> float:
 
 def num_threads() -> int:
     return _load().or_num_threads()
+
+
+# ------------------------------------------------------------------ mixed precision ----
+FP32 = 1
+BF16 = 2
+
+_MIXED_SIGS = {
+    "or_round_fp32": (ctypes.c_double, [ctypes.c_double]),
+    "or_round_bf16": (ctypes.c_double, [ctypes.c_double]),
+    "or_sketch_apply_lowp": (None, [_c_int, _c_i64, _c_i64, _c_dp, _c_i64, _c_i64, _c_u64, _c_dp,
+                                    _c_i64]),
+    "or_apply_rinv_lowp": (None, [_c_int, _c_i64, _c_i64, _c_dp, _c_i64, _c_dp, _c_i64, _c_dp,
+                                  _c_i64]),
+    "or_gram_lowp": (None, [_c_int, _c_i64, _c_i64, _c_dp, _c_i64, _c_dp, _c_i64]),
+    "or_trtri_upper": (None, [_c_i64, _c_dp, _c_i64, _c_dp, _c_i64]),
+    "or_rxr_cholqr_mixed": (_c_int, [_c_int, _c_int, _c_i64, _c_i64, _c_dp, _c_i64, _c_i64, _c_u64,
+                                     _c_int, _c_dp, _c_i64, _c_dp, _c_i64,
+                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+}
+
+
+def _load_mixed():
+    lib = _load()
+    if not getattr(lib, "_mixed_sigs", False):
+        for name, (res, args) in _MIXED_SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        lib._mixed_sigs = True
+    return lib
+
+
+def round_fp32(x: float) -> float:
+    return _load_mixed().or_round_fp32(x)
+
+
+def round_bf16(x: float) -> float:
+    return _load_mixed().or_round_bf16(x)
+
+
+def sketch_apply_lowp(prec: int, A: np.ndarray, s: int, seed: int) -> np.ndarray:
+    A = _f64(A, "A")
+    m, n = A.shape
+    B = np.zeros((s, n), dtype=np.float64, order="F")
+    _load_mixed().or_sketch_apply_lowp(prec, m, n, _ptr(A), _ld(A), s, seed, _ptr(B), max(1, s))
+    return B
+
+
+def apply_rinv_lowp(prec: int, Y: np.ndarray, Rinv: np.ndarray) -> np.ndarray:
+    Y = _f64(Y, "Y")
+    Rinv = _f64(Rinv, "Rinv")
+    m, n = Y.shape
+    X = np.zeros((m, n), dtype=np.float64, order="F")
+    _load_mixed().or_apply_rinv_lowp(prec, m, n, _ptr(Y), _ld(Y), _ptr(Rinv), _ld(Rinv), _ptr(X),
+                                     max(1, m))
+    return X
+
+
+def gram_lowp(prec: int, X: np.ndarray) -> np.ndarray:
+    X = _f64(X, "X")
+    m, n = X.shape
+    W = np.zeros((n, n), dtype=np.float64, order="F")
+    _load_mixed().or_gram_lowp(prec, m, n, _ptr(X), _ld(X), _ptr(W), max(1, n))
+    return W
+
+
+def trtri_upper(T: np.ndarray) -> np.ndarray:
+    T = _f64(T, "T")
+    n = T.shape[0]
+    X = np.zeros((n, n), dtype=np.float64, order="F")
+    _load_mixed().or_trtri_upper(n, _ptr(T), _ld(T), _ptr(X), max(1, n))
+    return X
+
+
+def rxr_cholqr_mixed(A: np.ndarray, s: int, seed: int, prec: int = FP32, variant: int = RQR,
+                     fp64_passes: int = 1):
+    A = _f64(A, "A")
+    m, n = A.shape
+    Q = np.zeros((m, n), dtype=np.float64, order="F")
+    R = np.zeros((n, n), dtype=np.float64, order="F")
+    lp = ctypes.c_int(0)
+    npass = ctypes.c_int(0)
+    info = _load_mixed().or_rxr_cholqr_mixed(variant, prec, m, n, _ptr(A), _ld(A), s, seed,
+                                             fp64_passes, _ptr(Q), max(1, m), _ptr(R), max(1, n),
+                                             ctypes.byref(lp), ctypes.byref(npass))
+    return {"Q": Q, "R": R, "info": info, "lp_info": lp.value, "passes": npass.value}

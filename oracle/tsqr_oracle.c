@@ -522,3 +522,171 @@ int or_num_threads(void) {
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------------------
+ * Mixed precision (a reading of the benchmark's mixed configuration, not in the paper):
+ * the sketch, the preconditioner apply A1 = A R0^{-1} and the first Gram matrix take
+ * inputs rounded to FP32 or BF16; R0, R0^{-1}, the Cholesky factors, the R products and
+ * the final CholeskyQR passes are FP64.  Roundings: FP64 -> FP32 round to nearest even;
+ * BF16 = round to nearest even of that FP32 value to 8 significant bits.  The low-precision
+ * steps here are the exact (FP64-accumulated) sums of the rounded inputs; a device may
+ * add FP32 accumulation error on top, bounded in the tests.
+ * ------------------------------------------------------------------------------------ */
+#define OR_FP32 1
+#define OR_BF16 2
+
+double or_round_fp32(double x) { return (double)(float)x; }
+
+double or_round_bf16(double x) {
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (double)f; /* inf / nan unchanged */
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb; /* round to nearest, ties to even, on the upper 16 bits */
+    u &= 0xffff0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+static double or_round_p(int prec, double x) {
+    return prec == OR_BF16 ? or_round_bf16(x) : or_round_fp32(x);
+}
+
+/* B = (1/sqrt(s)) * sum_j r(Z(i,j)) r(A(j,c)), r = rounding to the input type; the
+ * normal Z is first made an FP32 number (as the sketch defines it). */
+void or_sketch_apply_lowp(int prec, int64_t m, int64_t n, const double *A, int64_t lda,
+                          int64_t s, uint64_t seed, double *B, int64_t ldb) {
+    double rs = 1.0 / sqrt((double)s);
+#pragma omp parallel
+    {
+        double *zrow = (double *)malloc((size_t)(m > 0 ? m : 1) * sizeof(double));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t i = 0; i < s; ++i) {
+            for (int64_t j = 0; j < m; ++j)
+                zrow[j] = or_round_p(prec, or_round_fp32(or_sketch_normal(seed, i, j)));
+            for (int64_t c = 0; c < n; ++c) {
+                double acc = 0.0;
+                for (int64_t j = 0; j < m; ++j) acc += zrow[j] * or_round_p(prec, A[IDX(j, c, lda)]);
+                B[IDX(i, c, ldb)] = rs * acc;
+            }
+        }
+        free(zrow);
+    }
+}
+
+/* X = r(Y) r(Rinv) for upper-triangular Rinv, summed in FP64, then rounded to the input
+ * type (the stored low-precision A1). */
+void or_apply_rinv_lowp(int prec, int64_t m, int64_t n, const double *Y, int64_t ldy,
+                        const double *Rinv, int64_t ldr, double *X, int64_t ldx) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t c = 0; c < n; ++c) {
+            double acc = 0.0;
+            for (int64_t k = 0; k <= c; ++k)
+                acc += or_round_p(prec, Y[IDX(i, k, ldy)]) * or_round_p(prec, Rinv[IDX(k, c, ldr)]);
+            X[IDX(i, c, ldx)] = or_round_p(prec, acc);
+        }
+}
+
+/* W = r(X)^T r(X), FP64 sums (both triangles). */
+void or_gram_lowp(int prec, int64_t m, int64_t n, const double *X, int64_t ldx, double *W,
+                  int64_t ldw) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t b = 0; b < n; ++b)
+        for (int64_t a = 0; a <= b; ++a) {
+            double acc = 0.0;
+            for (int64_t j = 0; j < m; ++j)
+                acc += or_round_p(prec, X[IDX(j, a, ldx)]) * or_round_p(prec, X[IDX(j, b, ldx)]);
+            W[IDX(a, b, ldw)] = acc;
+            W[IDX(b, a, ldw)] = acc;
+        }
+}
+
+/* Inverse of an upper-triangular T by substitution, column by column (T X = I). */
+void or_trtri_upper(int64_t n, const double *T, int64_t ldt, double *X, int64_t ldx) {
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = n - 1; i >= 0; --i) {
+            double acc = (i == j) ? 1.0 : 0.0;
+            if (i > j) { X[IDX(i, j, ldx)] = 0.0; continue; }
+            for (int64_t k = i + 1; k <= j; ++k) acc -= T[IDX(i, k, ldt)] * X[IDX(k, j, ldx)];
+            X[IDX(i, j, ldx)] = acc / T[IDX(i, i, ldt)];
+        }
+}
+
+/* The mixed-precision method with a fixed number of FP64 passes (1..3):
+ *   B = lowp sketch;  R0 = R factor of B (FP64);  R0inv = R0^{-1} (FP64);
+ *   A1 = lowp(A R0inv);  W1 = lowp Gram of A1;  R1 = chol(W1)  (breakdown -> R01 = R0);
+ *   R01 = R1 R0;  Q = A R01^{-1};  passes: W = Q^T Q, Rk = chol(W), Q = Q Rk^{-1},
+ *   R = Rk ... R01.
+ * Returns info as or_rxr_cholqr (stages 3, 4 = first, further FP64 passes); *lp_info
+ * receives the low-precision Cholesky's breakdown column (0 if none), *passes_out the
+ * number of FP64 passes completed. */
+int or_rxr_cholqr_mixed(int variant, int prec, int64_t m, int64_t n, const double *A,
+                        int64_t lda, int64_t s, uint64_t seed, int fp64_passes, double *Q,
+                        int64_t ldq, double *R, int64_t ldr, int *lp_info, int *passes_out) {
+    size_t nn = (size_t)n * (size_t)n;
+    double *B = (double *)malloc((size_t)s * (size_t)n * sizeof(double));
+    double *R0 = (double *)calloc(nn, sizeof(double));
+    double *R0inv = (double *)calloc(nn, sizeof(double));
+    double *R1 = (double *)calloc(nn, sizeof(double));
+    double *Racc = (double *)calloc(nn, sizeof(double));
+    double *Rk = (double *)calloc(nn, sizeof(double));
+    double *T = (double *)calloc(nn, sizeof(double));
+    double *W = (double *)calloc(nn, sizeof(double));
+    double *A1 = (double *)malloc((size_t)m * (size_t)n * sizeof(double));
+    int info = 0, lp = 0, npass = 0;
+
+    or_sketch_apply_lowp(prec, m, n, A, lda, s, seed, B, s);
+    info = (variant == 1) ? or_lu_r(s, n, B, s, R0, n, NULL) : or_householder_r(s, n, B, s, R0, n);
+    if (!info) {
+        or_trtri_upper(n, R0, n, R0inv, n);
+        or_apply_rinv_lowp(prec, m, n, A, lda, R0inv, n, A1, m);
+        or_gram_lowp(prec, m, n, A1, m, W, n);
+        lp = or_cholesky_upper(n, W, n, R1, n);
+        if (lp) memcpy(Racc, R0, nn * sizeof(double));
+        else or_trmm_upper(n, R1, n, R0, n, Racc, n);
+        or_trsm_ru(m, n, A, lda, Racc, n, Q, ldq);
+        /* fp64_passes = 1..3: that many plain passes.  0 = automatic: per pass, with
+         * W = Q^T Q, dev = ||W - I||_F; a Cholesky breakdown is retried with the shift
+         * 11 (m n + n (n+1)) u ||W||_F on the diagonal (shifted CholeskyQR, paper
+         * Section 2.1); another pass follows while dev > 1/2 or the shift was used, at
+         * most three passes. */
+        int maxp = fp64_passes > 0 ? fp64_passes : 3, more = 1;
+        for (int pass = 0; pass < maxp && more && !info; ++pass) {
+            or_gram(m, n, Q, ldq, W, n);
+            double dev2 = 0.0, w2 = 0.0;
+            for (int64_t j = 0; j < n; ++j)
+                for (int64_t i = 0; i < n; ++i) {
+                    double d = W[IDX(i, j, n)] - (i == j ? 1.0 : 0.0);
+                    dev2 += d * d;
+                    w2 += W[IDX(i, j, n)] * W[IDX(i, j, n)];
+                }
+            int c = or_cholesky_upper(n, W, n, Rk, n), shifted = 0;
+            if (c && fp64_passes == 0) {
+                double shift = 11.0 * ((double)m * (double)n + (double)n * (double)(n + 1)) *
+                               0x1p-53 * sqrt(w2);
+                for (int64_t k = 0; k < n; ++k) W[IDX(k, k, n)] += shift;
+                c = or_cholesky_upper(n, W, n, Rk, n);
+                shifted = 1;
+            }
+            if (c) { info = (pass == 0 ? 3000 : 4000) + c; break; }
+            or_trsm_ru(m, n, Q, ldq, Rk, n, Q, ldq);
+            or_trmm_upper(n, Rk, n, Racc, n, T, n);
+            memcpy(Racc, T, nn * sizeof(double));
+            ++npass;
+            if (fp64_passes == 0) more = shifted || !(sqrt(dev2) <= 0.5);
+        }
+    }
+    if (!info)
+        for (int64_t j = 0; j < n; ++j)
+            for (int64_t i = 0; i < n; ++i) R[IDX(i, j, ldr)] = Racc[IDX(i, j, n)];
+    else {
+        fill_nan(m, n, Q, ldq);
+        fill_nan(n, n, R, ldr);
+    }
+    if (lp_info) *lp_info = lp;
+    if (passes_out) *passes_out = npass;
+    free(B); free(R0); free(R0inv); free(R1); free(Racc); free(Rk); free(T); free(W); free(A1);
+    return info;
+}

@@ -47,6 +47,15 @@ _SIGS = {
     "tsqr_philox4x32_10": (_int, [_i64, _vp, _u64, _vp, _vp]),
     "tsqr_sketch_normals": (_int, [_u64, _i64, _i64, _i64, _i64, _vp, _i64, _vp]),
     "tsqr_version": (ctypes.c_char_p, []),
+    "tsqr_mixed_workspace_bytes": (_sz, [_i64, _i64, _i64, _int]),
+    "tsqr_rxr_cholqr_mixed_ws": (_int, [_int, _int, _i64, _i64, _vp, _i64, _i64, _u64, _int, _vp,
+                                        _i64, _vp, _i64, _vp, _sz, _vp,
+                                        ctypes.POINTER(ctypes.c_int), _vp]),
+    "tsqr_sketch_lowp": (_int, [_int, _i64, _i64, _vp, _i64, _i64, _u64, _vp, _i64, _vp, _sz, _vp]),
+    "tsqr_rinv_lowp_bytes": (_sz, [_i64, _int]),
+    "tsqr_apply_rinv_lowp": (_int, [_int, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz,
+                                    _vp]),
+    "tsqr_gram_lowp": (_int, [_int, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp]),
     "tsqr_profile_start": (_int, []),
     "tsqr_profile_stop": (_int, []),
     "tsqr_profile_record": (_int, [_int, ctypes.POINTER(ctypes.c_char_p),
@@ -188,6 +197,89 @@ def rxr_cholqr(A: torch.Tensor, sketch_rows: int, seed: int, variant: int = RQR,
                                    _stream(stream))
     _check(rc, "tsqr_rxr_cholqr_ws")
     return Q, R, info
+
+
+FP32 = 1
+BF16 = 2
+
+
+def mixed_workspace_bytes(m: int, n: int, sketch_rows: int, lowp: int) -> int:
+    return int(load().tsqr_mixed_workspace_bytes(m, n, sketch_rows, lowp))
+
+
+def rxr_cholqr_mixed(A: torch.Tensor, sketch_rows: int, seed: int, lowp: int = FP32,
+                     variant: int = RQR, fp64_passes: int = 0, Q: torch.Tensor | None = None,
+                     R: torch.Tensor | None = None, want_r: bool = True,
+                     workspace: torch.Tensor | None = None, info: torch.Tensor | None = None,
+                     stream=None):
+    """Mixed-precision variant (low-precision sketch, apply and first Gram; FP64 passes).
+
+    fp64_passes: 1-3 fixed FP64 CholeskyQR passes, or 0 for the automatic rule.
+    Returns (Q, R, info, passes)."""
+    lda = _mat(A, "A")
+    m, n = A.shape
+    if Q is None:
+        Q = colmajor(m, n, device=A.device)
+    ldq = _mat(Q, "Q", m, n)
+    if R is None and want_r:
+        R = colmajor(n, n, device=A.device)
+    ldr = _mat(R, "R", n, n) if R is not None else n
+    if workspace is None:
+        nbytes = mixed_workspace_bytes(m, n, sketch_rows, lowp)
+        if nbytes == 0:
+            raise ValueError("invalid sizes for the workspace")
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    passes = ctypes.c_int(0)
+    rc = load().tsqr_rxr_cholqr_mixed_ws(variant, lowp, m, n, A.data_ptr(), lda, sketch_rows,
+                                         seed, fp64_passes, Q.data_ptr(), ldq,
+                                         R.data_ptr() if R is not None else None, ldr,
+                                         workspace.data_ptr(), workspace.numel(),
+                                         info.data_ptr(), ctypes.byref(passes), _stream(stream))
+    _check(rc, "tsqr_rxr_cholqr_mixed_ws")
+    return Q, R, info, passes.value
+
+
+def sketch_lowp(A: torch.Tensor, s: int, seed: int, lowp: int = FP32, stream=None):
+    lda = _mat(A, "A")
+    m, n = A.shape
+    B = colmajor(s, n, device=A.device)
+    nbytes = int(load().tsqr_sketch_workspace_bytes(m, n, s))
+    work = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=A.device)
+    _check(load().tsqr_sketch_lowp(lowp, m, n, A.data_ptr(), lda, s, seed, B.data_ptr(), s,
+                                   work.data_ptr(), nbytes, _stream(stream)), "tsqr_sketch_lowp")
+    return B
+
+
+def apply_rinv_lowp(Y: torch.Tensor, Rinv: torch.Tensor, lowp: int = FP32, stream=None):
+    """X = r(Y) r(Rinv) in the low-precision type (float32 or bfloat16 tensor, column-major)."""
+    ldy = _mat(Y, "Y")
+    m, n = Y.shape
+    ldr = _mat(Rinv, "Rinv", n, n)
+    X = colmajor(m, n, device=Y.device, dtype=torch.float32 if lowp == FP32 else torch.bfloat16)
+    nbytes = int(load().tsqr_rinv_lowp_bytes(n, lowp))
+    work = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=Y.device)
+    _check(load().tsqr_apply_rinv_lowp(lowp, m, n, Y.data_ptr(), ldy, Rinv.data_ptr(), ldr,
+                                       X.data_ptr(), m, work.data_ptr(), nbytes, _stream(stream)),
+           "tsqr_apply_rinv_lowp")
+    return X
+
+
+def gram_lowp(X: torch.Tensor, lowp: int = FP32, stream=None) -> torch.Tensor:
+    want = torch.float32 if lowp == FP32 else torch.bfloat16
+    if X.dtype != want or X.device.type != "cuda" or X.dim() != 2:
+        raise ValueError(f"X must be a {want} GPU matrix")
+    m, n = X.shape
+    if n > 1 and m > 1 and X.stride(0) != 1:
+        raise ValueError("X must be column-major")
+    ldx = X.stride(1) if n > 1 else m
+    W = colmajor(n, n, device=X.device)
+    nbytes = int(load().tsqr_gram_workspace_bytes(m, n))
+    work = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=X.device)
+    _check(load().tsqr_gram_lowp(lowp, m, n, X.data_ptr(), ldx, W.data_ptr(), n, work.data_ptr(),
+                                 nbytes, _stream(stream)), "tsqr_gram_lowp")
+    return W
 
 
 def rqr_cholqr(A: torch.Tensor, sketch_rows: int, seed: int, stream=None):

@@ -1,0 +1,475 @@
+// Low-precision phases of the mixed-precision variant: the sketch B = S A, the
+// preconditioner apply A1 = A R0^{-1} (with the explicit inverse, computed in FP64 and
+// rounded) and the first Gram matrix A1^T A1, each with FP32 or BF16 inputs on the
+// matrix cores and FP32 accumulation; partial sums are kept in FP64.
+//
+// MFMA shapes (gfx950): V_MFMA_F32_16X16X4_F32 (one FP32 value per lane and operand, K = 4)
+// and V_MFMA_F32_16X16X32_BF16 (eight BF16 values per lane, K = 32).  In both, lane l
+// supplies A[l%16][KPL*(l/16) + e] and B[KPL*(l/16) + e][l%16] (e < KPL) and holds
+// D[4*(l/16) + r][l%16] in register r.
+//
+// Roundings: FP64 -> FP32 is round-to-nearest-even; BF16 is the round-to-nearest-even
+// BF16 of that FP32 value (two roundings, kept apart on purpose: see LowT).  Sketch normals are FP32 numbers (BF16 path: rounded).
+#include "tsqr_device.hpp"
+#include "tsqr_launch.hpp"
+
+namespace tsqr {
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ v4f mfma_f32(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma_bf16(v8bf a, v8bf b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+template <int PREC>
+struct LowT;
+template <>
+struct LowT<TSQR_LOWP_FP32> {
+  typedef float E;
+  static __device__ __forceinline__ E from_double(double x) { return (float)x; }
+  static __device__ __forceinline__ E from_float(float x) { return x; }
+};
+template <>
+struct LowT<TSQR_LOWP_BF16> {
+  typedef __bf16 E;
+  // Two roundings, FP64 -> FP32 -> BF16, each to nearest even.  The compiler would
+  // otherwise fuse the pair into one correctly rounded FP64 -> BF16 conversion (a
+  // different value for inputs near a BF16 midpoint, and a longer instruction sequence);
+  // the empty asm makes the FP32 value opaque so both roundings happen as written.
+  static __device__ __forceinline__ E from_double(double x) {
+    float f = (float)x;
+    asm volatile("" : "+v"(f));
+    return (__bf16)f;
+  }
+  static __device__ __forceinline__ E from_float(float x) { return (__bf16)x; }
+};
+
+// value D[i][j] held at (lane, reg) in the low-precision accumulator layout goes to the
+// FP64 tile-native position (16*reg + lane%16, lane/16) used by the partial-sum reductions
+__device__ __forceinline__ int lowp_to_f64_tile_index(int lane, int r) {
+  return (16 * r + (lane & 15)) * 4 + (lane >> 4);
+}
+
+// ===================================================================== sketch ====
+// One workgroup: a row block of A, i-tiles it0.. of B for each wavefront, JT column tiles.
+// A is staged in LDS column-major (rows contiguous) already rounded to the input type.
+template <int PREC, int IT, int JT, int NW>
+__global__ __launch_bounds__(NW * 64) void k_sketch_lowp(
+    int64_t m, int n, const double* __restrict__ A, int64_t lda, uint32_t k0, uint32_t k1,
+    int64_t rows_per_block, int it_total, int jt_total, double* __restrict__ part) {
+  typedef typename LowT<PREC>::E E;
+  constexpr int KC = 64;                       // rows per chunk
+  constexpr int NC = JT * 16;
+  constexpr int LDR = (PREC == TSQR_LOWP_FP32) ? KC + 1 : KC + 8;
+  constexpr int T = NW * 64;
+  __shared__ __attribute__((aligned(16))) E lds[NC * LDR];
+
+  const int lane = lane_id(), wave = wave_id();
+  const int q = lane >> 4, c16 = lane & 15;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = min(m, r0 + rows_per_block);
+  const int it0 = (int)blockIdx.y * (NW * IT) + wave * IT;
+  const int c0 = (int)blockIdx.z * NC;
+
+  v4f acc[IT][JT];
+  v4d acc64[IT][JT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it)
+#pragma unroll
+    for (int jt = 0; jt < JT; ++jt) {
+      acc[it][jt] = v4f{0.f, 0.f, 0.f, 0.f};
+      acc64[it][jt] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+
+  for (int64_t rb = r0; rb < r1; rb += KC) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < KC * NC; e += T) {
+      const int rr = e % KC, cc = e / KC;
+      const int64_t row = rb + rr;
+      const int col = c0 + cc;
+      const double v = (row < r1 && col < n) ? A[(int64_t)col * lda + row] : 0.0;
+      lds[cc * LDR + rr] = LowT<PREC>::from_double(v);
+    }
+    __syncthreads();
+    if (PREC == TSQR_LOWP_FP32) {
+#pragma unroll
+      for (int g = 0; g < KC / 16; ++g) {
+        const int64_t jbase = rb + 16 * g;
+        if (jbase >= r1) break;
+        float z[IT][4];
+#pragma unroll
+        for (int it = 0; it < IT; ++it)
+          sketch_normals4((uint64_t)(jbase >> 2) + (uint64_t)q, (uint32_t)((it0 + it) * 16 + c16),
+                          k0, k1, z[it]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          float bop[JT];
+#pragma unroll
+          for (int jt = 0; jt < JT; ++jt)
+            bop[jt] = (float)lds[(16 * jt + c16) * LDR + 16 * g + 4 * q + t];
+#pragma unroll
+          for (int it = 0; it < IT; ++it)
+#pragma unroll
+            for (int jt = 0; jt < JT; ++jt) acc[it][jt] = mfma_f32(z[it][t], bop[jt], acc[it][jt]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int g = 0; g < KC / 32; ++g) {
+        const int64_t jbase = rb + 32 * g;
+        if (jbase >= r1) break;
+        v8bf a8[IT];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+          float z[8];
+          const uint32_t i = (uint32_t)((it0 + it) * 16 + c16);
+          const uint64_t p = (uint64_t)(jbase >> 2) + 2 * (uint64_t)q;
+          sketch_normals4(p, i, k0, k1, z);
+          sketch_normals4(p + 1, i, k0, k1, z + 4);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) a8[it][e] = (__bf16)z[e];
+        }
+#pragma unroll
+        for (int jt = 0; jt < JT; ++jt) {
+          const v8bf b8 =
+              *reinterpret_cast<const v8bf*>(&lds[(16 * jt + c16) * LDR + 32 * g + 8 * q]);
+#pragma unroll
+          for (int it = 0; it < IT; ++it) acc[it][jt] = mfma_bf16(a8[it], b8, acc[it][jt]);
+        }
+      }
+    }
+    // FP32 accumulation over at most 64 rows, then into FP64
+#pragma unroll
+    for (int it = 0; it < IT; ++it)
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc64[it][jt][r] += (double)acc[it][jt][r];
+        acc[it][jt] = v4f{0.f, 0.f, 0.f, 0.f};
+      }
+  }
+
+  const size_t Et = (size_t)it_total * jt_total * 256;
+  double* dst = part + (size_t)blockIdx.x * Et;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int itg = it0 + it;
+    if (itg >= it_total) continue;
+#pragma unroll
+    for (int jt = 0; jt < JT; ++jt) {
+      const int jtg = (int)blockIdx.z * JT + jt;
+      if (jtg >= jt_total) continue;
+      double* tp = dst + ((size_t)itg * jt_total + jtg) * 256;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) tp[lowp_to_f64_tile_index(lane, r)] = acc64[it][jt][r];
+    }
+  }
+}
+
+// ======================================================== apply A1 = A R0^{-1} ====
+// Rinv (n x n upper, FP64) is rounded into the input type and laid out for the A
+// operand: FP32 as upper 16x16 tiles (tile (a,b) row-major at tri_index(a,b)*256), BF16
+// as a padded column-major matrix (ld = rinv_bf16_ld(JT)) so eight consecutive k of a
+// column are one 16-byte read.
+__host__ __device__ constexpr int lp_tri_index(int a, int b) { return b * (b + 1) / 2 + a; }
+
+// BF16 layout leading dimension: every K-group of 32 rows that a column tile reads must lie
+// inside its own column, so ld >= 32 * ceil(jt / 2); the +8 staggers LDS banks.
+__host__ __device__ constexpr int rinv_bf16_ld(int jt) { return 32 * ((jt + 1) / 2) + 8; }
+
+template <int PREC>
+__host__ __device__ constexpr size_t rinv_elems(int jt) {
+  return PREC == TSQR_LOWP_FP32 ? (size_t)jt * (jt + 1) / 2 * 256
+                                : (size_t)(16 * jt) * rinv_bf16_ld(jt);
+}
+
+template <int PREC>
+__global__ void k_rinv_prep(int n, int jt, const double* __restrict__ Rinv, int64_t ldr,
+                            typename LowT<PREC>::E* __restrict__ out) {
+  const size_t total = rinv_elems<PREC>(jt);
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    int k, c;
+    if (PREC == TSQR_LOWP_FP32) {
+      const int t = (int)(e / 256), w = (int)(e % 256);
+      int b = 0;
+      while ((b + 1) * (b + 2) / 2 <= t) ++b;
+      const int a = t - b * (b + 1) / 2;
+      k = 16 * a + w / 16;
+      c = 16 * b + w % 16;
+    } else {
+      const int ld = rinv_bf16_ld(jt);
+      c = (int)(e / ld);
+      k = (int)(e % ld);
+    }
+    const double v = (k < n && c < n && k <= c) ? Rinv[(int64_t)c * ldr + k] : 0.0;
+    out[e] = LowT<PREC>::from_double(v);
+  }
+}
+
+// One wavefront per 16-row tile; output X = Y Rinv in the input type (column-major).
+// FP32: K-step kk of block a feeds Y(row, 16a + 4kk + q) as the B operand.
+// BF16: K-group g feeds Y(row, 32g + 8q .. 32g + 8q + 7).
+template <int PREC, int JT>
+__global__ __launch_bounds__(256) void k_apply_rinv_lowp(
+    int64_t m, int n, const double* __restrict__ Y, int64_t ldy,
+    const typename LowT<PREC>::E* __restrict__ Ri, typename LowT<PREC>::E* X, int64_t ldx) {
+  typedef typename LowT<PREC>::E E;
+  constexpr size_t NE = rinv_elems<PREC>(JT);
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  E* rl = reinterpret_cast<E*>(smem);
+  for (size_t e = threadIdx.x; e < NE; e += blockDim.x) rl[e] = Ri[e];
+  __syncthreads();
+
+  const int lane = lane_id();
+  const int q = lane >> 4, c16 = lane & 15;
+  const int64_t ntiles = (m + 15) / 16;
+  const int64_t wstride = (int64_t)gridDim.x * (blockDim.x / kWave);
+  for (int64_t tile = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); tile < ntiles;
+       tile += wstride) {
+    typedef __attribute__((address_space(3))) E lds_e;
+    lds_e* rp = (lds_e*)rl;
+    asm volatile("" : "+v"(rp));
+    const int64_t row = tile * 16 + c16;
+    const bool rok = row < m;
+    v4f acc[JT];
+#pragma unroll
+    for (int b = 0; b < JT; ++b) acc[b] = v4f{0.f, 0.f, 0.f, 0.f};
+    if (PREC == TSQR_LOWP_FP32) {
+      float yv[JT][4];
+#pragma unroll
+      for (int a = 0; a < JT; ++a)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int col = 16 * a + 4 * kk + q;
+          yv[a][kk] = (rok && col < n) ? (float)Y[(int64_t)col * ldy + row] : 0.f;
+        }
+#pragma unroll
+      for (int b = 0; b < JT; ++b)
+#pragma unroll
+        for (int a = 0; a <= b; ++a)
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk)
+            acc[b] = mfma_f32((float)rp[lp_tri_index(a, b) * 256 + (4 * kk + q) * 16 + c16],
+                              yv[a][kk], acc[b]);
+    } else {
+      constexpr int NG = (JT + 1) / 2;  // K-groups of 32 columns
+      constexpr int LD = rinv_bf16_ld(JT);
+      v8bf yv[NG];
+#pragma unroll
+      for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int col = 32 * g + 8 * q + e;
+          yv[g][e] = LowT<PREC>::from_double((rok && col < n) ? Y[(int64_t)col * ldy + row] : 0.0);
+        }
+#pragma unroll
+      for (int b = 0; b < JT; ++b)
+#pragma unroll
+        for (int g = 0; g <= b / 2; ++g) {
+          const v8bf a8 = *reinterpret_cast<const v8bf*>((const E*)rp + (16 * b + c16) * LD + 32 * g + 8 * q);
+          acc[b] = mfma_bf16(a8, yv[g], acc[b]);
+        }
+    }
+    if (rok) {
+#pragma unroll
+      for (int b = 0; b < JT; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int col = 16 * b + 4 * q + r;
+          if (col < n) X[(int64_t)col * ldx + row] = LowT<PREC>::from_float(acc[b][r]);
+        }
+    }
+  }
+}
+
+// ================================================================= Gram (low) ====
+// W partials (FP64, tile-native) of X^T X for X in the input type; rows staged in LDS
+// (FP32: row-major; BF16: column-major so eight consecutive rows are one 16-byte read);
+// FP32 accumulation over each 64-row chunk, then FP64.
+template <int PREC, int JT, int NW>
+__global__ __launch_bounds__(NW * 64) void k_gram_lowp(int64_t m, int n,
+                                                       const typename LowT<PREC>::E* __restrict__ X,
+                                                       int64_t ldx, int64_t rows_per_block,
+                                                       int ntiles, double* __restrict__ part) {
+  typedef typename LowT<PREC>::E E;
+  constexpr int KC = 64;
+  constexpr int NC = JT * 16;
+  constexpr int NT = JT * (JT + 1) / 2;
+  constexpr int TPW = (NT + NW - 1) / NW;
+  constexpr int LDA = (PREC == TSQR_LOWP_FP32) ? NC + 1 : KC + 8;  // row-major / col-major
+  __shared__ __attribute__((aligned(16))) E lds[(PREC == TSQR_LOWP_FP32) ? KC * LDA : NC * LDA];
+
+  const int lane = lane_id(), wave = wave_id();
+  const int q = lane >> 4, c16 = lane & 15;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = min(m, r0 + rows_per_block);
+  v4f acc[TPW];
+  v4d acc64[TPW];
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) {
+    acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
+    acc64[u] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
+  for (int64_t rb = r0; rb < r1; rb += KC) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < KC * NC; e += NW * 64) {
+      const int rr = e % KC, cc = e / KC;
+      const int64_t row = rb + rr;
+      const E v = (row < r1 && cc < n) ? X[(int64_t)cc * ldx + row] : LowT<PREC>::from_float(0.f);
+      if (PREC == TSQR_LOWP_FP32) lds[rr * LDA + cc] = v;
+      else lds[cc * LDA + rr] = v;
+    }
+    __syncthreads();
+    if (PREC == TSQR_LOWP_FP32) {
+#pragma unroll 4
+      for (int kk = 0; kk < KC / 4; ++kk) {
+        float op[JT];
+#pragma unroll
+        for (int c = 0; c < JT; ++c) op[c] = (float)lds[(4 * kk + q) * LDA + 16 * c + c16];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          constexpr int dummy = 0;
+          (void)dummy;
+          int b = 0;
+          while ((b + 1) * (b + 2) / 2 <= t) ++b;
+          const int a = t - b * (b + 1) / 2;
+          if (t % NW == wave) acc[t / NW] = mfma_f32(op[a], op[b], acc[t / NW]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int g = 0; g < KC / 32; ++g) {
+        v8bf op[JT];
+#pragma unroll
+        for (int c = 0; c < JT; ++c)
+          op[c] = *reinterpret_cast<const v8bf*>(&lds[(16 * c + c16) * LDA + 32 * g + 8 * q]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          int b = 0;
+          while ((b + 1) * (b + 2) / 2 <= t) ++b;
+          const int a = t - b * (b + 1) / 2;
+          if (t % NW == wave) acc[t / NW] = mfma_bf16(op[a], op[b], acc[t / NW]);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc64[u][r] += (double)acc[u][r];
+      acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+  }
+  double* dst = part + (size_t)blockIdx.x * ntiles * 256;
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+    if (t % NW == wave && t < ntiles)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dst[(size_t)t * 256 + lowp_to_f64_tile_index(lane, r)] = acc64[t / NW][r];
+}
+
+// ================================================================== launchers ====
+static int jt_pow2(int n) {
+  int jt = 1;
+  while (jt < (n + 15) / 16) jt <<= 1;
+  return jt;
+}
+
+size_t lowp_elem_bytes(int prec) { return prec == TSQR_LOWP_FP32 ? 4 : 2; }
+
+size_t rinv_lowp_bytes(int prec, int n) {
+  const int jt = jt_pow2(n);
+  return (prec == TSQR_LOWP_FP32 ? rinv_elems<TSQR_LOWP_FP32>(jt) * 4
+                                 : rinv_elems<TSQR_LOWP_BF16>(jt) * 2);
+}
+
+template <int PREC, int IT, int JT, int NW>
+static hipError_t sketch_lowp_t(const SketchPlan& p, int64_t m, int n, const double* A,
+                                int64_t lda, uint64_t seed, double* part, hipStream_t st) {
+  dim3 grid(p.kblocks, p.igroups, p.jgroups);
+  hipLaunchKernelGGL((k_sketch_lowp<PREC, IT, JT, NW>), grid, dim3(NW * 64), 0, st, m, n, A, lda,
+                     (uint32_t)seed, (uint32_t)(seed >> 32), p.rows_per_block, p.it_total,
+                     p.jt_total, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_sketch_lowp(int prec, const SketchPlan& p, int64_t m, int n, const double* A,
+                              int64_t lda, uint64_t seed, double* part, hipStream_t st) {
+#define TSQR_SKL(PR, IT_, JT_, NW_)                                                           \
+  if (prec == PR && p.IT == IT_ && p.JT == JT_ && p.NW == NW_)                                \
+    return sketch_lowp_t<PR, IT_, JT_, NW_>(p, m, n, A, lda, seed, part, st);
+#define TSQR_SKL_ALL(PR)                                                                      \
+  TSQR_SKL(PR, 1, 1, 4) TSQR_SKL(PR, 1, 2, 4) TSQR_SKL(PR, 1, 4, 4) TSQR_SKL(PR, 1, 8, 4)     \
+  TSQR_SKL(PR, 1, 1, 8) TSQR_SKL(PR, 1, 2, 8) TSQR_SKL(PR, 1, 4, 8) TSQR_SKL(PR, 1, 8, 8)     \
+  TSQR_SKL(PR, 2, 8, 4) TSQR_SKL(PR, 2, 8, 8) TSQR_SKL(PR, 2, 4, 8) TSQR_SKL(PR, 2, 4, 4)     \
+  TSQR_SKL(PR, 2, 2, 8) TSQR_SKL(PR, 2, 1, 8) TSQR_SKL(PR, 2, 2, 4) TSQR_SKL(PR, 2, 1, 4)
+  TSQR_SKL_ALL(TSQR_LOWP_FP32)
+  TSQR_SKL_ALL(TSQR_LOWP_BF16)
+#undef TSQR_SKL_ALL
+#undef TSQR_SKL
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_rinv_prep(int prec, int n, const double* Rinv, int64_t ldr, void* out,
+                            hipStream_t st) {
+  const int jt = jt_pow2(n);
+  if (jt > 16) return hipErrorInvalidValue;
+  const size_t total = prec == TSQR_LOWP_FP32 ? rinv_elems<TSQR_LOWP_FP32>(jt)
+                                              : rinv_elems<TSQR_LOWP_BF16>(jt);
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 2048) blocks = 2048;
+  if (prec == TSQR_LOWP_FP32)
+    hipLaunchKernelGGL(k_rinv_prep<TSQR_LOWP_FP32>, dim3(blocks), dim3(256), 0, st, n, jt, Rinv,
+                       ldr, (float*)out);
+  else
+    hipLaunchKernelGGL(k_rinv_prep<TSQR_LOWP_BF16>, dim3(blocks), dim3(256), 0, st, n, jt, Rinv,
+                       ldr, (__bf16*)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_rinv_lowp(int prec, int64_t m, int n, const double* Y, int64_t ldy,
+                                  const void* Ri, void* X, int64_t ldx, hipStream_t st) {
+  const int jt = jt_pow2(n);
+  const int64_t ntiles = (m + 15) / 16;
+  int64_t blocks = (ntiles + 3) / 4;
+  const int64_t cap = (int64_t)device_cu_count() * 4;
+  if (blocks > cap) blocks = cap;
+  dim3 grid((unsigned)blocks), block(256);
+#define TSQR_APL(PR, J)                                                                        \
+  if (prec == PR && jt == J) {                                                                 \
+    typedef typename LowT<PR>::E E;                                                            \
+    const size_t sh = rinv_elems<PR>(J) * sizeof(E);                                           \
+    hipLaunchKernelGGL((k_apply_rinv_lowp<PR, J>), grid, block, sh, st, m, n, Y, ldy,           \
+                       (const E*)Ri, (E*)X, ldx);                                              \
+    return hipGetLastError();                                                                  \
+  }
+  TSQR_APL(TSQR_LOWP_FP32, 1) TSQR_APL(TSQR_LOWP_FP32, 2) TSQR_APL(TSQR_LOWP_FP32, 4)
+  TSQR_APL(TSQR_LOWP_FP32, 8) TSQR_APL(TSQR_LOWP_FP32, 16)
+  TSQR_APL(TSQR_LOWP_BF16, 1) TSQR_APL(TSQR_LOWP_BF16, 2) TSQR_APL(TSQR_LOWP_BF16, 4)
+  TSQR_APL(TSQR_LOWP_BF16, 8) TSQR_APL(TSQR_LOWP_BF16, 16)
+#undef TSQR_APL
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gram_lowp(int prec, const GramPlan& p, int64_t m, int n, const void* X,
+                            int64_t ldx, double* part, hipStream_t st) {
+  dim3 grid(p.kblocks);
+#define TSQR_GRL(PR, J, NW_)                                                                  \
+  if (prec == PR && p.jt_total <= J) {                                                        \
+    typedef typename LowT<PR>::E E;                                                           \
+    hipLaunchKernelGGL((k_gram_lowp<PR, J, NW_>), grid, dim3(NW_ * 64), 0, st, m, n,           \
+                       (const E*)X, ldx, p.rows_per_block, p.ntiles, part);                   \
+    return hipGetLastError();                                                                 \
+  }
+  TSQR_GRL(TSQR_LOWP_FP32, 1, 4) TSQR_GRL(TSQR_LOWP_FP32, 2, 4) TSQR_GRL(TSQR_LOWP_FP32, 4, 4)
+  TSQR_GRL(TSQR_LOWP_FP32, 8, 4) TSQR_GRL(TSQR_LOWP_FP32, 16, 8)
+  TSQR_GRL(TSQR_LOWP_BF16, 1, 4) TSQR_GRL(TSQR_LOWP_BF16, 2, 4) TSQR_GRL(TSQR_LOWP_BF16, 4, 4)
+  TSQR_GRL(TSQR_LOWP_BF16, 8, 4) TSQR_GRL(TSQR_LOWP_BF16, 16, 8)
+#undef TSQR_GRL
+  return hipErrorInvalidValue;
+}
+
+}  // namespace tsqr

@@ -427,12 +427,14 @@ __global__ __launch_bounds__(kSmallThreads) void k_getrf_glb(int s, int n,
 // ================================================================== Cholesky =========
 // Right-looking Cholesky on the full symmetric matrix (both triangles kept current), so
 // that the owner of column k holds row k of R as its column: R(k, i) = W(i, k)/r_kk.
-// Reads only the upper triangle of W (the lower one is mirrored on load).
+// Reads only the upper triangle of W (the lower one is mirrored on load); `shift` is
+// added to the diagonal (shifted CholeskyQR; 0 for the plain factorization).
 template <int RPL, int CPW>
 __global__ __launch_bounds__(kSmallThreads) void k_potrf_reg(int n, const double* __restrict__ W,
                                                              int64_t ldw, double* __restrict__ R,
                                                              int64_t ldr, int stage,
-                                                             int* __restrict__ info) {
+                                                             int* __restrict__ info,
+                                                             double shift) {
   __shared__ double rowk[2][64 * RPL];
   __shared__ int fail_sh;
   const int lane = lane_id(), wave = wave_id();
@@ -444,6 +446,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_potrf_reg(int n, const double
       const int c = wave + kSmallWaves * qc, i = lane + 64 * r;
       double v = 0.0;
       if (c < n && i < n) v = (i <= c) ? W[(int64_t)c * ldw + i] : W[(int64_t)i * ldw + c];
+      if (c == i) v += shift;
       col[qc][r] = v;
     }
   if (threadIdx.x == 0) fail_sh = -1;
@@ -492,7 +495,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_potrf_glb(int n, const double
                                                              int64_t ldw, double* __restrict__ R,
                                                              int64_t ldr, int stage,
                                                              int* __restrict__ info,
-                                                             double* __restrict__ Wk) {
+                                                             double* __restrict__ Wk,
+                                                             double shift) {
   extern __shared__ double sm[];
   double* rk0 = sm;
   double* rk1 = sm + n;
@@ -500,7 +504,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_potrf_glb(int n, const double
   const int lane = lane_id(), wave = wave_id();
   for (int c = wave; c < n; c += kSmallWaves)
     for (int i = lane; i < n; i += 64)
-      Wk[(int64_t)c * n + i] = (i <= c) ? W[(int64_t)c * ldw + i] : W[(int64_t)i * ldw + c];
+      Wk[(int64_t)c * n + i] =
+          ((i <= c) ? W[(int64_t)c * ldw + i] : W[(int64_t)i * ldw + c]) + (i == c ? shift : 0.0);
   if (threadIdx.x == 0) fail_sh = -1;
   __syncthreads();
   for (int k = 0; k < n; ++k) {
@@ -575,6 +580,79 @@ __global__ void k_poison(const int* __restrict__ info, int64_t m, int n, double*
 
 __global__ void k_set_int(int* p, int v) { *p = v; }
 
+// I (n x n, ld n)
+__global__ void k_identity(int n, double* __restrict__ Y) {
+  const int64_t total = (int64_t)n * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x)
+    Y[e] = (e % n == e / n) ? 1.0 : 0.0;
+}
+
+// C = *flag ? B : A B for upper n x n A, B (the mixed-precision preconditioner R01 falls
+// back to R0 when the Cholesky factor of the low-precision Gram matrix broke down).
+__global__ __launch_bounds__(256) void k_trmm_or_copy(const int* __restrict__ flag, int n,
+                                                      const double* __restrict__ A, int64_t lda,
+                                                      const double* __restrict__ B, int64_t ldb,
+                                                      double* __restrict__ C, int64_t ldc) {
+  __shared__ double as[16][17], bs[16][17];
+  const bool copy = *flag != 0;
+  const int i0 = 16 * blockIdx.y, j0 = 16 * blockIdx.x;
+  const int ti = threadIdx.x % 16, tj = threadIdx.x / 16;
+  const int i = i0 + ti, j = j0 + tj;
+  double acc = 0.0;
+  if (copy) {
+    if (i < n && j < n) acc = (i <= j) ? B[(int64_t)j * ldb + i] : 0.0;
+  } else if (i0 <= j0 + 15) {
+    for (int k0 = i0; k0 < j0 + 16 && k0 < n; k0 += 16) {
+      const int ka = k0 + tj, kb = k0 + ti;
+      as[ti][tj] = (i < n && ka < n && ka >= i) ? A[(int64_t)ka * lda + i] : 0.0;
+      bs[ti][tj] = (kb < n && j < n && kb <= j) ? B[(int64_t)j * ldb + kb] : 0.0;
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc += as[ti][k] * bs[k][tj];
+      __syncthreads();
+    }
+  }
+  if (i < n && j < n) C[(int64_t)j * ldc + i] = (i <= j) ? acc : 0.0;
+}
+
+// *need = 1 when the preconditioned matrix Q1 with Gram W = Q1^T Q1 is not close enough
+// to orthonormal for one CholeskyQR pass (||W - I||_F > thresh), or when `lp_info` or
+// `info` report a breakdown.  One workgroup.
+__global__ __launch_bounds__(256) void k_pass_decide(int n, const double* __restrict__ W,
+                                                     int64_t ldw, const int* __restrict__ lp_info,
+                                                     const int* __restrict__ info, double thresh,
+                                                     int* __restrict__ need,
+                                                     double* __restrict__ dev_out) {
+  __shared__ double red[256], red2[256];
+  double acc = 0.0, acc2 = 0.0;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e % n, j = e / n;
+    const double w = W[(int64_t)j * ldw + i];
+    const double d = w - (i == j ? 1.0 : 0.0);
+    acc += d * d;
+    acc2 += w * w;
+  }
+  red[threadIdx.x] = acc;
+  red2[threadIdx.x] = acc2;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      red[threadIdx.x] += red[threadIdx.x + s];
+      red2[threadIdx.x] += red2[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double dev = sqrt(red[0]);
+    *need = ((lp_info && *lp_info) || (info && *info) || !(dev <= thresh)) ? 1 : 0;
+    if (dev_out) {
+      dev_out[0] = dev;            // ||W - I||_F
+      dev_out[1] = sqrt(red2[0]);  // ||W||_F
+    }
+  }
+}
+
 // ================================================================== launchers ========
 static int pow2_at_least(int x) {
   int p = 1;
@@ -614,20 +692,21 @@ hipError_t launch_sketch_factor(int variant, int s, int n, const double* B, int6
 }
 
 hipError_t launch_potrf(int n, const double* W, int64_t ldw, double* R, int64_t ldr, int stage,
-                        int* info, double* scratch, hipStream_t st) {
+                        int* info, double* scratch, hipStream_t st, double shift) {
   const int rpl = pow2_at_least((n + 63) / 64), cpw = pow2_at_least((n + 15) / 16);
   dim3 grid(1), block(kSmallThreads);
 #define TSQR_POTRF(RPL_, CPW_)                                                                 \
   if (rpl == RPL_ && cpw == CPW_) {                                                            \
     hipLaunchKernelGGL((k_potrf_reg<RPL_, CPW_>), grid, block, 0, st, n, W, ldw, R, ldr, stage, \
-                       info);                                                                  \
+                       info, shift);                                                           \
     return hipGetLastError();                                                                  \
   }
   TSQR_POTRF(1, 1) TSQR_POTRF(1, 2) TSQR_POTRF(1, 4) TSQR_POTRF(2, 8)
 #undef TSQR_POTRF
   if (n > kMaxS) return hipErrorInvalidValue;
   const size_t sh = (size_t)(2 * n) * sizeof(double);
-  hipLaunchKernelGGL(k_potrf_glb, grid, block, sh, st, n, W, ldw, R, ldr, stage, info, scratch);
+  hipLaunchKernelGGL(k_potrf_glb, grid, block, sh, st, n, W, ldw, R, ldr, stage, info, scratch,
+                     shift);
   return hipGetLastError();
 }
 
@@ -646,6 +725,30 @@ hipError_t launch_poison(const int* info, int64_t m, int n, double* Q, int64_t l
 
 hipError_t launch_set_int(int* p, int v, hipStream_t st) {
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_identity(int n, double* Y, hipStream_t st) {
+  int blocks = (n * n + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_identity, dim3(blocks), dim3(256), 0, st, n, Y);
+  return hipGetLastError();
+}
+
+hipError_t launch_trmm_or_copy(const int* flag, int n, const double* A, int64_t lda,
+                               const double* B, int64_t ldb, double* C, int64_t ldc,
+                               hipStream_t st) {
+  const int nb = (n + 15) / 16;
+  hipLaunchKernelGGL(k_trmm_or_copy, dim3(nb, nb), dim3(256), 0, st, flag, n, A, lda, B, ldb, C,
+                     ldc);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_decide(int n, const double* W, int64_t ldw, const int* lp_info,
+                              const int* info, double thresh, int* need, double* dev_out,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_pass_decide, dim3(1), dim3(256), 0, st, n, W, ldw, lp_info, info, thresh,
+                     need, dev_out);
   return hipGetLastError();
 }
 

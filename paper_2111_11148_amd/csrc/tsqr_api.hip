@@ -220,6 +220,136 @@ int plain_form(int variant, int64_t m, int64_t n, const double* A, int64_t lda, 
   return rc;
 }
 
+// ---- mixed precision ---------------------------------------------------------------
+// Extra workspace after the FP64 layout: A1 in the input type, R0^{-1} (FP64 and rounded),
+// identity, R01 = R1 R0, two more n x n factors, the low-precision breakdown word, the
+// pass decision and the deviation ||W - I||_F.
+struct MixedLayout {
+  Layout base;
+  size_t A1, Rinv, Ri_lp, Id, R01, R3, Rt, lp_info, need, dev, total;
+};
+
+MixedLayout make_mixed_layout(int64_t m, int64_t n, int64_t s, int lowp) {
+  MixedLayout L{};
+  L.base = make_layout(m, n, s);
+  const size_t nn = (size_t)n * n * sizeof(double);
+  size_t off = L.base.total;
+  L.A1 = off; off += align256((size_t)m * n * lowp_elem_bytes(lowp));
+  L.Rinv = off; off += align256(nn);
+  L.Ri_lp = off; off += align256(rinv_lowp_bytes(lowp, (int)n));
+  L.Id = off; off += align256(nn);
+  L.R01 = off; off += align256(nn);
+  L.R3 = off; off += align256(nn);
+  L.Rt = off; off += align256(nn);
+  L.lp_info = off; off += 256;
+  L.need = off; off += 256;
+  L.dev = off; off += 256;
+  L.total = off;
+  return L;
+}
+
+// Deviation of Q1^T Q1 from I above which another FP64 CholeskyQR pass is run in the
+// automatic mode: ||W - I||_F <= 1/2 gives cond(W) <= 3, i.e. cond(Q1) <= 1.8.
+constexpr double kPassThresh = 0.5;
+
+int run_chain_mixed(int variant, int lowp, int64_t m, int64_t n, const double* A, int64_t lda,
+                    int64_t s, uint64_t seed, int fp64_passes, double* Q, int64_t ldq,
+                    double* R, int64_t ldr, void* work, int* d_info, int* passes_out,
+                    hipStream_t st) {
+  const MixedLayout M = make_mixed_layout(m, n, s, lowp);
+  const Layout& L = M.base;
+  char* base = (char*)work;
+  int* info = d_info ? d_info : (int*)(base + L.info);
+  double* B = (double*)(base + L.B);
+  double* R0 = (double*)(base + L.R0);
+  double* R1 = (double*)(base + L.R1);
+  double* R2 = (double*)(base + L.R2);
+  double* Racc = (double*)(base + L.R10);
+  double* W = (double*)(base + L.W);
+  double* fac = (double*)(base + L.fac);
+  double* Tt = (double*)(base + L.Tt);
+  double* part = (double*)(base + L.part);
+  void* A1 = base + M.A1;
+  double* Rinv = (double*)(base + M.Rinv);
+  void* Ri_lp = base + M.Ri_lp;
+  double* Id = (double*)(base + M.Id);
+  double* R01 = (double*)(base + M.R01);
+  double* R3 = (double*)(base + M.R3);
+  double* Rt = (double*)(base + M.Rt);
+  int* lp_info = (int*)(base + M.lp_info);
+  int* need = (int*)(base + M.need);
+  double* dev = (double*)(base + M.dev);
+  const int ni = (int)n, si = (int)s;
+  const int max_passes = fp64_passes > 0 ? fp64_passes : 3;
+
+  TSQR_CHECK(launch_set_int(info, 0, st));
+  TSQR_CHECK(launch_set_int(lp_info, 0, st));
+  // low-precision sketch, FP64 factor of the sketch, FP64 inverse
+  TSQR_PHASE("sketch_lowp", launch_sketch_lowp(lowp, L.sp, m, ni, A, lda, seed, part, st));
+  TSQR_PHASE("sketch_reduce",
+             launch_sketch_reduce(L.sp, si, ni, part, 1.0 / sqrt((double)s), B, s, st));
+  TSQR_PHASE(variant == 1 ? "sketch_lu" : "sketch_qr",
+             launch_sketch_factor(variant, si, ni, B, s, R0, n, info, fac, st));
+  TSQR_CHECK(launch_identity(ni, Id, st));
+  TSQR_PHASE("trtri_r0", launch_trsm(n, ni, Id, n, R0, n, Rinv, n, Tt, st));
+  TSQR_PHASE("rinv_round", launch_rinv_prep(lowp, ni, Rinv, n, Ri_lp, st));
+  // low-precision preconditioner apply and first Gram matrix
+  TSQR_PHASE("apply_lowp", launch_apply_rinv_lowp(lowp, m, ni, A, lda, Ri_lp, A1, m, st));
+  TSQR_PHASE("gram_lowp", launch_gram_lowp(lowp, L.gp, m, ni, A1, m, part, st));
+  TSQR_PHASE("gram1_reduce", launch_gram_reduce(L.gp, ni, part, W, n, st));
+  TSQR_PHASE("potrf1", launch_potrf(ni, W, n, R1, n, 2, lp_info, fac, st));
+  // R01 = R1 R0, or R0 alone when the low-precision Cholesky broke down
+  TSQR_PHASE("trmm", launch_trmm_or_copy(lp_info, ni, R1, n, R0, n, R01, n, st));
+  // FP64 CholeskyQR passes on A R01^{-1}
+  TSQR_PHASE("trsm_r01", launch_trsm(m, ni, A, lda, R01, n, Q, ldq, Tt, st));
+  // FP64 CholeskyQR passes.  Fixed mode: exactly fp64_passes passes, no waiting.
+  // Automatic mode (fp64_passes == 0): the host reads, per pass, the deviation
+  // ||W - I||_F and ||W||_F of the pass's Gram matrix and the Cholesky status; a
+  // breakdown is retried once with the shift 11 (m n + n (n + 1)) u ||W||_F on the
+  // diagonal (the shifted CholeskyQR of the paper's Section 2.1), and another pass
+  // follows while the pass input deviated by more than 1/2 or needed the shift.
+  double* Rcur = R01;  // R accumulated so far
+  int passes = 0;
+  bool more = true;
+  for (int pass = 0; pass < max_passes && more; ++pass) {
+    double* Rk = (pass == 0) ? R2 : R3;
+    double* Rnext = (Rcur == Racc) ? Rt : Racc;
+    const int stage = 3 + (pass > 0);
+    TSQR_PHASE("gram", launch_gram(L.gp, m, ni, Q, ldq, part, st));
+    TSQR_PHASE("gram_reduce", launch_gram_reduce(L.gp, ni, part, W, n, st));
+    if (fp64_passes == 0) {
+      double hdev[2] = {0.0, 0.0};
+      int hpi = 0;
+      TSQR_CHECK(launch_set_int(need + 1, 0, st));
+      TSQR_CHECK(launch_pass_decide(ni, W, n, nullptr, nullptr, kPassThresh, need, dev, st));
+      TSQR_PHASE("potrf", launch_potrf(ni, W, n, Rk, n, stage, need + 1, fac, st));
+      TSQR_CHECK(hipMemcpyAsync(hdev, dev, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      TSQR_CHECK(hipMemcpyAsync(&hpi, need + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+      TSQR_CHECK(hipStreamSynchronize(st));
+      bool shifted = false;
+      if (hpi != 0) {
+        const double u = 0x1p-53;
+        const double shift =
+            11.0 * ((double)m * (double)n + (double)n * (double)(n + 1)) * u * hdev[1];
+        TSQR_PHASE("potrf_shifted", launch_potrf(ni, W, n, Rk, n, stage, info, fac, st, shift));
+        shifted = true;
+      }
+      more = shifted || !(hdev[0] <= kPassThresh);
+    } else {
+      TSQR_PHASE("potrf", launch_potrf(ni, W, n, Rk, n, stage, info, fac, st));
+    }
+    TSQR_PHASE("trsm", launch_trsm(m, ni, Q, ldq, Rk, n, Q, ldq, Tt, st));
+    TSQR_PHASE("trmm", launch_trmm_upper(ni, Rk, n, Rcur, n, Rnext, n, st));
+    Rcur = Rnext;
+    ++passes;
+  }
+  if (R) TSQR_CHECK(hipMemcpy2DAsync(R, ldr * sizeof(double), Rcur, n * sizeof(double),
+                                     n * sizeof(double), n, hipMemcpyDeviceToDevice, st));
+  TSQR_PHASE("poison", launch_poison(info, m, ni, Q, ldq, R, ldr, st));
+  if (passes_out) *passes_out = passes;
+  return TSQR_OK;
+}
+
 }  // namespace
 }  // namespace tsqr
 
@@ -302,8 +432,108 @@ int tsqr_rxr_cholqr_ws(int variant, int64_t m, int64_t n, const double* A, int64
   if (!work) return -13;
   if (n > kMaxN) return TSQR_ERR_UNSUPPORTED;
   if (work_bytes < make_layout(m, n, sketch_rows).total) return TSQR_ERR_WORKSPACE;
-  return run_chain(variant, m, n, A, lda, sketch_rows, seed, extra_pass, Q, ldq, R, ldr, work,
+  return run_chain(variant, m, n, A, lda, sketch_rows, seed, extra_pass != 0, Q, ldq, R, ldr, work,
                    d_info, (hipStream_t)stream);
+}
+
+size_t tsqr_mixed_workspace_bytes(int64_t m, int64_t n, int64_t sketch_rows, int lowp) {
+  if (n < 1 || m < n || sketch_rows < n || sketch_rows > kMaxSketchRows) return 0;
+  if (lowp != TSQR_LOWP_FP32 && lowp != TSQR_LOWP_BF16) return 0;
+  return make_mixed_layout(m, n, sketch_rows, lowp).total;
+}
+
+int tsqr_rxr_cholqr_mixed_ws(int variant, int lowp, int64_t m, int64_t n, const double* A,
+                             int64_t lda, int64_t sketch_rows, uint64_t seed, int fp64_passes,
+                             double* Q, int64_t ldq, double* R, int64_t ldr, void* work,
+                             size_t work_bytes, int* d_info, int* passes_out, void* stream) {
+  if (variant != TSQR_VARIANT_RQR && variant != TSQR_VARIANT_RLU) return -1;
+  if (lowp != TSQR_LOWP_FP32 && lowp != TSQR_LOWP_BF16) return -2;
+  const ArgErr e = validate(m, n, A, lda, sketch_rows, Q, ldq, R, ldr);
+  switch (e) {
+    case E_OK: break;
+    case E_M: return -3;
+    case E_N: return -4;
+    case E_A: return -5;
+    case E_LDA: return -6;
+    case E_S: return -7;
+    case E_Q: return -10;
+    case E_LDQ: return -11;
+    case E_R: return -12;
+    case E_LDR: return -13;
+  }
+  if (fp64_passes < 0 || fp64_passes > 3) return -9;
+  if (!work) return -14;
+  if (n > kMaxN) return TSQR_ERR_UNSUPPORTED;
+  if (work_bytes < make_mixed_layout(m, n, sketch_rows, lowp).total) return TSQR_ERR_WORKSPACE;
+  return run_chain_mixed(variant, lowp, m, n, A, lda, sketch_rows, seed, fp64_passes, Q, ldq, R,
+                         ldr, work, d_info, passes_out, (hipStream_t)stream);
+}
+
+int tsqr_sketch_lowp(int lowp, int64_t m, int64_t n, const double* A, int64_t lda, int64_t s,
+                     uint64_t seed, double* B, int64_t ldb, void* work, size_t work_bytes,
+                     void* stream) {
+  if (lowp != TSQR_LOWP_FP32 && lowp != TSQR_LOWP_BF16) return -1;
+  if (m < 1) return -2;
+  if (n < 1 || n > kMaxN) return -3;
+  if (!A) return -4;
+  if (lda < m) return -5;
+  if (s < 1 || s > kMaxSketchRows) return -6;
+  if (!B) return -8;
+  if (ldb < s) return -9;
+  if (!work) return -10;
+  const SketchPlan p = plan_sketch(m, (int)n, (int)s);
+  if (work_bytes < p.part_doubles * sizeof(double)) return TSQR_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  if (launch_sketch_lowp(lowp, p, m, (int)n, A, lda, seed, (double*)work, st) != hipSuccess ||
+      launch_sketch_reduce(p, (int)s, (int)n, (double*)work, 1.0 / sqrt((double)s), B, ldb, st) !=
+          hipSuccess)
+    return TSQR_ERR_HIP;
+  return TSQR_OK;
+}
+
+size_t tsqr_rinv_lowp_bytes(int64_t n, int lowp) {
+  if (n < 1 || n > kMaxN || (lowp != TSQR_LOWP_FP32 && lowp != TSQR_LOWP_BF16)) return 0;
+  return rinv_lowp_bytes(lowp, (int)n);
+}
+
+int tsqr_apply_rinv_lowp(int lowp, int64_t m, int64_t n, const double* Y, int64_t ldy,
+                         const double* Rinv, int64_t ldr, void* X, int64_t ldx, void* work,
+                         size_t work_bytes, void* stream) {
+  if (lowp != TSQR_LOWP_FP32 && lowp != TSQR_LOWP_BF16) return -1;
+  if (m < 1) return -2;
+  if (n < 1 || n > kMaxN) return -3;
+  if (!Y) return -4;
+  if (ldy < m) return -5;
+  if (!Rinv) return -6;
+  if (ldr < n) return -7;
+  if (!X) return -8;
+  if (ldx < m) return -9;
+  if (!work) return -10;
+  if (work_bytes < rinv_lowp_bytes(lowp, (int)n)) return TSQR_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  if (launch_rinv_prep(lowp, (int)n, Rinv, ldr, work, st) != hipSuccess ||
+      launch_apply_rinv_lowp(lowp, m, (int)n, Y, ldy, work, X, ldx, st) != hipSuccess)
+    return TSQR_ERR_HIP;
+  return TSQR_OK;
+}
+
+int tsqr_gram_lowp(int lowp, int64_t m, int64_t n, const void* X, int64_t ldx, double* W,
+                   int64_t ldw, void* work, size_t work_bytes, void* stream) {
+  if (lowp != TSQR_LOWP_FP32 && lowp != TSQR_LOWP_BF16) return -1;
+  if (m < 1) return -2;
+  if (n < 1 || n > kMaxN) return -3;
+  if (!X) return -4;
+  if (ldx < m) return -5;
+  if (!W) return -6;
+  if (ldw < n) return -7;
+  if (!work) return -8;
+  const GramPlan p = plan_gram(m, (int)n);
+  if (work_bytes < p.part_doubles * sizeof(double)) return TSQR_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  if (launch_gram_lowp(lowp, p, m, (int)n, X, ldx, (double*)work, st) != hipSuccess ||
+      launch_gram_reduce(p, (int)n, (double*)work, W, ldw, st) != hipSuccess)
+    return TSQR_ERR_HIP;
+  return TSQR_OK;
 }
 
 size_t tsqr_sketch_workspace_bytes(int64_t m, int64_t n, int64_t s) {

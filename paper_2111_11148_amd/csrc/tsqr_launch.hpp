@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/tsqr.h"
+
 namespace tsqr {
 
 // ---- tiled partial-sum geometry -----------------------------------------------------
@@ -52,7 +54,7 @@ hipError_t launch_sketch_factor(int variant, int s, int n, const double* B, int6
                                 hipStream_t st);
 // Cholesky of the symmetric W (both triangles stored) into upper R; info stage
 hipError_t launch_potrf(int n, const double* W, int64_t ldw, double* R, int64_t ldr, int stage,
-                        int* info, double* scratch, hipStream_t st);
+                        int* info, double* scratch, hipStream_t st, double shift = 0.0);
 // C = A B for upper-triangular n x n matrices
 hipError_t launch_trmm_upper(int n, const double* A, int64_t lda, const double* B, int64_t ldb,
                              double* C, int64_t ldc, hipStream_t st);
@@ -60,6 +62,27 @@ hipError_t launch_trmm_upper(int n, const double* A, int64_t lda, const double* 
 hipError_t launch_poison(const int* info, int64_t m, int n, double* Q, int64_t ldq, double* R,
                          int64_t ldr, hipStream_t st);
 hipError_t launch_set_int(int* p, int v, hipStream_t st);
+hipError_t launch_identity(int n, double* Y, hipStream_t st);
+// C = *flag ? B : A B (upper n x n)
+hipError_t launch_trmm_or_copy(const int* flag, int n, const double* A, int64_t lda,
+                               const double* B, int64_t ldb, double* C, int64_t ldc,
+                               hipStream_t st);
+// *need = breakdown in lp_info/info or ||W - I||_F > thresh (one workgroup)
+hipError_t launch_pass_decide(int n, const double* W, int64_t ldw, const int* lp_info,
+                              const int* info, double thresh, int* need, double* dev_out,
+                              hipStream_t st);
+
+// ---- low-precision phases (precision codes TSQR_LOWP_FP32 / TSQR_LOWP_BF16) -------------
+size_t lowp_elem_bytes(int prec);
+size_t rinv_lowp_bytes(int prec, int n);
+hipError_t launch_sketch_lowp(int prec, const SketchPlan& p, int64_t m, int n, const double* A,
+                              int64_t lda, uint64_t seed, double* part, hipStream_t st);
+hipError_t launch_rinv_prep(int prec, int n, const double* Rinv, int64_t ldr, void* out,
+                            hipStream_t st);
+hipError_t launch_apply_rinv_lowp(int prec, int64_t m, int n, const double* Y, int64_t ldy,
+                                  const void* Ri, void* X, int64_t ldx, hipStream_t st);
+hipError_t launch_gram_lowp(int prec, const GramPlan& p, int64_t m, int n, const void* X,
+                            int64_t ldx, double* part, hipStream_t st);
 
 // ---- test / debug kernels -------------------------------------------------------------
 hipError_t launch_philox_words(int64_t count, const uint32_t* ctr, uint64_t seed, uint32_t* out,

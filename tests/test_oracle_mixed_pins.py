@@ -1,0 +1,200 @@
+"""Pins of the oracle's mixed-precision routines against things other than themselves.
+
+The low-precision steps are pinned by: torch's own FP32 -> BF16 conversion (round to
+nearest even), exact integer arithmetic (inputs that every type represents, so the rounded
+and the exact results coincide), reduction to the pinned FP64 routines when rounding is
+the identity, and LAPACK's triangular inverse.  The mixed driver is pinned by the
+invariants of a QR factorization and by LAPACK's R factor within the perturbation bound.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+import torch
+
+import oracle
+from inputs import gen_matrix
+
+FP32, BF16 = oracle.FP32, oracle.BF16
+U64 = 2.0 ** -53
+
+
+def F(x):
+    return np.asfortranarray(x, dtype=np.float64)
+
+
+def torch_round(x, prec):
+    t = torch.as_tensor(np.asarray(x, dtype=np.float64)).to(torch.float32)
+    if prec == BF16:
+        t = t.to(torch.bfloat16).to(torch.float32)
+    return t.to(torch.float64).numpy()
+
+
+def signfix(Rm):
+    d = np.sign(np.diag(Rm))
+    d[d == 0] = 1
+    return d[:, None] * Rm
+
+
+# ------------------------------------------------------------------------- rounding --
+def test_round_bf16_matches_torch():
+    rng = np.random.default_rng(5)
+    xs = list(rng.standard_normal(20000) * 10.0 ** rng.integers(-30, 30, 20000))
+    # ties at the BF16 rounding point: 1 + 2^-8 (tie, even down), 1 + 3*2^-8 (tie, up)
+    xs += [1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -(1.0 + 2.0 ** -8), 1.0 + 2.0 ** -8 + 2.0 ** -20,
+           0.0, -0.0, 1e-40, -3e-39, 3.3e38, 1e39, float("inf"), float("-inf")]
+    for x in xs:
+        got = oracle.round_bf16(x)
+        exp = float(torch_round(x, BF16))
+        assert got == exp or (math.isnan(got) and math.isnan(exp)), (x, got, exp)
+    assert math.isnan(oracle.round_bf16(float("nan")))
+
+
+def test_round_fp32_matches_numpy():
+    rng = np.random.default_rng(6)
+    with np.errstate(over="ignore"):
+        for x in rng.standard_normal(5000) * 10.0 ** rng.integers(-40, 40, 5000):
+            assert oracle.round_fp32(x) == float(np.float32(x))
+
+
+# ------------------------------------------------------------------------- triangle --
+@pytest.mark.parametrize("n", [1, 7, 33])
+def test_trtri_matches_lapack(n):
+    rng = np.random.default_rng(n)
+    T = np.triu(rng.standard_normal((n, n))) + 4 * np.eye(n)
+    X = oracle.trtri_upper(F(T))
+    exp = scipy.linalg.solve_triangular(T, np.eye(n), lower=False)
+    assert np.array_equal(np.tril(X, -1), np.zeros((n, n)))
+    assert np.abs(X - exp).max() <= 64 * n * U64 * np.abs(exp).max()
+    assert np.abs(T @ X - np.eye(n)).max() <= 64 * n * U64 * np.abs(T).max() * np.abs(X).max()
+
+
+# ------------------------------------------------------------------------ sketch ----
+def test_sketch_lowp_reduces_to_fp64_sketch_on_representable_input():
+    """With A exactly representable in BF16 and the normals already FP32 numbers, only the
+    rounding of the normals separates the low-precision sketch from the FP64 one."""
+    m, n, s, seed = 300, 5, 16, 11104
+    rng = np.random.default_rng(0)
+    A = F(rng.integers(-128, 128, size=(m, n)) * 2.0 ** -4)  # 8-bit significands
+    Z = oracle.sketch_normals(seed, 0, s, 0, m)
+    B64 = oracle.sketch_apply(A, s, seed)
+    for prec in (FP32, BF16):
+        Bl = oracle.sketch_apply_lowp(prec, A, s, seed)
+        Zr = torch_round(Z, prec)
+        exp = (Zr @ A) / math.sqrt(s)
+        # exact products of the rounded normals, summed in FP64
+        assert np.abs(Bl - exp).max() <= 4 * m * U64 * (np.abs(Zr) @ np.abs(A)).max()
+        # and within the normal rounding of the FP64 sketch
+        dz = (2.0 ** -24 if prec == FP32 else 2.0 ** -8) * np.abs(Z)
+        bound = (dz @ np.abs(A)) / math.sqrt(s) + 4 * m * U64 * np.abs(B64).max()
+        assert np.all(np.abs(Bl - B64) <= bound)
+
+
+def test_sketch_lowp_rounds_the_input():
+    """A column of 1 + 2^-30 rounds to all ones in both types: the low-precision sketch
+    of it equals the sketch of a ones column; a column of 1 + 2^-12 survives FP32 only."""
+    m, s, seed = 257, 8, 3
+    A = F(np.stack([np.full(m, 1 + 2.0 ** -30), np.full(m, 1 + 2.0 ** -12)], axis=1))
+    ones = F(np.ones((m, 1)))
+    for prec in (FP32, BF16):
+        Bl = oracle.sketch_apply_lowp(prec, A, s, seed)
+        Bones = oracle.sketch_apply_lowp(prec, ones, s, seed)
+        assert np.array_equal(Bl[:, :1], Bones)
+        if prec == BF16:
+            assert np.array_equal(Bl[:, 1:], Bones)
+        else:
+            assert np.allclose(Bl[:, 1:], Bones * (1 + 2.0 ** -12), rtol=1e-14, atol=0)
+
+
+# ------------------------------------------------------------------------- apply ----
+def test_apply_rinv_lowp_exact_integers_and_triangularity():
+    rng = np.random.default_rng(1)
+    m, n = 50, 9
+    Y = F(rng.integers(-8, 9, size=(m, n)))
+    Rfull = F(rng.integers(-8, 9, size=(n, n)))  # lower part must be ignored
+    exp = Y @ np.triu(Rfull)
+    for prec in (FP32, BF16):
+        X = oracle.apply_rinv_lowp(prec, Y, Rfull)
+        assert np.array_equal(X, torch_round(exp, prec))
+
+
+def test_apply_rinv_lowp_rounds_operands_and_result():
+    rng = np.random.default_rng(2)
+    m, n = 40, 6
+    Y = F(rng.standard_normal((m, n)))
+    Rv = F(np.triu(rng.standard_normal((n, n))))
+    for prec in (FP32, BF16):
+        exact = torch_round(Y, prec) @ torch_round(Rv, prec)  # few terms: FP64 sum is exact
+        X = oracle.apply_rinv_lowp(prec, Y, Rv)               # to well below the final rounding
+        assert np.array_equal(X, torch_round(exact, prec))
+
+
+# -------------------------------------------------------------------------- gram ----
+def test_gram_lowp_exact_and_rounded():
+    rng = np.random.default_rng(3)
+    X = F(rng.integers(-16, 17, size=(100, 7)))
+    for prec in (FP32, BF16):
+        assert np.array_equal(oracle.gram_lowp(prec, X), X.T @ X)
+    Xr = F(rng.standard_normal((100, 7)))
+    for prec in (FP32, BF16):
+        Xp = torch_round(Xr, prec)
+        W = oracle.gram_lowp(prec, Xr)
+        assert np.array_equal(W, W.T)
+        assert np.abs(W - Xp.T @ Xp).max() <= 4 * 100 * U64 * (np.abs(Xp).T @ np.abs(Xp)).max()
+
+
+# ------------------------------------------------------------------------ driver ----
+@pytest.mark.parametrize("prec", [FP32, BF16])
+@pytest.mark.parametrize("kappa", [1e4, 1e8, 1e12])
+def test_mixed_driver_auto_is_a_qr_factorization(prec, kappa):
+    m, n, s = 2048, 16, 32
+    A = gen_matrix(m, n, kappa, 211104)
+    r = oracle.rxr_cholqr_mixed(A, s, 11104, prec=prec, fp64_passes=0)
+    assert r["info"] == 0
+    assert 1 <= r["passes"] <= 3
+    Q, R = r["Q"], r["R"]
+    assert np.array_equal(np.tril(R, -1), np.zeros((n, n)))
+    assert np.all(np.diag(R) > 0)
+    # FP64 accuracy of a Householder QR, with the same constants as the FP64 method's pins
+    assert oracle.orthogonality(Q) <= 2 * math.sqrt(n) * 64 * U64 * n
+    assert oracle.residual(A, Q, R) <= 64 * U64 * math.sqrt(n)
+    # R is the unique positive-diagonal R factor of A: LAPACK's, to kappa * u
+    Rl = signfix(np.linalg.qr(A, mode="r"))
+    assert np.linalg.norm(R - Rl) / np.linalg.norm(Rl) <= 4 * n * kappa * U64
+
+
+def test_mixed_driver_pass_counts():
+    """A well-conditioned input needs a single FP64 pass in automatic mode; a fixed count
+    is obeyed; BF16 at kappa 1e12 needs more passes than FP32 at kappa 1e4."""
+    A4 = gen_matrix(2048, 16, 1e4, 7)
+    A12 = gen_matrix(2048, 16, 1e12, 7)
+    assert oracle.rxr_cholqr_mixed(A4, 32, 1, prec=FP32, fp64_passes=0)["passes"] == 1
+    for k in (1, 2, 3):
+        assert oracle.rxr_cholqr_mixed(A4, 32, 1, prec=FP32, fp64_passes=k)["passes"] == k
+    assert oracle.rxr_cholqr_mixed(A12, 32, 1, prec=BF16, fp64_passes=0)["passes"] >= 2
+
+
+def test_mixed_driver_low_precision_breakdown_falls_back():
+    """Two columns equal to 1e-9 collapse after rounding to BF16: the low-precision
+    Cholesky breaks down, R0 alone preconditions, and the FP64 passes still give an
+    orthonormal Q."""
+    A = gen_matrix(4096, 32, 1e4, 5)
+    A[:, 5] = A[:, 4] * (1 + 1e-9)
+    r = oracle.rxr_cholqr_mixed(F(A), 64, 7, prec=BF16, fp64_passes=0)
+    assert r["lp_info"] > 0
+    assert r["info"] == 0
+    assert oracle.orthogonality(r["Q"]) <= 1e-13
+
+
+def test_mixed_driver_fixed_single_pass_fails_loudly_or_not_at_all():
+    """With one fixed pass and a far too ill-conditioned input the method either succeeds
+    or reports a breakdown (stage 3) with NaN outputs; never a silent non-orthogonal Q
+    with info 0 beyond the CholeskyQR bound kappa(A1)^2 u."""
+    A = gen_matrix(2048, 16, 1e16, 9)
+    r = oracle.rxr_cholqr_mixed(A, 32, 1, prec=BF16, fp64_passes=1)
+    if r["info"]:
+        assert r["info"] // 1000 == 3
+        assert np.isnan(r["Q"]).all() and np.isnan(r["R"]).all()
+    else:
+        assert np.isfinite(r["Q"]).all()
