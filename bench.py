@@ -9,7 +9,10 @@ outputs are preallocated, so the timed region allocates nothing.
 
 Printed: one JSON line with the throughput (GFLOP/s of the algorithmic flop count), the
 roofline of the dominant kernel (average duration from HIP events recorded on the
-library's stream during the timed steps), and the CPU oracle timed on a bounded sample.
+library's stream during the timed steps), the CPU oracle timed on a bounded sample, and
+the mixed-precision comparison: time to ||Q^T Q - I||_F <= 1e-12 on the mixed256 workload
+(m = 2^20, n = 256, s = 512, kappa in {1e4, 1e8, 1e12}) for FP64 and for the FP32 / BF16
+mixed variant.
 """
 from __future__ import annotations
 
@@ -94,6 +97,118 @@ def gpu_metrics(A, Q, R):
     return float(torch.linalg.matrix_norm(G)), float(torch.sqrt(num) / torch.sqrt(den))
 
 
+def cached_matrix(cache_dir, name, m, n, kappa, seed):
+    """The seeded test matrix, generated on the host (kept under cache_dir if given)."""
+    import numpy as np
+
+    from inputs import gen_matrix
+
+    cache = None
+    if cache_dir:
+        os.makedirs(cache_dir, exist_ok=True)
+        cache = os.path.join(cache_dir, f"A_{name}_{seed}.npy")
+        if os.path.exists(cache):
+            return np.load(cache, mmap_mode="r")
+    t0 = time.perf_counter()
+    A_h = gen_matrix(m, n, kappa, seed)
+    print(f"# generated A ({m}x{n}, kappa={kappa:g}) in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    if cache:
+        np.save(cache, np.asfortranarray(A_h))
+    return A_h
+
+
+def timed(fn, steps: int, warmup: int) -> float:
+    """Average wall time per call in ms, device synchronised on both sides."""
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def phases_of(fn) -> dict:
+    """Per-phase device time (ms) of one call, from the library's HIP events."""
+    import torch
+
+    import paper_2111_11148_amd as tsqr
+
+    torch.cuda.synchronize()
+    tsqr.profile_start()
+    fn()
+    torch.cuda.synchronize()
+    out = {}
+    for name, ms in tsqr.profile_stop():
+        out[name] = round(out.get(name, 0.0) + ms, 4)
+    return out
+
+
+def mixed_comparison(args, kappas):
+    """Time to an orthonormal Q (||Q^T Q - I||_F <= 1e-12) on the mixed256 workload:
+    the FP64 method with one extra pass against the mixed variant with FP32 and with BF16
+    inputs (automatic FP64 passes), same matrix, same GPU, each timed on its own."""
+    import numpy as np
+    import torch
+
+    import paper_2111_11148_amd as tsqr
+    from inputs import WORKLOADS
+
+    wl = WORKLOADS["mixed256"]
+    m, n, s, seed = wl.m, wl.n, wl.s, wl.sketch_seed
+    F = flops(m, n, s, "rqr", True)["total"]
+    Q = tsqr.colmajor(m, n)
+    R = tsqr.colmajor(n, n)
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    work64 = tsqr.alloc_workspace(m, n, s)
+    out = []
+    for kappa in kappas:
+        j = list(wl.kappas).index(kappa)
+        A_h = cached_matrix(args.cache_dir, wl.name, m, n, kappa, wl.gen_seeds[j])
+        A = tsqr.to_device_colmajor(np.asarray(A_h))
+        del A_h
+        row = {"kappa": kappa}
+
+        def fp64():
+            tsqr.rxr_cholqr(A, s, seed, Q=Q, R=R, workspace=work64, info=info)
+
+        ms = timed(fp64, args.mixed_steps, 2)
+        ortho, res = gpu_metrics(A, Q, R)
+        row["fp64"] = {"ms": round(ms, 4), "gflops": round(F / ms / 1e6, 2), "ortho": ortho,
+                       "residual": res, "info": int(info.item()), "phases_ms": phases_of(fp64)}
+        for name, lowp in (("fp32", tsqr.FP32), ("bf16", tsqr.BF16)):
+            ws = torch.empty(tsqr.mixed_workspace_bytes(m, n, s, lowp), dtype=torch.uint8,
+                             device="cuda")
+            npass = []
+
+            def mixed():
+                npass.append(tsqr.rxr_cholqr_mixed(A, s, seed, lowp, Q=Q, R=R, workspace=ws,
+                                                   info=info)[3])
+
+            ms_m = timed(mixed, args.mixed_steps, 2)
+            o_m, r_m = gpu_metrics(A, Q, R)
+            ok = o_m <= 1e-12 and row["fp64"]["ortho"] <= 1e-12 and int(info.item()) == 0
+            row[name] = {"ms": round(ms_m, 4), "gflops_equiv": round(F / ms_m / 1e6, 2),
+                         "fp64_passes": npass[-1], "ortho": o_m, "residual": r_m,
+                         "info": int(info.item()),
+                         "speedup_vs_fp64": round(ms / ms_m, 3) if ok else None,
+                         "phases_ms": phases_of(mixed)}
+            del ws
+        out.append(row)
+        print(f"# mixed kappa={kappa:g}: fp64 {row['fp64']['ms']:.3f} ms, fp32 "
+              f"{row['fp32']['ms']:.3f} ms ({row['fp32']['fp64_passes']} passes), bf16 "
+              f"{row['bf16']['ms']:.3f} ms ({row['bf16']['fp64_passes']} passes)",
+              file=sys.stderr, flush=True)
+        del A
+        torch.cuda.empty_cache()
+    return {"workload": f"{wl.name} (m={m}, n={n}, s={s}, rqr)", "flops_per_step": F,
+            "target_ortho": 1e-12, "results": out}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +220,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cache-dir", default=None,
                     help="directory to keep the generated input matrix between runs")
+    ap.add_argument("--mixed-kappas", default="1e4,1e8,1e12",
+                    help="condition numbers of the mixed-precision comparison (mixed256 "
+                         "workload, m=2^20, n=256, s=512); empty to skip it")
+    ap.add_argument("--mixed-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -136,20 +255,7 @@ def main() -> int:
     variant = tsqr.RQR if args.variant == "rqr" else tsqr.RLU
     extra_pass = wl.extra_pass
 
-    A_h = None
-    cache = None
-    if args.cache_dir:
-        os.makedirs(args.cache_dir, exist_ok=True)
-        cache = os.path.join(args.cache_dir, f"A_{wl.name}_{wl.gen_seeds[0]}.npy")
-        if os.path.exists(cache):
-            A_h = np.load(cache, mmap_mode="r")
-    if A_h is None:
-        t0 = time.perf_counter()
-        A_h = gen_matrix(m, n, kappa, wl.gen_seeds[0])
-        print(f"# generated A ({m}x{n}, kappa={kappa:g}) in {time.perf_counter() - t0:.1f} s",
-              file=sys.stderr, flush=True)
-        if cache:
-            np.save(cache, np.asfortranarray(A_h))
+    A_h = cached_matrix(args.cache_dir, wl.name, m, n, kappa, wl.gen_seeds[0])
     A = tsqr.to_device_colmajor(np.asarray(A_h))
     Q = tsqr.colmajor(m, n)
     R = tsqr.colmajor(n, n)
@@ -229,6 +335,13 @@ def main() -> int:
                "sample": f"first {ms_} rows of the same matrix (n={n}, s={s}), one full "
                          f"factorization, {dt:.2f} s, info={r['info']}"}
 
+    mixed = None
+    kappas = [float(k) for k in args.mixed_kappas.split(",") if k.strip()]
+    if kappas:
+        del A, Q, R, work
+        torch.cuda.empty_cache()
+        mixed = mixed_comparison(args, kappas)
+
     line = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -252,6 +365,7 @@ def main() -> int:
         "residual": res,
         "info": binfo,
         "phases_ms": {k: round(v, 4) for k, v in per_step.items()},
+        "mixed_vs_fp64": mixed,
     }
     print(json.dumps(line), flush=True)
     return 0 if binfo == 0 else 1
