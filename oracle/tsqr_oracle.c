@@ -19,10 +19,11 @@
  *     R1, 3 = second Cholesky R2, 4 = any further Cholesky pass).  On breakdown the
  *     outputs Q and R are filled with NaN.
  *
- * Parity unpinned: the paper prints no worked numerical example (its accuracy and runtime
- * figures are absent from the text), so no function here is checked against a value the
- * paper prints; each is pinned instead by closed forms, invariants, brute force, library
- * cross-checks and the paper's bounds (see the tests).
+ * Pins: the paper prints no worked numerical example (its accuracy and runtime figures
+ * are absent from the text), so no function here is checked against a value the paper
+ * prints; each is pinned instead by closed forms, invariants, brute force, independent
+ * library implementations (NumPy's Philox, LAPACK, torch's BF16 rounding, mpmath) and the
+ * bounds the paper states (see tests/test_oracle_pins.py, tests/test_oracle_mixed_pins.py).
  */
 #include <math.h>
 #include <stdint.h>
