@@ -287,24 +287,92 @@ __global__ __launch_bounds__(256) void k_apply_rinv_lowp(
 }
 
 // ================================================================= Gram (low) ====
-// W partials (FP64, tile-native) of X^T X for X in the input type; rows staged in LDS
-// (FP32: row-major; BF16: column-major so eight consecutive rows are one 16-byte read);
-// FP32 accumulation over each 64-row chunk, then FP64.
-template <int PREC, int JT, int NW>
-__global__ __launch_bounds__(NW * 64) void k_gram_lowp(int64_t m, int n,
+// W partials (FP64, tile-native) of X^T X for X in the input type.  A workgroup streams
+// its row block in 64-row chunks, the next chunk loaded into registers (16-byte loads)
+// while the current one, staged in LDS, feeds the matrix cores (FP32: row-major LDS, one
+// K-step per 4 rows; BF16: column-major LDS so that eight consecutive rows are one
+// 16-byte read, one K-step per 32 rows).  FP32 accumulation over each 64-row chunk, then
+// into FP64 registers.  The upper tiles are shared out over NS workgroups per row block
+// (blockIdx.y) and NW waves each: slot y NW + w owns tiles t = slot, slot + NS NW, ...;
+// the tile set is a compile-time property of the slot.
+template <int PREC>
+struct LowOp;
+template <>
+struct LowOp<TSQR_LOWP_FP32> {
+  typedef float T;
+  static __device__ __forceinline__ v4f mma(T a, T b, v4f c) { return mfma_f32(a, b, c); }
+};
+template <>
+struct LowOp<TSQR_LOWP_BF16> {
+  typedef v8bf T;
+  static __device__ __forceinline__ v4f mma(T a, T b, v4f c) { return mfma_bf16(a, b, c); }
+};
+
+template <int PREC, int STRIDE, int SLOT, int TPW, int... U>
+__device__ __forceinline__ void gram_lowp_step(const typename LowOp<PREC>::T* op, v4f (&acc)[TPW],
+                                               std::integer_sequence<int, U...>) {
+  ((acc[U] = LowOp<PREC>::mma(op[UpperTile<SLOT + U * STRIDE>::a],
+                              op[UpperTile<SLOT + U * STRIDE>::b], acc[U])),
+   ...);
+}
+
+template <int PREC, int JT, int STRIDE, int SLOT, int KC, int LDA, int TPW>
+__device__ __forceinline__ void gram_lowp_chunk(const typename LowT<PREC>::E* lds, int q,
+                                                int c16, v4f (&acc)[TPW]) {
+  constexpr int NT = JT * (JT + 1) / 2;
+  constexpr int CNT = NT > SLOT ? (NT - SLOT + STRIDE - 1) / STRIDE : 0;
+  typedef typename LowT<PREC>::E E;
+  typedef __attribute__((address_space(3))) const E lds_e;
+  if constexpr (PREC == TSQR_LOWP_FP32) {
+#pragma unroll
+    for (int kk = 0; kk < KC / 4; ++kk) {
+      // opaque per-step row pointer: keeps each step's operand reads next to its MFMAs
+      lds_e* rowp = (lds_e*)(lds + (4 * kk + q) * LDA + c16);
+      asm volatile("" : "+v"(rowp));
+      float op[JT];
+#pragma unroll
+      for (int c = 0; c < JT; ++c) op[c] = rowp[16 * c];
+      gram_lowp_step<PREC, STRIDE, SLOT, TPW>(op, acc, std::make_integer_sequence<int, CNT>{});
+    }
+  } else {
+#pragma unroll
+    for (int g = 0; g < KC / 32; ++g) {
+      v8bf op[JT];
+#pragma unroll
+      for (int c = 0; c < JT; ++c)
+        op[c] = *reinterpret_cast<const v8bf*>(&lds[(16 * c + c16) * LDA + 32 * g + 8 * q]);
+      gram_lowp_step<PREC, STRIDE, SLOT, TPW>(op, acc, std::make_integer_sequence<int, CNT>{});
+    }
+  }
+}
+
+// VEC: X is 16-byte aligned and ldx, m are multiples of the elements per 16-byte word
+// (chosen on the host), so every in-range row group is one aligned load; the loads are
+// branch-free either way.
+template <int PREC, int JT, int NW, int NS, bool VEC>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) void k_gram_lowp(int64_t m, int n,
                                                        const typename LowT<PREC>::E* __restrict__ X,
                                                        int64_t ldx, int64_t rows_per_block,
                                                        int ntiles, double* __restrict__ part) {
   typedef typename LowT<PREC>::E E;
+  constexpr bool F32 = PREC == TSQR_LOWP_FP32;
   constexpr int KC = 64;
   constexpr int NC = JT * 16;
   constexpr int NT = JT * (JT + 1) / 2;
-  constexpr int TPW = (NT + NW - 1) / NW;
-  constexpr int LDA = (PREC == TSQR_LOWP_FP32) ? NC + 1 : KC + 8;  // row-major / col-major
-  __shared__ __attribute__((aligned(16))) E lds[(PREC == TSQR_LOWP_FP32) ? KC * LDA : NC * LDA];
+  constexpr int STRIDE = NW * NS;
+  constexpr int TPW = (NT + STRIDE - 1) / STRIDE;
+  constexpr int THREADS = NW * 64;
+  constexpr int EPL = 16 / sizeof(E);        // elements per 16-byte load (rows of a column)
+  constexpr int RPC = KC / EPL;              // loads per column per chunk
+  constexpr int CPP = THREADS / RPC;         // columns per pass
+  constexpr int PASSES = (NC + CPP - 1) / CPP;
+  constexpr int LDA = F32 ? NC + 1 : KC + 8;  // row-major / column-major
+  static_assert(STRIDE <= 16, "slot dispatch covers at most 16 slots");
+  __shared__ __attribute__((aligned(16))) E lds[F32 ? KC * LDA : NC * LDA];
 
   const int lane = lane_id(), wave = wave_id();
   const int q = lane >> 4, c16 = lane & 15;
+  const int slot = (int)blockIdx.y * NW + wave;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t r1 = min(m, r0 + rows_per_block);
   v4f acc[TPW];
@@ -314,47 +382,62 @@ __global__ __launch_bounds__(NW * 64) void k_gram_lowp(int64_t m, int n,
     acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
     acc64[u] = v4d{0.0, 0.0, 0.0, 0.0};
   }
+
+  // rows start at multiples of 64; with m a multiple of EPL, row < r1 implies that the
+  // whole group row .. row + EPL - 1 is in range
+  const int rp = (int)threadIdx.x % RPC, cb = (int)threadIdx.x / RPC;
+  E pre[PASSES][EPL];
+  auto load_chunk = [&](int64_t rb) {
+#pragma unroll
+    for (int ps = 0; ps < PASSES; ++ps) {
+      const int cc = cb + ps * CPP;
+      const int64_t row = rb + EPL * rp;
+      const bool okc = (cc < NC) && (cc < n);
+      if constexpr (VEC) {
+        const bool ok = okc && row < r1;
+        const E* src = ok ? X + (int64_t)cc * ldx + row : X;  // clamped, always valid
+        uint4 v = *reinterpret_cast<const uint4*>(src);
+        if (!ok) v = uint4{0u, 0u, 0u, 0u};
+        __builtin_memcpy(pre[ps], &v, 16);
+      } else {
+        const E* src = X + (int64_t)cc * ldx + row;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e)
+          pre[ps][e] = (okc && row + e < r1) ? src[e] : LowT<PREC>::from_float(0.f);
+      }
+    }
+  };
+
+  if (r0 < r1) load_chunk(r0);
   for (int64_t rb = r0; rb < r1; rb += KC) {
     __syncthreads();
-    for (int e = threadIdx.x; e < KC * NC; e += NW * 64) {
-      const int rr = e % KC, cc = e / KC;
-      const int64_t row = rb + rr;
-      const E v = (row < r1 && cc < n) ? X[(int64_t)cc * ldx + row] : LowT<PREC>::from_float(0.f);
-      if (PREC == TSQR_LOWP_FP32) lds[rr * LDA + cc] = v;
-      else lds[cc * LDA + rr] = v;
+#pragma unroll
+    for (int ps = 0; ps < PASSES; ++ps) {
+      const int cc = cb + ps * CPP;
+      if (cc < NC) {
+        if constexpr (F32) {
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) lds[(EPL * rp + e) * LDA + cc] = pre[ps][e];
+        } else {
+          *reinterpret_cast<uint4*>(&lds[cc * LDA + EPL * rp]) =
+              *reinterpret_cast<const uint4*>(pre[ps]);
+        }
+      }
     }
     __syncthreads();
-    if (PREC == TSQR_LOWP_FP32) {
-#pragma unroll 4
-      for (int kk = 0; kk < KC / 4; ++kk) {
-        float op[JT];
-#pragma unroll
-        for (int c = 0; c < JT; ++c) op[c] = (float)lds[(4 * kk + q) * LDA + 16 * c + c16];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          constexpr int dummy = 0;
-          (void)dummy;
-          int b = 0;
-          while ((b + 1) * (b + 2) / 2 <= t) ++b;
-          const int a = t - b * (b + 1) / 2;
-          if (t % NW == wave) acc[t / NW] = mfma_f32(op[a], op[b], acc[t / NW]);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int g = 0; g < KC / 32; ++g) {
-        v8bf op[JT];
-#pragma unroll
-        for (int c = 0; c < JT; ++c)
-          op[c] = *reinterpret_cast<const v8bf*>(&lds[(16 * c + c16) * LDA + 32 * g + 8 * q]);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          int b = 0;
-          while ((b + 1) * (b + 2) / 2 <= t) ++b;
-          const int a = t - b * (b + 1) / 2;
-          if (t % NW == wave) acc[t / NW] = mfma_bf16(op[a], op[b], acc[t / NW]);
-        }
-      }
+    if (rb + KC < r1) load_chunk(rb + KC);
+    switch (slot) {
+#define TSQR_GRL_SLOT(S_)                                                                   \
+  case S_:                                                                                  \
+    if constexpr (S_ < STRIDE)                                                              \
+      gram_lowp_chunk<PREC, JT, STRIDE, S_, KC, LDA, TPW>(lds, q, c16, acc);                \
+    break;
+      TSQR_GRL_SLOT(0) TSQR_GRL_SLOT(1) TSQR_GRL_SLOT(2) TSQR_GRL_SLOT(3)
+      TSQR_GRL_SLOT(4) TSQR_GRL_SLOT(5) TSQR_GRL_SLOT(6) TSQR_GRL_SLOT(7)
+      TSQR_GRL_SLOT(8) TSQR_GRL_SLOT(9) TSQR_GRL_SLOT(10) TSQR_GRL_SLOT(11)
+      TSQR_GRL_SLOT(12) TSQR_GRL_SLOT(13) TSQR_GRL_SLOT(14) TSQR_GRL_SLOT(15)
+#undef TSQR_GRL_SLOT
+      default: break;
     }
 #pragma unroll
     for (int u = 0; u < TPW; ++u) {
@@ -365,10 +448,12 @@ __global__ __launch_bounds__(NW * 64) void k_gram_lowp(int64_t m, int n,
   }
   double* dst = part + (size_t)blockIdx.x * ntiles * 256;
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
-    if (t % NW == wave && t < ntiles)
+  for (int u = 0; u < TPW; ++u) {
+    const int t = slot + u * STRIDE;
+    if (t < NT && t < ntiles)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) dst[(size_t)t * 256 + lowp_to_f64_tile_index(lane, r)] = acc64[t / NW][r];
+      for (int r = 0; r < 4; ++r) dst[(size_t)t * 256 + lowp_to_f64_tile_index(lane, r)] = acc64[u][r];
+  }
 }
 
 // ================================================================== launchers ====
@@ -456,18 +541,28 @@ hipError_t launch_apply_rinv_lowp(int prec, int64_t m, int n, const double* Y, i
 
 hipError_t launch_gram_lowp(int prec, const GramPlan& p, int64_t m, int n, const void* X,
                             int64_t ldx, double* part, hipStream_t st) {
-  dim3 grid(p.kblocks);
-#define TSQR_GRL(PR, J, NW_)                                                                  \
+  const int64_t epl = prec == TSQR_LOWP_FP32 ? 4 : 8;
+  const bool vec = ((reinterpret_cast<uintptr_t>(X) & 15) == 0) && (ldx % epl == 0) &&
+                   (m % epl == 0);
+#define TSQR_GRL(PR, J, NW_, NS_)                                                             \
   if (prec == PR && p.jt_total <= J) {                                                        \
     typedef typename LowT<PR>::E E;                                                           \
-    hipLaunchKernelGGL((k_gram_lowp<PR, J, NW_>), grid, dim3(NW_ * 64), 0, st, m, n,           \
-                       (const E*)X, ldx, p.rows_per_block, p.ntiles, part);                   \
+    if (vec)                                                                                  \
+      hipLaunchKernelGGL((k_gram_lowp<PR, J, NW_, NS_, true>), dim3(p.kblocks, NS_),           \
+                         dim3(NW_ * 64), 0, st, m, n, (const E*)X, ldx, p.rows_per_block,      \
+                         p.ntiles, part);                                                     \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_gram_lowp<PR, J, NW_, NS_, false>), dim3(p.kblocks, NS_),          \
+                         dim3(NW_ * 64), 0, st, m, n, (const E*)X, ldx, p.rows_per_block,      \
+                         p.ntiles, part);                                                     \
     return hipGetLastError();                                                                 \
   }
-  TSQR_GRL(TSQR_LOWP_FP32, 1, 4) TSQR_GRL(TSQR_LOWP_FP32, 2, 4) TSQR_GRL(TSQR_LOWP_FP32, 4, 4)
-  TSQR_GRL(TSQR_LOWP_FP32, 8, 4) TSQR_GRL(TSQR_LOWP_FP32, 16, 8)
-  TSQR_GRL(TSQR_LOWP_BF16, 1, 4) TSQR_GRL(TSQR_LOWP_BF16, 2, 4) TSQR_GRL(TSQR_LOWP_BF16, 4, 4)
-  TSQR_GRL(TSQR_LOWP_BF16, 8, 4) TSQR_GRL(TSQR_LOWP_BF16, 16, 8)
+  TSQR_GRL(TSQR_LOWP_FP32, 1, 4, 1) TSQR_GRL(TSQR_LOWP_FP32, 2, 4, 1)
+  TSQR_GRL(TSQR_LOWP_FP32, 4, 4, 1) TSQR_GRL(TSQR_LOWP_FP32, 8, 4, 1)
+  TSQR_GRL(TSQR_LOWP_FP32, 16, 8, 2)
+  TSQR_GRL(TSQR_LOWP_BF16, 1, 4, 1) TSQR_GRL(TSQR_LOWP_BF16, 2, 4, 1)
+  TSQR_GRL(TSQR_LOWP_BF16, 4, 4, 1) TSQR_GRL(TSQR_LOWP_BF16, 8, 4, 1)
+  TSQR_GRL(TSQR_LOWP_BF16, 16, 8, 2)
 #undef TSQR_GRL
   return hipErrorInvalidValue;
 }

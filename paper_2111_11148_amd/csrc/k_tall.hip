@@ -177,18 +177,142 @@ __global__ __launch_bounds__(512, 1) void k_trsm_mfma(int64_t m, int n,
   }
 }
 
+// ------------------------------------------------------------------------------------
+// Off-diagonal update of the column-blocked solve: C = Y - X T for a kBlk x nb block T of
+// the triangular factor (nb <= kBlk), X m x kBlk (a solved block), Y and C m x nb.
+// T is staged once per workgroup in LDS (row-major, padded); each wavefront owns 16-row
+// tiles and computes the transposed product C^T(16b.., rows) = T^T X^T on FP64 MFMA:
+// A operand = T(k, 16b + l%16) from LDS, B operand = X(row, k) from global memory, and
+// accumulator register r of lane l is C(row l%16, 16b + 4r + l/16).  C may alias Y (each
+// wavefront reads its whole tile before writing it).
+// ------------------------------------------------------------------------------------
+constexpr int kBlk = 128;  // column block of the blocked solve
+
+__global__ __launch_bounds__(512) void k_trsm_update(int64_t m, int nb,
+                                                     const double* __restrict__ X, int64_t ldx,
+                                                     const double* __restrict__ T, int64_t ldt,
+                                                     const double* Y, int64_t ldy, double* C,
+                                                     int64_t ldc) {
+  constexpr int NB = kBlk / 16;  // column tiles of C
+  constexpr int KS = kBlk / 4;   // MFMA K-steps
+  constexpr int LDT = kBlk + 1;
+  extern __shared__ double ts[];  // kBlk x LDT
+  for (int e = threadIdx.x; e < kBlk * kBlk; e += blockDim.x) {
+    const int k = e % kBlk, c = e / kBlk;
+    ts[k * LDT + c] = (c < nb) ? T[(int64_t)c * ldt + k] : 0.0;
+  }
+  __syncthreads();
+
+  const int lane = lane_id();
+  const int q = lane >> 4, c16 = lane & 15;
+  const int64_t ntiles = (m + 15) / 16;
+  const int nw = blockDim.x / kWave;
+  const int64_t wstride = (int64_t)gridDim.x * nw;
+  for (int64_t tile = (int64_t)blockIdx.x * nw + wave_id(); tile < ntiles; tile += wstride) {
+    const int64_t row = tile * 16 + c16;
+    const bool rok = row < m;
+    const int64_t rowc = rok ? row : 0;  // clamped, always a valid address
+    // X(row, k) for k = 4kk + q, in chunks of KC K-steps; chunk c+1 is loaded while chunk
+    // c feeds the matrix cores
+    constexpr int KC = 8;
+    auto load_x = [&](int c, double (&xb)[KC]) {
+      // per-lane base (row, column q of the chunk), then uniform strides of 4 columns
+      const double* xp = X + (int64_t)(4 * c * KC + q) * ldx + rowc;
+      asm volatile("" : "+v"(xp));
+#pragma unroll
+      for (int j = 0; j < KC; ++j) {
+        const double v = xp[(int64_t)(4 * j) * ldx];
+        xb[j] = rok ? v : 0.0;
+      }
+    };
+    v4d acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = v4d{0.0, 0.0, 0.0, 0.0};
+    double xa[KC], xn[KC];
+    load_x(0, xa);
+#pragma unroll
+    for (int c = 0; c < KS / KC; ++c) {
+      if (c + 1 < KS / KC) load_x(c + 1, xn);
+#pragma unroll
+      for (int j = 0; j < KC; ++j) {
+        // opaque per-step row pointer: keeps the step's operand reads next to its MFMAs
+        const lds_f64* tp = (const lds_f64*)ts + (4 * (c * KC + j) + q) * LDT + c16;
+        asm volatile("" : "+v"(tp));
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[b] = mfma_f64(tp[16 * b], xa[j], acc[b]);
+      }
+#pragma unroll
+      for (int j = 0; j < KC; ++j) xa[j] = xn[j];
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      double yv[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int col = 16 * b + 4 * r + q;
+        yv[r] = Y[(int64_t)(col < nb ? col : 0) * ldy + rowc];
+      }
+      if (rok)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int col = 16 * b + 4 * r + q;
+          if (col < nb) C[(int64_t)col * ldc + row] = yv[r] - acc[b][r];
+        }
+    }
+  }
+}
+
 size_t trsm_scratch_doubles(int n) {
+  // wider matrices are solved in column blocks of kBlk that reuse one prepared block
+  const int nn = n > kBlk ? kBlk : n;
   int jt = 1;
-  while (jt < (n + 15) / 16) jt <<= 1;
+  while (jt < (nn + 15) / 16) jt <<= 1;
   return trsm_prep_doubles(jt);
 }
 
+static hipError_t launch_trsm_block(int64_t m, int n, const double* Y, int64_t ldy,
+                                    const double* T, int64_t ldt, double* X, int64_t ldx,
+                                    double* scratch, hipStream_t st);
+
+// X = Y T^{-1}.  Up to kBlk columns: one substitution kernel.  Wider: by column blocks,
+// X_k = (Y_k - sum_{j<k} X_j T_jk) T_kk^{-1} (the update kernel, then the substitution of
+// the diagonal block in place).
 hipError_t launch_trsm(int64_t m, int n, const double* Y, int64_t ldy, const double* T,
                        int64_t ldt, double* X, int64_t ldx, double* scratch, hipStream_t st) {
   if (m <= 0 || n <= 0) return hipSuccess;
+  if (n <= kBlk) return launch_trsm_block(m, n, Y, ldy, T, ldt, X, ldx, scratch, st);
+  const int64_t ntiles = (m + 15) / 16;
+  int64_t ublocks = (ntiles + 7) / 8;
+  const int64_t cap = (int64_t)device_cu_count();
+  if (ublocks > cap) ublocks = cap;
+  const size_t ush = (size_t)kBlk * (kBlk + 1) * sizeof(double);
+  for (int k0 = 0; k0 < n; k0 += kBlk) {
+    const int nbk = (n - k0) < kBlk ? (n - k0) : kBlk;
+    for (int j0 = 0; j0 < k0; j0 += kBlk) {
+      const double* src = (j0 == 0) ? Y + (int64_t)k0 * ldy : X + (int64_t)k0 * ldx;
+      const int64_t lds_ = (j0 == 0) ? ldy : ldx;
+      hipLaunchKernelGGL(k_trsm_update, dim3((unsigned)ublocks), dim3(512), ush, st, m, nbk,
+                         X + (int64_t)j0 * ldx, ldx, T + (int64_t)k0 * ldt + j0, ldt, src, lds_,
+                         X + (int64_t)k0 * ldx, ldx);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    const double* src = (k0 == 0) ? Y : X;
+    const int64_t lds_ = (k0 == 0) ? ldy : ldx;
+    const hipError_t e = launch_trsm_block(m, nbk, src + (int64_t)k0 * lds_, lds_,
+                                           T + (int64_t)k0 * ldt + k0, ldt,
+                                           X + (int64_t)k0 * ldx, ldx, scratch, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+static hipError_t launch_trsm_block(int64_t m, int n, const double* Y, int64_t ldy,
+                                    const double* T, int64_t ldt, double* X, int64_t ldx,
+                                    double* scratch, hipStream_t st) {
   int jt = 1;
   while (jt < (n + 15) / 16) jt <<= 1;
-  if (jt > 16) return hipErrorInvalidValue;
+  if (jt > 8) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_trsm_prep, dim3(jt), dim3(256), 0, st, n, jt, T, ldt, scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -205,33 +329,71 @@ hipError_t launch_trsm(int64_t m, int n, const double* Y, int64_t ldy, const dou
     return hipGetLastError();                                                              \
   }
   TSQR_TRSM(1, true) TSQR_TRSM(2, true) TSQR_TRSM(4, true) TSQR_TRSM(8, true)
-  TSQR_TRSM(16, false)
 #undef TSQR_TRSM
   return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------------------------------------------
-// Gram matrix W = X^T X (upper 16x16 tiles), split over row blocks.  A workgroup stages
-// 64 rows of X in LDS (row-major, padded) and each wavefront accumulates a fixed subset
-// of the upper tiles; for MFMA K-step kk, lane l reads X(row 4kk + l/16, col 16c + l%16),
-// which is simultaneously the A operand (X^T) of tile (c, .) and the B operand of (., c).
-// Partials are written tile-natively and summed in a fixed order by k_gram_reduce.
+// Gram matrix W = X^T X (upper 16x16 tiles), split over row blocks.  A workgroup streams
+// its row block in 32-row chunks: the next chunk is loaded into registers (16-byte loads,
+// two rows of one column per thread) while the current one, staged row-major in LDS, feeds
+// the matrix cores, so global latency hides behind the MFMA work with one barrier pair per
+// chunk.  For MFMA K-step kk, lane l reads X(row 4kk + l/16, col 16c + l%16), which is
+// simultaneously the A operand (X^T) of tile (c, .) and the B operand of (., c).  Wave w
+// owns the upper tiles t = w, w + NW, ... (tiles numbered column by column); the tile set
+// is a compile-time property of the wave (gram_chunk<..., W>), so the inner loop is a
+// straight run of MFMAs with no per-tile branches.  For wide matrices the tiles are also
+// shared out over NS workgroups per row block (blockIdx.y): slot y NW + w owns tiles
+// slot, slot + NS NW, ...  Partials are written tile-natively and summed in a fixed order
+// by k_gram_reduce.
 // ------------------------------------------------------------------------------------
-template <int JT, int NW>
-__global__ __launch_bounds__(NW * 64) void k_gram_f64(int64_t m, int n,
+// One K-step of wave W: acc[u] += X(:, a)^T X(:, b) for its tiles t = W + u NW.
+template <int STRIDE, int W, int TPW, int... U>
+__device__ __forceinline__ void gram_step(const double* op, v4d (&acc)[TPW],
+                                          std::integer_sequence<int, U...>) {
+  ((acc[U] = mfma_f64(op[UpperTile<W + U * STRIDE>::a], op[UpperTile<W + U * STRIDE>::b],
+                      acc[U])),
+   ...);
+}
+
+template <int JT, int STRIDE, int W, int KC, int LDN, int TPW>
+__device__ __forceinline__ void gram_chunk(const lds_f64* lds, int q, int c16, v4d (&acc)[TPW]) {
+  constexpr int NT = JT * (JT + 1) / 2;
+  constexpr int CNT = NT > W ? (NT - W + STRIDE - 1) / STRIDE : 0;
+  const lds_f64* lp = lds + q * LDN + c16;
+#pragma unroll
+  for (int kk = 0; kk < KC / 4; ++kk) {
+    const lds_f64* rowp = lp + 4 * kk * LDN;
+    double op[JT];
+#pragma unroll
+    for (int c = 0; c < JT; ++c) op[c] = rowp[16 * c];
+    gram_step<STRIDE, W, TPW>(op, acc, std::make_integer_sequence<int, CNT>{});
+  }
+}
+
+// VEC: X is 16-byte aligned, ldx and m are even, so every in-range row pair is one
+// aligned 16-byte load (chosen on the host; the loads stay branch-free either way, so the
+// prefetch is never waited for before the MFMA work that should hide it).
+template <int JT, int NW, int NS, bool VEC>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) void k_gram_f64(int64_t m, int n,
                                                       const double* __restrict__ X, int64_t ldx,
                                                       int64_t rows_per_block, int ntiles,
                                                       double* __restrict__ part) {
-  constexpr int KC = 64;
+  constexpr int KC = 32;
   constexpr int NC = JT * 16;
   constexpr int LDN = NC + 1;
   constexpr int NT = JT * (JT + 1) / 2;
-  constexpr int TPW = (NT + NW - 1) / NW;
+  constexpr int STRIDE = NW * NS;
+  constexpr int TPW = (NT + STRIDE - 1) / STRIDE;
   constexpr int THREADS = NW * 64;
+  constexpr int CPP = THREADS / (KC / 2);  // columns loaded per pass
+  constexpr int PASSES = (NC + CPP - 1) / CPP;
+  static_assert(STRIDE <= 16, "slot dispatch covers at most 16 slots");
   __shared__ double lds[KC * LDN];
 
   const int lane = lane_id(), wave = wave_id();
   const int q = lane >> 4, c16 = lane & 15;
+  const int slot = (int)blockIdx.y * NW + wave;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t r1 = min(m, r0 + rows_per_block);
 
@@ -239,24 +401,55 @@ __global__ __launch_bounds__(NW * 64) void k_gram_f64(int64_t m, int n,
 #pragma unroll
   for (int u = 0; u < TPW; ++u) acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
 
+  // rows start even (row blocks and chunks are multiples of 32): with m even, row < r1
+  // implies row + 1 < r1, and the pair (2rp, 2rp+1) is one aligned 16-byte word
+  const int rp = (int)threadIdx.x % (KC / 2), cb = (int)threadIdx.x / (KC / 2);
+  double pre[PASSES][2];
+  auto load_chunk = [&](int64_t rb) {
+#pragma unroll
+    for (int ps = 0; ps < PASSES; ++ps) {
+      const int cc = cb + ps * CPP;
+      const int64_t row = rb + 2 * rp;
+      const bool okc = (cc < NC) && (cc < n);
+      if constexpr (VEC) {
+        const bool ok = okc && row < r1;
+        const double* src = ok ? X + (int64_t)cc * ldx + row : X;  // clamped, always valid
+        const v2d v = *reinterpret_cast<const v2d*>(src);
+        pre[ps][0] = ok ? v[0] : 0.0;
+        pre[ps][1] = ok ? v[1] : 0.0;
+      } else {
+        const double* src = X + (int64_t)cc * ldx + row;
+        pre[ps][0] = (okc && row < r1) ? src[0] : 0.0;
+        pre[ps][1] = (okc && row + 1 < r1) ? src[1] : 0.0;
+      }
+    }
+  };
+
+  if (r0 < r1) load_chunk(r0);
   for (int64_t rb = r0; rb < r1; rb += KC) {
     __syncthreads();
-    // col-major global (rows contiguous) -> row-major LDS
-    for (int e = threadIdx.x; e < KC * NC; e += THREADS) {
-      const int rr = e % KC, cc = e / KC;
-      const int64_t row = rb + rr;
-      lds[rr * LDN + cc] = (row < r1 && cc < n) ? X[(int64_t)cc * ldx + row] : 0.0;
+#pragma unroll
+    for (int ps = 0; ps < PASSES; ++ps) {
+      const int cc = cb + ps * CPP;
+      if (cc < NC) {
+        lds[(2 * rp) * LDN + cc] = pre[ps][0];
+        lds[(2 * rp + 1) * LDN + cc] = pre[ps][1];
+      }
     }
     __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < KC / 4; ++kk) {
-      double op[JT];
-#pragma unroll
-      for (int c = 0; c < JT; ++c) op[c] = lds[(4 * kk + q) * LDN + 16 * c + c16];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        if (t % NW == wave) acc[t / NW] = mfma_f64(op[tri_a(t)], op[tri_b(t)], acc[t / NW]);
-      }
+    if (rb + KC < r1) load_chunk(rb + KC);
+    const lds_f64* lp = (const lds_f64*)lds;
+    switch (slot) {
+#define TSQR_GRAM_SLOT(W_)                                                             \
+  case W_:                                                                             \
+    if constexpr (W_ < STRIDE) gram_chunk<JT, STRIDE, W_, KC, LDN, TPW>(lp, q, c16, acc); \
+    break;
+      TSQR_GRAM_SLOT(0) TSQR_GRAM_SLOT(1) TSQR_GRAM_SLOT(2) TSQR_GRAM_SLOT(3)
+      TSQR_GRAM_SLOT(4) TSQR_GRAM_SLOT(5) TSQR_GRAM_SLOT(6) TSQR_GRAM_SLOT(7)
+      TSQR_GRAM_SLOT(8) TSQR_GRAM_SLOT(9) TSQR_GRAM_SLOT(10) TSQR_GRAM_SLOT(11)
+      TSQR_GRAM_SLOT(12) TSQR_GRAM_SLOT(13) TSQR_GRAM_SLOT(14) TSQR_GRAM_SLOT(15)
+#undef TSQR_GRAM_SLOT
+      default: break;
     }
   }
 
@@ -264,9 +457,10 @@ __global__ __launch_bounds__(NW * 64) void k_gram_f64(int64_t m, int n,
   // n x n matrix (the rest only exist in the padded template size)
   double* dst = part + (size_t)blockIdx.x * ntiles * 256;
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
-    if (t % NW == wave && t < ntiles)
-      *reinterpret_cast<v4d*>(dst + (size_t)t * 256 + lane * 4) = acc[t / NW];
+  for (int u = 0; u < TPW; ++u) {
+    const int t = slot + u * STRIDE;
+    if (t < NT && t < ntiles) *reinterpret_cast<v4d*>(dst + (size_t)t * 256 + lane * 4) = acc[u];
+  }
 }
 
 // W(i, j) = W(j, i) = sum_kb part[kb][tile][lane][reg]; same deterministic two-level
@@ -313,14 +507,21 @@ GramPlan plan_gram(int64_t m, int n) {
 
 hipError_t launch_gram(const GramPlan& p, int64_t m, int n, const double* X, int64_t ldx,
                        double* part, hipStream_t st) {
-  dim3 grid(p.kblocks);
-#define TSQR_GRAM(J, NW_)                                                                   \
+  const bool vec = ((reinterpret_cast<uintptr_t>(X) & 15) == 0) && ((ldx & 1) == 0) &&
+                   ((m & 1) == 0);
+#define TSQR_GRAM(J, NW_, NS_)                                                              \
   if (p.jt_total <= J) {                                                                   \
-    hipLaunchKernelGGL((k_gram_f64<J, NW_>), grid, dim3(NW_ * 64), 0, st, m, n, X, ldx,     \
-                       p.rows_per_block, p.ntiles, part);                                             \
+    const dim3 grid(p.kblocks, NS_);                                                       \
+    if (vec)                                                                               \
+      hipLaunchKernelGGL((k_gram_f64<J, NW_, NS_, true>), grid, dim3(NW_ * 64), 0, st, m, n, \
+                         X, ldx, p.rows_per_block, p.ntiles, part);                        \
+    else                                                                                   \
+      hipLaunchKernelGGL((k_gram_f64<J, NW_, NS_, false>), grid, dim3(NW_ * 64), 0, st, m,  \
+                         n, X, ldx, p.rows_per_block, p.ntiles, part);                     \
     return hipGetLastError();                                                               \
   }
-  TSQR_GRAM(1, 4) TSQR_GRAM(2, 4) TSQR_GRAM(4, 4) TSQR_GRAM(8, 4) TSQR_GRAM(16, 8)
+  TSQR_GRAM(1, 4, 1) TSQR_GRAM(2, 4, 1) TSQR_GRAM(4, 4, 1) TSQR_GRAM(8, 4, 1)
+  TSQR_GRAM(16, 8, 2)
 #undef TSQR_GRAM
   return hipErrorInvalidValue;
 }

@@ -9,11 +9,29 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 namespace tsqr {
 
 constexpr int kWave = 64;
 
+// Upper-triangular tile numbering, column by column: tile t is (a, b) with
+// t = b (b + 1) / 2 + a, a <= b.  UpperTile<t> evaluates the map at compile time (a
+// template constant, so it is folded even where a loop over t would not be unrolled
+// far enough for the optimiser to fold a constexpr call).
+template <int T>
+struct UpperTile {
+  static constexpr int col() {
+    int b = 0;
+    while ((b + 1) * (b + 2) / 2 <= T) ++b;
+    return b;
+  }
+  static constexpr int b = col();
+  static constexpr int a = T - b * (b + 1) / 2;
+};
+
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------------
@@ -34,8 +52,10 @@ __device__ __forceinline__ U32x4 philox4x32_10(U32x4 c, uint32_t k0, uint32_t k1
       k0 += W0;
       k1 += W1;
     }
-    const uint32_t hi0 = __umulhi(M0, c.x), lo0 = M0 * c.x;
-    const uint32_t hi1 = __umulhi(M1, c.z), lo1 = M1 * c.z;
+    // one 32 x 32 -> 64-bit product per multiplier (v_mad_u64_u32) gives both halves
+    const uint64_t p0 = (uint64_t)M0 * c.x, p1 = (uint64_t)M1 * c.z;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
     c = U32x4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
   }
   return c;
@@ -81,6 +101,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
-__device__ __forceinline__ int wave_id() { return (int)(threadIdx.x / kWave); }
+// wavefront index inside the workgroup, as a uniform (scalar) value
+__device__ __forceinline__ int wave_id() {
+  return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+}
 
 }  // namespace tsqr
