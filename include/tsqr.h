@@ -167,7 +167,9 @@ int tsqr_sketch(int64_t m, int64_t n, const double* A, int64_t lda, int64_t s, u
  * pivot LU; the result is sign-normalised, R0 = diag(sign d_k) * (R or U), and written as
  * an n x n upper matrix (strict lower part zeroed, ldr >= n).  A zero or NaN diagonal at
  * column k sets *d_info = 1000 + k (if *d_info was 0) and R0(k,k) = NaN.
- * Workspace: at least s*n doubles (scratch of the large-size variant). */
+ * Workspace (args 9, 10): tsqr_sketch_factor_workspace_bytes(s, n) bytes (a working copy
+ * of B and the blocked factorization's reflector block). */
+size_t tsqr_sketch_factor_workspace_bytes(int64_t s, int64_t n);
 int tsqr_sketch_factor(int variant, int64_t s, int64_t n, const double* B, int64_t ldb,
                        double* R0, int64_t ldr, int* d_info, void* work, size_t work_bytes,
                        void* stream);

@@ -37,6 +37,7 @@ _SIGS = {
                                   _i64, _vp, _sz, _vp, _vp]),
     "tsqr_sketch_workspace_bytes": (_sz, [_i64, _i64, _i64]),
     "tsqr_sketch": (_int, [_i64, _i64, _vp, _i64, _i64, _u64, _vp, _i64, _vp, _sz, _vp]),
+    "tsqr_sketch_factor_workspace_bytes": (_sz, [_i64, _i64]),
     "tsqr_sketch_factor": (_int, [_int, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _sz, _vp]),
     "tsqr_trsm_workspace_bytes": (_sz, [_i64]),
     "tsqr_trsm": (_int, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp]),
@@ -320,9 +321,10 @@ def sketch_factor(B: torch.Tensor, variant: int = RQR, stream=None):
     s, n = B.shape
     R0 = colmajor(n, n, device=B.device)
     info = torch.zeros(1, dtype=torch.int32, device=B.device)
-    work = torch.empty(s * n, dtype=torch.float64, device=B.device)
+    nbytes = int(load().tsqr_sketch_factor_workspace_bytes(s, n))
+    work = torch.empty(max(nbytes, 8), dtype=torch.uint8, device=B.device)
     _check(load().tsqr_sketch_factor(variant, s, n, B.data_ptr(), ldb, R0.data_ptr(), n,
-                                     info.data_ptr(), work.data_ptr(), work.numel() * 8,
+                                     info.data_ptr(), work.data_ptr(), nbytes,
                                      _stream(stream)), "tsqr_sketch_factor")
     return R0, info
 

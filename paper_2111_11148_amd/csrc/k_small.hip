@@ -217,6 +217,226 @@ __global__ __launch_bounds__(kSmallThreads) void k_geqrf_glb(int s, int n,
   }
 }
 
+// ====================================================== blocked Householder QR =====
+// For sketches too large for the register-resident kernel: panels of NB columns.  The
+// panel kernel (one workgroup) factors rows j0.. of NB columns in LDS with the same
+// reflectors as above, and forms the compact-WY factor T of the panel's block reflector
+// (H_0 H_1 ... = I - V T V^T; T upper, T_kk = tau_k, T(0:k, k) = -tau_k T(0:k, 0:k)
+// V(:, 0:k)^T v_k).  The update kernel applies the block reflector's transpose to the
+// trailing columns, C = C - V (T^T (V^T C)), one wavefront per column.  The R entries
+// (upper triangle) accumulate in the working copy Wk (ld s); the diagonal is kept in
+// `betas`; the finish kernel writes the sign-normalised R0.
+// Working space: Wk s*n, V s*NB, T NB*NB, betas n (see qr_blocked_scratch_doubles).
+// dst(i, c) = src(i, c) for i < rows, c < cols (src ld lds, dst ld ldd), eight loads in
+// flight per thread so the copy is not a chain of memory latencies
+__device__ __forceinline__ void copy_to_lds(const double* __restrict__ src, int64_t lds_, int rows,
+                                            int cols, double* dst, int ldd) {
+  const int total = rows * cols;
+  for (int e0 = threadIdx.x; e0 < total; e0 += 8 * (int)blockDim.x) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * (int)blockDim.x;
+      const int c = e / rows, i = e - c * rows;
+      v[u] = (e < total) ? src[(int64_t)c * lds_ + i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * (int)blockDim.x;
+      const int c = e / rows, i = e - c * rows;
+      if (e < total) dst[c * ldd + i] = v[u];
+    }
+  }
+}
+
+template <int NB>
+__host__ __device__ constexpr size_t qr_panel_lds_doubles(int p) {
+  return (size_t)NB * (p + 1) + 2 * NB * NB + 2 * NB;
+}
+
+template <int NB>
+__global__ __launch_bounds__(kSmallThreads) void k_qr_panel(int s, int n, int j0,
+                                                            double* __restrict__ Wk,
+                                                            double* __restrict__ Vb,
+                                                            double* __restrict__ Tb,
+                                                            double* __restrict__ betas) {
+  extern __shared__ double sm[];
+  const int p = s - j0;                  // panel rows
+  const int w = min(NB, n - j0);         // panel columns
+  const int ldp = p + 1;
+  double* P = sm;                        // column c at P + c * ldp
+  double* G = P + (size_t)NB * ldp;      // G[j * NB + k] = v_j^T v_k (j < k)
+  double* T = G + NB * NB;               // T[j * NB + k]
+  double* tau = T + NB * NB;
+  double* bet = tau + NB;
+  const int lane = lane_id(), wave = wave_id();
+  copy_to_lds(Wk + (int64_t)j0 * s + j0, s, p, w, P, ldp);
+  __syncthreads();
+  // reflector of column k from rows k.. of its (updated) column: v = (1, x2 scal)
+  auto reflector = [&](int k) {
+    double* x = P + k * ldp;
+    double part = 0.0;
+    for (int i = k + 1 + lane; i < p; i += kWave) part += x[i] * x[i];
+    const double xnorm2 = wave_sum(part);
+    const double alpha = x[k];
+    double beta, tk, scal;
+    house(alpha, xnorm2, beta, tk, scal);
+    for (int i = k + 1 + lane; i < p; i += kWave) x[i] *= scal;
+    if (lane == 0) {
+      x[k] = 1.0;
+      tau[k] = tk;
+      bet[k] = beta;
+    }
+  };
+  if (wave == 0) reflector(0);
+  // step k: apply H_k to columns k+1.. (wave 0 takes column k+1 and then builds the next
+  // reflector at once, the other waves share the rest), one barrier per step
+  for (int k = 0; k < w; ++k) {
+    __syncthreads();
+    const double* x = P + k * ldp;
+    const double tk = tau[k];
+    auto apply = [&](int c) {
+      double* y = P + c * ldp;
+      double d = 0.0;
+      for (int i = k + lane; i < p; i += kWave) d += x[i] * y[i];
+      const double wv = wave_sum(d) * tk;
+      for (int i = k + lane; i < p; i += kWave) y[i] -= x[i] * wv;
+    };
+    if (wave == 0) {
+      if (k + 1 < w) {
+        apply(k + 1);
+        reflector(k + 1);
+      }
+    } else {
+      for (int c = k + 1 + wave; c < w; c += kSmallWaves - 1) apply(c);
+    }
+  }
+  __syncthreads();
+  // Gram of the reflector vectors (v_j is zero above row j and 1 at row j)
+  for (int t = wave; t < w * w; t += kSmallWaves) {
+    const int j = t / w, k = t % w;
+    if (j >= k) continue;
+    double d = 0.0;
+    for (int i = k + lane; i < p; i += kWave) d += P[j * ldp + i] * P[k * ldp + i];
+    d = wave_sum(d);
+    if (lane == 0) G[j * NB + k] = d;
+  }
+  __syncthreads();
+  if (wave == 0) {
+    // lane j builds row j of T; it only reads entries of that row it wrote itself
+    for (int k = 0; k < w; ++k) {
+      if (lane < k) {
+        double z = 0.0;
+        for (int i = lane; i < k; ++i) z += T[lane * NB + i] * G[i * NB + k];
+        T[lane * NB + k] = -tau[k] * z;
+      } else if (lane == k) {
+        T[k * NB + k] = tau[k];
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < NB * NB; e += kSmallThreads) {
+    const int j = e / NB, k = e % NB;
+    Tb[e] = (j <= k && k < w) ? T[e] : 0.0;
+  }
+  for (int c = 0; c < w; ++c)
+    for (int i = threadIdx.x; i < p; i += kSmallThreads) {
+      const double v = P[c * ldp + i];
+      Vb[(int64_t)c * s + i] = (i < c) ? 0.0 : v;                 // reflector vectors
+      if (i < c) Wk[(int64_t)(j0 + c) * s + j0 + i] = v;          // R entries
+    }
+  if (threadIdx.x < w) betas[j0 + threadIdx.x] = bet[threadIdx.x];
+}
+
+template <int NB, int RPL>
+__global__ __launch_bounds__(256) void k_qr_update(int s, int n, int j0, int w, int cpb,
+                                                   const double* __restrict__ Vb,
+                                                   const double* __restrict__ Tb,
+                                                   double* __restrict__ Wk) {
+  extern __shared__ double sm[];
+  const int p = s - j0;
+  double* Vs = sm;                      // column k at Vs + k * p
+  double* Ts = Vs + (size_t)NB * p;     // NB x NB
+  copy_to_lds(Vb, s, p, w, Vs, p);
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) Ts[e] = Tb[e];
+  __syncthreads();
+  const int lane = lane_id(), wave = wave_id();
+  const int c0 = j0 + w + (int)blockIdx.x * cpb;
+  const int c1 = min(n, c0 + cpb);
+  for (int c = c0 + wave; c < c1; c += (int)blockDim.x / kWave) {
+    double* y = Wk + (int64_t)c * s + j0;
+    double yl[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lane + kWave * r;
+      yl[r] = (i < p) ? y[i] : 0.0;
+    }
+    double d[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      double part = 0.0;
+      if (k < w)
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+          const int i = lane + kWave * r;
+          if (i < p) part += Vs[k * p + i] * yl[r];
+        }
+      d[k] = wave_sum(part);
+    }
+    // e = T^T d  (T upper: e_k = sum_{j <= k} T_jk d_j)
+    double e[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j <= k; ++j) acc += Ts[j * NB + k] * d[j];
+      e[k] = acc;
+    }
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lane + kWave * r;
+      if (i < p) {
+        double v = yl[r];
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+          if (k < w) v -= Vs[k * p + i] * e[k];
+        y[i] = v;
+      }
+    }
+  }
+}
+
+// R0 = diag(sign(beta)) R: R(i, c) = sign(beta_i) Wk(i, c) (i < c), |beta_c| on the
+// diagonal (NaN when beta_c is zero or NaN), zero below; info = 1000 + first bad column.
+__global__ __launch_bounds__(256) void k_qr_finish(int s, int n, const double* __restrict__ Wk,
+                                                   const double* __restrict__ betas,
+                                                   double* __restrict__ R, int64_t ldr,
+                                                   int* __restrict__ info) {
+  const int c = blockIdx.x;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double v = 0.0;
+    if (i < c) {
+      v = (betas[i] < 0.0 ? -1.0 : 1.0) * Wk[(int64_t)c * s + i];
+    } else if (i == c) {
+      const double b = betas[c];
+      v = (b != 0.0) ? fabs(b) : NAN;
+    }
+    R[(int64_t)c * ldr + i] = v;
+  }
+  if (c == 0 && threadIdx.x == 0 && info) {
+    int bad = 0;
+    for (int k = 0; k < n && !bad; ++k)
+      if (!(betas[k] != 0.0)) bad = k + 1;
+    if (bad && *info == 0) *info = 1000 + bad;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_copy_cols(int s, int n, const double* __restrict__ B,
+                                                   int64_t ldb, double* __restrict__ Wk) {
+  const int c = blockIdx.x;
+  for (int i = threadIdx.x; i < s; i += blockDim.x) Wk[(int64_t)c * s + i] = B[(int64_t)c * ldb + i];
+}
+
 // ========================================================== partial-pivot LU =========
 // Pivot: first row index of the largest |b_ik| among rows i >= k (NaN counts as largest).
 __device__ __forceinline__ bool piv_better(double a, int ia, double b, int ib) {
@@ -538,6 +758,122 @@ __global__ __launch_bounds__(kSmallThreads) void k_potrf_glb(int n, const double
   if (threadIdx.x == 0 && info && fail_sh >= 0 && *info == 0) *info = 1000 * stage + fail_sh + 1;
 }
 
+// Blocked Cholesky in one workgroup, in place in R (ld ldr): the upper triangle of W (plus
+// `shift` on the diagonal) is copied to R, then for each panel of NB columns
+//  (a) one wavefront factors the NB x NB diagonal block: lane c keeps column c in
+//      registers, and row k of the factor is published in LDS (one wavefront: no barrier);
+//  (b) the panel row R12 = R11^{-T} W12 by forward substitution, one thread per column;
+//  (c) the trailing update W22 -= R12^T R12 on FP64 MFMA (upper 16x16 tiles, round-robin
+//      over the wavefronts; operand layout as in the Gram kernel), read-modify-write in R.
+// Three barriers per panel instead of one per column.  LDS: potrf_blk_lds_doubles(n).
+template <int NB>
+__host__ __device__ constexpr size_t potrf_blk_lds_doubles(int n) {
+  return (size_t)NB * (NB + 1) + (size_t)NB * (n + 1);
+}
+
+template <int NB>
+__global__ __launch_bounds__(kSmallThreads) void k_potrf_blk(int n, const double* __restrict__ W,
+                                                             int64_t ldw, double* R, int64_t ldr,
+                                                             int stage, int* __restrict__ info,
+                                                             double shift) {
+  extern __shared__ double sm[];
+  constexpr int LDD = NB + 1;
+  double* D = sm;                  // D[k * LDD + c] = R11(k, c)
+  double* Pn = sm + NB * LDD;      // Pn[k * ldpn + c] = R12(k, c), zero-padded rows/cols
+  const int ldpn = n + 1;
+  __shared__ int fail_sh;
+  const int lane = lane_id(), wave = wave_id();
+  const int q = lane >> 4, c16 = lane & 15;
+  for (int c = wave; c < n; c += kSmallWaves)
+    for (int i = lane; i < n; i += kWave)
+      R[(int64_t)c * ldr + i] = (i <= c) ? W[(int64_t)c * ldw + i] + (i == c ? shift : 0.0) : 0.0;
+  if (threadIdx.x == 0) fail_sh = -1;
+  __syncthreads();
+
+  for (int j0 = 0; j0 < n; j0 += NB) {
+    const int b = min(NB, n - j0), t = n - j0 - b;
+    // (a) diagonal block
+    if (wave == 0) {
+      const int c = lane;
+      const bool cok = c < b;
+      double col[NB];
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        col[i] = (cok && i <= c) ? R[(int64_t)(j0 + c) * ldr + j0 + i] : 0.0;
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        if (k < b) {
+          const double dkk = __shfl(col[k], k, kWave);
+          const bool ok = dkk > 0.0;
+          const double rkk = ok ? sqrt(dkk) : NAN;
+          if (!ok && lane == 0 && fail_sh < 0) fail_sh = j0 + k;
+          double rkc = 0.0;
+          if (c == k) rkc = rkk;
+          else if (c > k && cok) rkc = col[k] / rkk;
+          col[k] = rkc;
+          if (c < NB) D[k * LDD + c] = rkc;
+          __builtin_amdgcn_wave_barrier();  // row k is read below by every lane
+#pragma unroll
+          for (int i = k + 1; i < NB; ++i)
+            if (i <= c && cok) col[i] -= D[k * LDD + i] * rkc;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        if (cok && i <= c) R[(int64_t)(j0 + c) * ldr + j0 + i] = col[i];
+    }
+    __syncthreads();
+    // (b) panel row R12 (rows j0 .. j0+b-1 of the trailing columns)
+    const int t16 = (t + 15) & ~15;
+    for (int tc = threadIdx.x; tc < t16; tc += kSmallThreads) {
+      if (tc < t) {
+        const int cg = j0 + b + tc;
+        double x[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) x[i] = (i < b) ? R[(int64_t)cg * ldr + j0 + i] : 0.0;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          if (i < b) {
+            double acc = x[i];
+#pragma unroll
+            for (int k = 0; k < i; ++k) acc -= D[k * LDD + i] * x[k];
+            x[i] = acc / D[i * LDD + i];
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          if (i < b) R[(int64_t)cg * ldr + j0 + i] = x[i];
+          Pn[i * ldpn + tc] = (i < b) ? x[i] : 0.0;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) Pn[i * ldpn + tc] = 0.0;
+      }
+    }
+    __syncthreads();
+    // (c) trailing update of the upper tiles
+    const int tt = t16 / 16;
+    for (int tile = wave; tile < tt * (tt + 1) / 2; tile += kSmallWaves) {
+      int tb = 0;
+      while ((tb + 1) * (tb + 2) / 2 <= tile) ++tb;
+      const int ta = tile - tb * (tb + 1) / 2;
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < NB / 4; ++kk)
+        acc = mfma_f64(Pn[(4 * kk + q) * ldpn + 16 * ta + c16],
+                       Pn[(4 * kk + q) * ldpn + 16 * tb + c16], acc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * ta + 4 * r + q, col = 16 * tb + c16;
+        if (row < t && col < t && row <= col)
+          R[(int64_t)(j0 + b + col) * ldr + j0 + b + row] -= acc[r];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && info && fail_sh >= 0 && *info == 0) *info = 1000 * stage + fail_sh + 1;
+}
+
 // ============================================================ small products =========
 // C = A B for upper-triangular A, B: one 16x16 output tile per workgroup, operands
 // staged through LDS in 16-wide chunks of the inner index (only k in [i0, j0+16)).
@@ -660,6 +996,45 @@ static int pow2_at_least(int x) {
   return p;
 }
 
+size_t sketch_factor_scratch_doubles(int s, int n) {
+  return (size_t)s * n + (size_t)32 * s + 32 * 32 + (size_t)n;
+}
+
+template <int NB, int RPL>
+static hipError_t qr_blocked_t(int s, int n, const double* B, int64_t ldb, double* R,
+                               int64_t ldr, int* info, double* scratch, hipStream_t st) {
+  double* Wk = scratch;
+  double* Vb = Wk + (size_t)s * n;
+  double* Tb = Vb + (size_t)s * NB;
+  double* betas = Tb + NB * NB;
+  hipLaunchKernelGGL(k_copy_cols, dim3(n), dim3(256), 0, st, s, n, B, ldb, Wk);
+  constexpr int kCpb = 8;  // trailing columns per update workgroup
+  for (int j0 = 0; j0 < n; j0 += NB) {
+    const int w = (n - j0) < NB ? (n - j0) : NB;
+    const int p = s - j0;
+    hipLaunchKernelGGL(k_qr_panel<NB>, dim3(1), dim3(kSmallThreads),
+                       qr_panel_lds_doubles<NB>(p) * sizeof(double), st, s, n, j0, Wk, Vb, Tb,
+                       betas);
+    const int rest = n - j0 - w;
+    if (rest > 0)
+      hipLaunchKernelGGL((k_qr_update<NB, RPL>), dim3((rest + kCpb - 1) / kCpb), dim3(256),
+                         ((size_t)NB * p + NB * NB) * sizeof(double), st, s, n, j0, w, kCpb, Vb,
+                         Tb, Wk);
+  }
+  hipLaunchKernelGGL(k_qr_finish, dim3(n), dim3(256), 0, st, s, n, Wk, betas, R, ldr, info);
+  return hipGetLastError();
+}
+
+// Blocked Householder QR for s <= 2048; the panel width keeps a panel (and the update's
+// copy of V) within 136 KiB of LDS.
+static hipError_t launch_qr_blocked(int s, int n, const double* B, int64_t ldb, double* R,
+                                    int64_t ldr, int* info, double* scratch, hipStream_t st) {
+  if (s <= 512) return qr_blocked_t<32, 8>(s, n, B, ldb, R, ldr, info, scratch, st);
+  if (s <= 1024) return qr_blocked_t<16, 16>(s, n, B, ldb, R, ldr, info, scratch, st);
+  if (s <= 2048) return qr_blocked_t<8, 32>(s, n, B, ldb, R, ldr, info, scratch, st);
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_sketch_factor(int variant, int s, int n, const double* B, int64_t ldb,
                                 double* R, int64_t ldr, int* info, double* scratch,
                                 hipStream_t st) {
@@ -681,6 +1056,7 @@ hipError_t launch_sketch_factor(int variant, int s, int n, const double* B, int6
   TSQR_FAC(8, 1) TSQR_FAC(8, 2) TSQR_FAC(8, 4)
 #undef TSQR_FAC
   if (s > kMaxS) return hipErrorInvalidValue;
+  if (variant == 0 && s <= 2048) return launch_qr_blocked(s, n, B, ldb, R, ldr, info, scratch, st);
   if (variant == 1) {
     const size_t sh = (size_t)(2 * s + n) * sizeof(double) + 2 * sizeof(int);
     hipLaunchKernelGGL(k_getrf_glb, grid, block, sh, st, s, n, B, ldb, R, ldr, info, scratch);
@@ -700,6 +1076,11 @@ hipError_t launch_potrf(int n, const double* W, int64_t ldw, double* R, int64_t 
     hipLaunchKernelGGL((k_potrf_reg<RPL_, CPW_>), grid, block, 0, st, n, W, ldw, R, ldr, stage, \
                        info, shift);                                                           \
     return hipGetLastError();                                                                  \
+  }
+  if (n > 64 && n <= 512) {
+    hipLaunchKernelGGL(k_potrf_blk<32>, grid, block, potrf_blk_lds_doubles<32>(n) * sizeof(double),
+                       st, n, W, ldw, R, ldr, stage, info, shift);
+    return hipGetLastError();
   }
   TSQR_POTRF(1, 1) TSQR_POTRF(1, 2) TSQR_POTRF(1, 4) TSQR_POTRF(2, 8)
 #undef TSQR_POTRF

@@ -54,7 +54,12 @@ Layout make_layout(int64_t m, int64_t n, int64_t s) {
   L.R2 = off; off += align256(nn);
   L.R10 = off; off += align256(nn);
   L.W = off; off += align256(nn);
-  L.fac = off; off += align256((size_t)(s > n ? s : n) * n * sizeof(double));
+  {
+    const size_t f = sketch_factor_scratch_doubles((int)s, (int)n);
+    const size_t nn2 = (size_t)n * n;
+    L.fac = off;
+    off += align256((f > nn2 ? f : nn2) * sizeof(double));
+  }
   L.Tt = off; off += align256(trsm_scratch_doubles((int)n) * sizeof(double));
   L.part = off;
   const size_t part = L.sp.part_doubles > L.gp.part_doubles ? L.sp.part_doubles : L.gp.part_doubles;
@@ -562,6 +567,11 @@ int tsqr_sketch(int64_t m, int64_t n, const double* A, int64_t lda, int64_t s, u
   return TSQR_OK;
 }
 
+size_t tsqr_sketch_factor_workspace_bytes(int64_t s, int64_t n) {
+  if (n < 1 || s < n || s > kMaxSketchRows) return 0;
+  return sketch_factor_scratch_doubles((int)s, (int)n) * sizeof(double);
+}
+
 int tsqr_sketch_factor(int variant, int64_t s, int64_t n, const double* B, int64_t ldb,
                        double* R0, int64_t ldr, int* d_info, void* work, size_t work_bytes,
                        void* stream) {
@@ -572,7 +582,8 @@ int tsqr_sketch_factor(int variant, int64_t s, int64_t n, const double* B, int64
   if (ldb < s) return -5;
   if (!R0) return -6;
   if (ldr < n) return -7;
-  if (!work || work_bytes < (size_t)s * n * sizeof(double)) return TSQR_ERR_WORKSPACE;
+  if (!work || work_bytes < sketch_factor_scratch_doubles((int)s, (int)n) * sizeof(double))
+    return TSQR_ERR_WORKSPACE;
   if (launch_sketch_factor(variant, (int)s, (int)n, B, ldb, R0, ldr, d_info, (double*)work,
                            (hipStream_t)stream) != hipSuccess)
     return TSQR_ERR_HIP;

@@ -48,7 +48,8 @@ size_t trsm_scratch_doubles(int n);
 hipError_t launch_trsm(int64_t m, int n, const double* Y, int64_t ldy, const double* T,
                        int64_t ldt, double* X, int64_t ldx, double* scratch, hipStream_t st);
 // R0 from the s x n sketch: Householder (variant 0) or partial-pivot LU (variant 1);
-// `scratch` holds s*n doubles for the large-size fallback.
+// `scratch` holds sketch_factor_scratch_doubles(s, n) doubles.
+size_t sketch_factor_scratch_doubles(int s, int n);
 hipError_t launch_sketch_factor(int variant, int s, int n, const double* B, int64_t ldb,
                                 double* R, int64_t ldr, int* info, double* scratch,
                                 hipStream_t st);

@@ -89,7 +89,8 @@ def test_sketch_leading_dimension_and_determinism():
 # ---------------------------------------------------------------------- small factors --
 @pytest.mark.parametrize("variant", [tsqr.RQR, tsqr.RLU])
 @pytest.mark.parametrize("s,n,kappa", [(64, 32, 1e4), (256, 128, 1e8), (40, 40, 1e3), (9, 1, 1.0),
-                                       (300, 150, 1e5), (512, 256, 1e6), (130, 65, 1e2)])
+                                       (300, 150, 1e5), (512, 256, 1e6), (130, 65, 1e2),
+                                       (1000, 100, 1e5), (1536, 700, 1e4), (512, 200, 1e12)])
 def test_sketch_factor_parity(variant, s, n, kappa):
     """R0 is the unique (sign-normalised) R or U factor: ||dR0||/||R0|| <= c n u kappa(B)."""
     B = gen_matrix(s, n, kappa, 17 + s)
@@ -157,7 +158,7 @@ def test_gram_parity(m, n):
 
 
 # ------------------------------------------------------------------------ Cholesky ----
-@pytest.mark.parametrize("n", [1, 5, 16, 32, 64, 100, 128, 129, 256])
+@pytest.mark.parametrize("n", [1, 5, 16, 32, 64, 65, 100, 128, 129, 200, 256])
 def test_potrf_parity(n):
     """R^T R = W to c n u ||W||; R agrees with the oracle within c n u cond(W)."""
     X = gen_matrix(4 * n + 10, n, 30.0, n)
@@ -181,6 +182,20 @@ def test_potrf_breakdown_and_upper_only():
     Rh = host(R)
     assert np.all(np.isnan(Rh[3:, 3:][np.triu_indices(3)]))
     assert np.array_equal(Rh[:3, :3], np.eye(3))
+
+
+def test_potrf_breakdown_blocked_panel():
+    """Breakdown inside the second 32-column panel of the blocked factorization."""
+    n = 200
+    W = np.eye(n)
+    W[40, 40] = -1.0
+    W[150, 3] = 77.0  # lower garbage is ignored
+    R, info = tsqr.potrf(dev(np.asfortranarray(W)), stage=3)
+    assert int(info.item()) == 3041
+    Rh = host(R)
+    assert np.all(np.isnan(Rh[40:, 40:][np.triu_indices(n - 40)]))
+    assert np.array_equal(Rh[:40, :40], np.eye(40))
+    assert np.all(np.tril(Rh, -1) == 0)
 
 
 def test_trmm_parity():
