@@ -254,7 +254,7 @@ __host__ __device__ constexpr size_t qr_panel_lds_doubles(int p) {
   return (size_t)NB * (p + 1) + 2 * NB * NB + 2 * NB;
 }
 
-template <int NB>
+template <int NB, int PR>  // PR: rows per lane, s <= 64 PR
 __global__ __launch_bounds__(kSmallThreads) void k_qr_panel(int s, int n, int j0,
                                                             double* __restrict__ Wk,
                                                             double* __restrict__ Vb,
@@ -276,12 +276,24 @@ __global__ __launch_bounds__(kSmallThreads) void k_qr_panel(int s, int n, int j0
   auto reflector = [&](int k) {
     double* x = P + k * ldp;
     double part = 0.0;
-    for (int i = k + 1 + lane; i < p; i += kWave) part += x[i] * x[i];
+    for (int r0 = 0; r0 < PR; r0 += 8) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int i = k + 1 + lane + kWave * (r0 + r);
+        if (i < p) part += x[i] * x[i];
+      }
+    }
     const double xnorm2 = wave_sum(part);
     const double alpha = x[k];
     double beta, tk, scal;
     house(alpha, xnorm2, beta, tk, scal);
-    for (int i = k + 1 + lane; i < p; i += kWave) x[i] *= scal;
+    for (int r0 = 0; r0 < PR; r0 += 8) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int i = k + 1 + lane + kWave * (r0 + r);
+        if (i < p) x[i] *= scal;
+      }
+    }
     if (lane == 0) {
       x[k] = 1.0;
       tau[k] = tk;
@@ -298,9 +310,21 @@ __global__ __launch_bounds__(kSmallThreads) void k_qr_panel(int s, int n, int j0
     auto apply = [&](int c) {
       double* y = P + c * ldp;
       double d = 0.0;
-      for (int i = k + lane; i < p; i += kWave) d += x[i] * y[i];
+      for (int r0 = 0; r0 < PR; r0 += 8) {  // eight rows per lane in flight
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const int i = k + lane + kWave * (r0 + r);
+          if (i < p) d += x[i] * y[i];
+        }
+      }
       const double wv = wave_sum(d) * tk;
-      for (int i = k + lane; i < p; i += kWave) y[i] -= x[i] * wv;
+      for (int r0 = 0; r0 < PR; r0 += 8) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const int i = k + lane + kWave * (r0 + r);
+          if (i < p) y[i] -= x[i] * wv;
+        }
+      }
     };
     if (wave == 0) {
       if (k + 1 < w) {
@@ -317,7 +341,13 @@ __global__ __launch_bounds__(kSmallThreads) void k_qr_panel(int s, int n, int j0
     const int j = t / w, k = t % w;
     if (j >= k) continue;
     double d = 0.0;
-    for (int i = k + lane; i < p; i += kWave) d += P[j * ldp + i] * P[k * ldp + i];
+    for (int r0 = 0; r0 < PR; r0 += 8) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int i = k + lane + kWave * (r0 + r);
+        if (i < p) d += P[j * ldp + i] * P[k * ldp + i];
+      }
+    }
     d = wave_sum(d);
     if (lane == 0) G[j * NB + k] = d;
   }
@@ -327,6 +357,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_qr_panel(int s, int n, int j0
     for (int k = 0; k < w; ++k) {
       if (lane < k) {
         double z = 0.0;
+#pragma unroll 8
         for (int i = lane; i < k; ++i) z += T[lane * NB + i] * G[i * NB + k];
         T[lane * NB + k] = -tau[k] * z;
       } else if (lane == k) {
@@ -349,7 +380,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_qr_panel(int s, int n, int j0
 }
 
 template <int NB, int RPL>
-__global__ __launch_bounds__(256) void k_qr_update(int s, int n, int j0, int w, int cpb,
+__global__ __launch_bounds__(512) void k_qr_update(int s, int n, int j0, int w, int cpb,
                                                    const double* __restrict__ Vb,
                                                    const double* __restrict__ Tb,
                                                    double* __restrict__ Wk) {
@@ -771,6 +802,8 @@ __host__ __device__ constexpr size_t potrf_blk_lds_doubles(int n) {
   return (size_t)NB * (NB + 1) + (size_t)NB * (n + 1);
 }
 
+constexpr int kTiles = 4;  // trailing tiles a wavefront updates together
+
 template <int NB>
 __global__ __launch_bounds__(kSmallThreads) void k_potrf_blk(int n, const double* __restrict__ W,
                                                              int64_t ldw, double* R, int64_t ldr,
@@ -784,9 +817,25 @@ __global__ __launch_bounds__(kSmallThreads) void k_potrf_blk(int n, const double
   __shared__ int fail_sh;
   const int lane = lane_id(), wave = wave_id();
   const int q = lane >> 4, c16 = lane & 15;
-  for (int c = wave; c < n; c += kSmallWaves)
-    for (int i = lane; i < n; i += kWave)
-      R[(int64_t)c * ldr + i] = (i <= c) ? W[(int64_t)c * ldw + i] + (i == c ? shift : 0.0) : 0.0;
+  {
+    // upper triangle of W (+ shift) into R, zeros below; eight loads in flight per thread
+    const int total = n * n;
+    for (int e0 = threadIdx.x; e0 < total; e0 += 8 * kSmallThreads) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kSmallThreads;
+        const int c = e / n, i = e - c * n;
+        v[u] = (e < total && i <= c) ? W[(int64_t)c * ldw + i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kSmallThreads;
+        const int c = e / n, i = e - c * n;
+        if (e < total) R[(int64_t)c * ldr + i] = v[u] + (i == c ? shift : 0.0);
+      }
+    }
+  }
   if (threadIdx.x == 0) fail_sh = -1;
   __syncthreads();
 
@@ -803,7 +852,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_potrf_blk(int n, const double
 #pragma unroll
       for (int k = 0; k < NB; ++k) {
         if (k < b) {
-          const double dkk = __shfl(col[k], k, kWave);
+          const double dkk = readlane_f64(col[k], k);
           const bool ok = dkk > 0.0;
           const double rkk = ok ? sqrt(dkk) : NAN;
           if (!ok && lane == 0 && fail_sh < 0) fail_sh = j0 + k;
@@ -851,22 +900,43 @@ __global__ __launch_bounds__(kSmallThreads) void k_potrf_blk(int n, const double
       }
     }
     __syncthreads();
-    // (c) trailing update of the upper tiles
+    // (c) trailing update of the upper tiles: a wavefront's tiles (at most kTiles) are
+    // read first, updated on the matrix cores, then written, so their memory latencies
+    // overlap instead of adding up
     const int tt = t16 / 16;
-    for (int tile = wave; tile < tt * (tt + 1) / 2; tile += kSmallWaves) {
-      int tb = 0;
-      while ((tb + 1) * (tb + 2) / 2 <= tile) ++tb;
-      const int ta = tile - tb * (tb + 1) / 2;
-      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+    const int ntile = tt * (tt + 1) / 2;
+    for (int base = wave; base < ntile; base += kTiles * kSmallWaves) {
+      int ta[kTiles], tb[kTiles];
+      double old[kTiles][4];
 #pragma unroll
-      for (int kk = 0; kk < NB / 4; ++kk)
-        acc = mfma_f64(Pn[(4 * kk + q) * ldpn + 16 * ta + c16],
-                       Pn[(4 * kk + q) * ldpn + 16 * tb + c16], acc);
+      for (int u = 0; u < kTiles; ++u) {
+        const int tile = base + u * kSmallWaves;
+        int b2 = 0;
+        while ((b2 + 1) * (b2 + 2) / 2 <= tile) ++b2;
+        tb[u] = b2;
+        ta[u] = tile - b2 * (b2 + 1) / 2;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = 16 * ta + 4 * r + q, col = 16 * tb + c16;
-        if (row < t && col < t && row <= col)
-          R[(int64_t)(j0 + b + col) * ldr + j0 + b + row] -= acc[r];
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * ta[u] + 4 * r + q, col = 16 * tb[u] + c16;
+          const bool ok = tile < ntile && row < t && col < t && row <= col;
+          old[u][r] = ok ? R[(int64_t)(j0 + b + col) * ldr + j0 + b + row] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kTiles; ++u) {
+        const int tile = base + u * kSmallWaves;
+        if (tile >= ntile) continue;
+        v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < NB / 4; ++kk)
+          acc = mfma_f64(Pn[(4 * kk + q) * ldpn + 16 * ta[u] + c16],
+                         Pn[(4 * kk + q) * ldpn + 16 * tb[u] + c16], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * ta[u] + 4 * r + q, col = 16 * tb[u] + c16;
+          if (row < t && col < t && row <= col)
+            R[(int64_t)(j0 + b + col) * ldr + j0 + b + row] = old[u][r] - acc[r];
+        }
       }
     }
     __syncthreads();
@@ -1008,16 +1078,16 @@ static hipError_t qr_blocked_t(int s, int n, const double* B, int64_t ldb, doubl
   double* Tb = Vb + (size_t)s * NB;
   double* betas = Tb + NB * NB;
   hipLaunchKernelGGL(k_copy_cols, dim3(n), dim3(256), 0, st, s, n, B, ldb, Wk);
-  constexpr int kCpb = 8;  // trailing columns per update workgroup
+  constexpr int kCpb = 8;  // trailing columns per update workgroup (one per wavefront)
   for (int j0 = 0; j0 < n; j0 += NB) {
     const int w = (n - j0) < NB ? (n - j0) : NB;
     const int p = s - j0;
-    hipLaunchKernelGGL(k_qr_panel<NB>, dim3(1), dim3(kSmallThreads),
+    hipLaunchKernelGGL((k_qr_panel<NB, RPL>), dim3(1), dim3(kSmallThreads),
                        qr_panel_lds_doubles<NB>(p) * sizeof(double), st, s, n, j0, Wk, Vb, Tb,
                        betas);
     const int rest = n - j0 - w;
     if (rest > 0)
-      hipLaunchKernelGGL((k_qr_update<NB, RPL>), dim3((rest + kCpb - 1) / kCpb), dim3(256),
+      hipLaunchKernelGGL((k_qr_update<NB, RPL>), dim3((rest + kCpb - 1) / kCpb), dim3(512),
                          ((size_t)NB * p + NB * NB) * sizeof(double), st, s, n, j0, w, kCpb, Vb,
                          Tb, Wk);
   }
