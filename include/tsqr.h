@@ -152,6 +152,50 @@ int tsqr_gram_lowp(int lowp, int64_t m, int64_t n, const void* X, int64_t ldx, d
                    int64_t ldw, void* work, size_t work_bytes, void* stream);
 
 /* ------------------------------------------------------------------------------------
+ * Batched factorizations: many independent problems of uneven sizes in one pass
+ * ------------------------------------------------------------------------------------
+ * Each problem is factored exactly as by tsqr_rxr_cholqr_ws with extra_pass = 1 (the
+ * method of the paper's Algorithm rQR- or rLU-CholeskyQR with the Gaussian sketch of
+ * Section 2.3 and one more CholeskyQR pass); the split-K blockings differ from the
+ * single-problem calls, so results agree with them to rounding, not bitwise.
+ * Limits: 1 <= n <= 128, n <= s <= 512 (s <= 256 when n > 64), m >= n; any other problem
+ * makes the create call return -3. */
+typedef struct {
+  int64_t m, n;        /* rows and columns of A */
+  int64_t lda;         /* leading dimension of A (>= m) */
+  int64_t s;           /* sketch rows */
+  uint64_t seed;       /* sketch seed (stream as for the single-problem calls) */
+  const double* A;     /* device, read only */
+  double* Q;           /* device output, ld ldq >= m, must not overlap A */
+  int64_t ldq;
+  double* R;           /* device output (ld ldr >= n) or NULL */
+  int64_t ldr;
+} tsqr_problem;
+
+typedef struct tsqr_batch tsqr_batch; /* opaque plan */
+
+/* Workspace bytes for a batch (0 if any problem is invalid).  `problems` is a host array. */
+size_t tsqr_batched_workspace_bytes(int64_t count, const tsqr_problem* problems);
+
+/* Plan a batch: groups the problems by width, sizes their blockings, lays out `work` and
+ * uploads the problem descriptors and work lists into it (synchronously).  Arguments:
+ * variant (1), count (2), problems (3, host array, not kept), work / work_bytes (4, 5),
+ * d_info (6: device int[count], one breakdown code per problem as for tsqr_rxr_cholqr_ws),
+ * out (7: receives the plan).  The plan refers to `work`, `d_info` and the problems' device
+ * buffers: they must stay valid and unmoved while the plan is used. */
+int tsqr_batched_create(int variant, int64_t count, const tsqr_problem* problems, void* work,
+                        size_t work_bytes, int* d_info, tsqr_batch** out);
+
+/* Enqueue the whole batch on `stream`.  Kernel launches only (no allocation, copy or host
+ * synchronisation), so a stream capture of this call records the batch as one graph. */
+int tsqr_batched_run(tsqr_batch* plan, void* stream);
+
+/* Number of kernel launches one run enqueues (one per phase and width class). */
+int tsqr_batched_launches(const tsqr_batch* plan);
+
+void tsqr_batched_destroy(tsqr_batch* plan);
+
+/* ------------------------------------------------------------------------------------
  * Steps of the method, one entry point per step (used for step-wise validation)
  * ------------------------------------------------------------------------------------ */
 

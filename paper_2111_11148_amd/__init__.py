@@ -57,6 +57,11 @@ _SIGS = {
     "tsqr_apply_rinv_lowp": (_int, [_int, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz,
                                     _vp]),
     "tsqr_gram_lowp": (_int, [_int, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp]),
+    "tsqr_batched_workspace_bytes": (_sz, [_i64, _vp]),
+    "tsqr_batched_create": (_int, [_int, _i64, _vp, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
+    "tsqr_batched_run": (_int, [_vp, _vp]),
+    "tsqr_batched_launches": (_int, [_vp]),
+    "tsqr_batched_destroy": (None, [_vp]),
     "tsqr_profile_start": (_int, []),
     "tsqr_profile_stop": (_int, []),
     "tsqr_profile_record": (_int, [_int, ctypes.POINTER(ctypes.c_char_p),
@@ -392,3 +397,62 @@ def sketch_normals(seed: int, i0: int, ni: int, j0: int, nj: int, device="cuda",
     _check(load().tsqr_sketch_normals(seed, i0, ni, j0, nj, Z.data_ptr(), max(ni, 1),
                                       _stream(stream)), "tsqr_sketch_normals")
     return Z
+
+
+# ------------------------------------------------------------------------------ batched ----
+class _Problem(ctypes.Structure):
+    """Mirror of tsqr_problem (include/tsqr.h)."""
+    _fields_ = [("m", _i64), ("n", _i64), ("lda", _i64), ("s", _i64), ("seed", _u64),
+                ("A", _vp), ("Q", _vp), ("ldq", _i64), ("R", _vp), ("ldr", _i64)]
+
+
+class Batch:
+    """A planned batch of independent factorizations (tsqr_batched_create).
+
+    As: list of column-major FP64 device matrices; sketch_rows, seeds: per problem (ints or
+    lists).  Q (and R unless want_r is False) are allocated here and kept alive with the
+    plan, which refers to them.  run() enqueues the whole batch (kernel launches only, so it
+    may be captured into a HIP graph); info is a (count,) int32 device tensor."""
+
+    def __init__(self, As, sketch_rows, seeds, variant: int = RQR, want_r: bool = True):
+        count = len(As)
+        if count < 1:
+            raise ValueError("empty batch")
+        s_list = list(sketch_rows) if hasattr(sketch_rows, "__len__") else [sketch_rows] * count
+        seed_list = list(seeds) if hasattr(seeds, "__len__") else [seeds] * count
+        dev = As[0].device
+        self.A, self.Q, self.R = list(As), [], []
+        probs = (_Problem * count)()
+        for i, A in enumerate(self.A):
+            lda = _mat(A, f"A[{i}]")
+            m, n = A.shape
+            Q = colmajor(m, n, device=dev)
+            R = colmajor(n, n, device=dev) if want_r else None
+            self.Q.append(Q)
+            self.R.append(R)
+            probs[i] = _Problem(m, n, lda, s_list[i], seed_list[i], A.data_ptr(), Q.data_ptr(), m,
+                                R.data_ptr() if R is not None else None, n)
+        nbytes = int(load().tsqr_batched_workspace_bytes(count, ctypes.cast(probs, _vp)))
+        if nbytes == 0:
+            raise ValueError("invalid problem in the batch")
+        self.work = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.info = torch.zeros(count, dtype=torch.int32, device=dev)
+        plan = _vp()
+        _check(load().tsqr_batched_create(variant, count, ctypes.cast(probs, _vp),
+                                          self.work.data_ptr(), nbytes, self.info.data_ptr(),
+                                          ctypes.byref(plan)), "tsqr_batched_create")
+        self._plan = plan
+        self.count = count
+
+    def run(self, stream=None):
+        _check(load().tsqr_batched_run(self._plan, _stream(stream)), "tsqr_batched_run")
+
+    @property
+    def launches(self) -> int:
+        return int(load().tsqr_batched_launches(self._plan))
+
+    def __del__(self):
+        plan = getattr(self, "_plan", None)
+        if plan is not None and plan.value is not None and _lib is not None:
+            _lib.tsqr_batched_destroy(plan)
+            self._plan = None

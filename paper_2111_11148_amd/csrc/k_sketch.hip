@@ -14,10 +14,14 @@
 
 namespace tsqr {
 
+// Body of one workgroup: row block bx, i-tile group by, column group bz (the kernel's
+// blockIdx; the batched kernel supplies them from its work list).
 template <int IT, int JT, int NW>
-__global__ __launch_bounds__(NW * 64) void k_sketch_f64(
-    int64_t m, int n, const double* __restrict__ A, int64_t lda, uint32_t k0, uint32_t k1,
-    int64_t rows_per_block, int it_total, int jt_total, double* __restrict__ part) {
+__device__ __forceinline__ void sketch_f64_body(int64_t m, int n, const double* __restrict__ A,
+                                                int64_t lda, uint32_t k0, uint32_t k1,
+                                                int64_t rows_per_block, int it_total,
+                                                int jt_total, double* __restrict__ part, int bx,
+                                                int by, int bz) {
   constexpr int KC = 32;          // rows of A per LDS chunk
   constexpr int NC = JT * 16;     // columns of A per workgroup
   constexpr int LDN = NC + 1;     // padded row length of the LDS chunk (doubles)
@@ -28,10 +32,10 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_f64(
 
   const int lane = lane_id(), wave = wave_id();
   const int q = lane >> 4, c16 = lane & 15;
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r0 = (int64_t)bx * rows_per_block;
   const int64_t r1 = min(m, r0 + rows_per_block);
-  const int it0 = (int)blockIdx.y * (NW * IT) + wave * IT;
-  const int c0 = (int)blockIdx.z * NC;
+  const int it0 = by * (NW * IT) + wave * IT;
+  const int c0 = bz * NC;
 
   v4d acc[IT][JT];
 #pragma unroll
@@ -98,14 +102,14 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_f64(
   }
 
   const size_t E = (size_t)it_total * (size_t)jt_total * 256;
-  double* dst = part + (size_t)blockIdx.x * E;
+  double* dst = part + (size_t)bx * E;
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int itg = it0 + it;
     if (itg >= it_total) continue;
 #pragma unroll
     for (int jt = 0; jt < JT; ++jt) {
-      const int jtg = (int)blockIdx.z * JT + jt;
+      const int jtg = bz * JT + jt;
       if (jtg >= jt_total) continue;
       double* tp = dst + ((size_t)itg * jt_total + jtg) * 256 + lane * 4;
       *reinterpret_cast<v4d*>(tp) = acc[it][jt];
@@ -113,19 +117,26 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_f64(
   }
 }
 
+template <int IT, int JT, int NW>
+__global__ __launch_bounds__(NW * 64) void k_sketch_f64(
+    int64_t m, int n, const double* __restrict__ A, int64_t lda, uint32_t k0, uint32_t k1,
+    int64_t rows_per_block, int it_total, int jt_total, double* __restrict__ part) {
+  sketch_f64_body<IT, JT, NW>(m, n, A, lda, k0, k1, rows_per_block, it_total, jt_total, part,
+                              (int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z);
+}
+
 // B(i, c) = scale * sum_kb part[kb][tile(i,c)][lane][reg].  A 256-thread block handles 16
 // consecutive partial entries; thread group g (16 of them) sums the row blocks kb = g,
 // g+16, ... in increasing order and the 16 group sums are added in group order, so the
 // result does not depend on timing (deterministic).
-__global__ __launch_bounds__(256) void k_sketch_reduce(int kblocks, int it_total, int jt_total,
-                                                       int s, int n,
-                                                       const double* __restrict__ part,
-                                                       double scale, double* __restrict__ B,
-                                                       int64_t ldb) {
+__device__ __forceinline__ void sketch_reduce_body(int kblocks, int it_total, int jt_total, int s,
+                                                   int n, const double* __restrict__ part,
+                                                   double scale, double* __restrict__ B,
+                                                   int64_t ldb, int bx) {
   __shared__ double red[16][17];
   const size_t E = (size_t)it_total * jt_total * 256;
   const int g = threadIdx.x / 16, o = threadIdx.x % 16;
-  const size_t e = (size_t)blockIdx.x * 16 + o;
+  const size_t e = (size_t)bx * 16 + o;
   double acc = 0.0;
   if (e < E)
     for (int kb = g; kb < kblocks; kb += 16) acc += part[(size_t)kb * E + e];
@@ -139,6 +150,31 @@ __global__ __launch_bounds__(256) void k_sketch_reduce(int kblocks, int it_total
     const int i = 16 * itg + 4 * r + (lane >> 4), c = 16 * jtg + (lane & 15);
     if (i < s && c < n) B[(int64_t)c * ldb + i] = scale * t;
   }
+}
+
+__global__ __launch_bounds__(256) void k_sketch_reduce(int kblocks, int it_total, int jt_total,
+                                                       int s, int n,
+                                                       const double* __restrict__ part,
+                                                       double scale, double* __restrict__ B,
+                                                       int64_t ldb) {
+  sketch_reduce_body(kblocks, it_total, jt_total, s, n, part, scale, B, ldb, (int)blockIdx.x);
+}
+
+// --- batched forms ------------------------------------------------------------------------
+template <int IT, int JT, int NW>
+__global__ __launch_bounds__(NW * 64) void k_b_sketch(const BItem* __restrict__ items,
+                                                      const BProb* __restrict__ probs) {
+  const BItem it = items[blockIdx.x];
+  const BProb& p = probs[it.pid];
+  sketch_f64_body<IT, JT, NW>(p.m, p.n, p.A, p.lda, p.k0, p.k1, p.sk_rpb, p.sk_it, p.sk_jt, p.part,
+                              it.x, it.y, it.z);
+}
+
+__global__ __launch_bounds__(256) void k_b_sketch_reduce(const BItem* __restrict__ items,
+                                                         const BProb* __restrict__ probs) {
+  const BItem it = items[blockIdx.x];
+  const BProb& p = probs[it.pid];
+  sketch_reduce_body(p.sk_kblocks, p.sk_it, p.sk_jt, p.s, p.n, p.part, p.scale, p.B, p.s, it.x);
 }
 
 // --- debug / test kernels --------------------------------------------------------------
@@ -224,6 +260,30 @@ hipError_t launch_sketch_reduce(const SketchPlan& p, int s, int n, const double*
   const int blocks = (int)((E + 15) / 16);
   hipLaunchKernelGGL(k_sketch_reduce, dim3(blocks), dim3(256), 0, st, p.kblocks, p.it_total,
                      p.jt_total, s, n, part, scale, B, ldb);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_sketch(int IT, int JT, int NW, const BItem* items, int nitems,
+                           const BProb* probs, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+#define TSQR_BSK(IT_, JT_, NW_)                                                          \
+  if (IT == IT_ && JT == JT_ && NW == NW_) {                                             \
+    hipLaunchKernelGGL((k_b_sketch<IT_, JT_, NW_>), dim3(nitems), dim3(NW_ * 64), 0, st, items, \
+                       probs);                                                           \
+    return hipGetLastError();                                                            \
+  }
+  TSQR_BSK(1, 1, 4) TSQR_BSK(1, 2, 4) TSQR_BSK(1, 4, 4) TSQR_BSK(1, 8, 4)
+  TSQR_BSK(1, 1, 8) TSQR_BSK(1, 2, 8) TSQR_BSK(1, 4, 8) TSQR_BSK(1, 8, 8)
+  TSQR_BSK(2, 8, 4) TSQR_BSK(2, 8, 8) TSQR_BSK(2, 4, 8) TSQR_BSK(2, 4, 4)
+  TSQR_BSK(2, 2, 8) TSQR_BSK(2, 1, 8) TSQR_BSK(2, 2, 4) TSQR_BSK(2, 1, 4)
+#undef TSQR_BSK
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_b_sketch_reduce(const BItem* items, int nitems, const BProb* probs,
+                                  hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_sketch_reduce, dim3(nitems), dim3(256), 0, st, items, probs);
   return hipGetLastError();
 }
 

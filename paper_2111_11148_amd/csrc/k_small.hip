@@ -60,7 +60,7 @@ __device__ __forceinline__ void house(double alpha, double xnorm2, double& beta,
 
 // ================================================================ Householder QR ====
 template <int RPL, int CPW>
-__global__ __launch_bounds__(kSmallThreads) void k_geqrf_reg(int s, int n,
+__device__ __forceinline__ void geqrf_reg_body(int s, int n,
                                                              const double* __restrict__ B,
                                                              int64_t ldb, double* __restrict__ R,
                                                              int64_t ldr, int* __restrict__ info) {
@@ -149,6 +149,14 @@ __global__ __launch_bounds__(kSmallThreads) void k_geqrf_reg(int s, int n,
       if (!(betas[k] != 0.0)) bad = k + 1;
     if (bad && *info == 0) *info = 1000 + bad;
   }
+}
+
+template <int RPL, int CPW>
+__global__ __launch_bounds__(kSmallThreads) void k_geqrf_reg(int s, int n,
+                                                             const double* __restrict__ B,
+                                                             int64_t ldb, double* __restrict__ R,
+                                                             int64_t ldr, int* __restrict__ info) {
+  geqrf_reg_body<RPL, CPW>(s, n, B, ldb, R, ldr, info);
 }
 
 // Global-memory fallback (any s <= kMaxS, n <= s): matrix copied to scratch (ld s).
@@ -491,7 +499,7 @@ __device__ __forceinline__ void wave_argmax(double& v, int& idx) {
 }
 
 template <int RPL, int CPW>
-__global__ __launch_bounds__(kSmallThreads) void k_getrf_reg(int s, int n,
+__device__ __forceinline__ void getrf_reg_body(int s, int n,
                                                              const double* __restrict__ B,
                                                              int64_t ldb, double* __restrict__ R,
                                                              int64_t ldr, int* __restrict__ info) {
@@ -592,6 +600,14 @@ __global__ __launch_bounds__(kSmallThreads) void k_getrf_reg(int s, int n,
   }
 }
 
+template <int RPL, int CPW>
+__global__ __launch_bounds__(kSmallThreads) void k_getrf_reg(int s, int n,
+                                                             const double* __restrict__ B,
+                                                             int64_t ldb, double* __restrict__ R,
+                                                             int64_t ldr, int* __restrict__ info) {
+  getrf_reg_body<RPL, CPW>(s, n, B, ldb, R, ldr, info);
+}
+
 __global__ __launch_bounds__(kSmallThreads) void k_getrf_glb(int s, int n,
                                                              const double* __restrict__ B,
                                                              int64_t ldb, double* __restrict__ R,
@@ -681,7 +697,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_getrf_glb(int s, int n,
 // Reads only the upper triangle of W (the lower one is mirrored on load); `shift` is
 // added to the diagonal (shifted CholeskyQR; 0 for the plain factorization).
 template <int RPL, int CPW>
-__global__ __launch_bounds__(kSmallThreads) void k_potrf_reg(int n, const double* __restrict__ W,
+__device__ __forceinline__ void potrf_reg_body(int n, const double* __restrict__ W,
                                                              int64_t ldw, double* __restrict__ R,
                                                              int64_t ldr, int stage,
                                                              int* __restrict__ info,
@@ -740,6 +756,15 @@ __global__ __launch_bounds__(kSmallThreads) void k_potrf_reg(int n, const double
   }
   __syncthreads();
   if (threadIdx.x == 0 && info && fail_sh >= 0 && *info == 0) *info = 1000 * stage + fail_sh + 1;
+}
+
+template <int RPL, int CPW>
+__global__ __launch_bounds__(kSmallThreads) void k_potrf_reg(int n, const double* __restrict__ W,
+                                                             int64_t ldw, double* __restrict__ R,
+                                                             int64_t ldr, int stage,
+                                                             int* __restrict__ info,
+                                                             double shift) {
+  potrf_reg_body<RPL, CPW>(n, W, ldw, R, ldr, stage, info, shift);
 }
 
 __global__ __launch_bounds__(kSmallThreads) void k_potrf_glb(int n, const double* __restrict__ W,
@@ -947,12 +972,12 @@ __global__ __launch_bounds__(kSmallThreads) void k_potrf_blk(int n, const double
 // ============================================================ small products =========
 // C = A B for upper-triangular A, B: one 16x16 output tile per workgroup, operands
 // staged through LDS in 16-wide chunks of the inner index (only k in [i0, j0+16)).
-__global__ __launch_bounds__(256) void k_trmm_upper(int n, const double* __restrict__ A,
+__device__ __forceinline__ void trmm_upper_body(int n, const double* __restrict__ A,
                                                     int64_t lda, const double* __restrict__ B,
                                                     int64_t ldb, double* __restrict__ C,
-                                                    int64_t ldc) {
+                                                    int64_t ldc, int bx, int by) {
   __shared__ double as[16][17], bs[16][17];
-  const int i0 = 16 * blockIdx.y, j0 = 16 * blockIdx.x;
+  const int i0 = 16 * by, j0 = 16 * bx;
   const int ti = threadIdx.x % 16, tj = threadIdx.x / 16;
   const int i = i0 + ti, j = j0 + tj;
   double acc = 0.0;
@@ -970,18 +995,30 @@ __global__ __launch_bounds__(256) void k_trmm_upper(int n, const double* __restr
   if (i < n && j < n) C[(int64_t)j * ldc + i] = (i <= j) ? acc : 0.0;
 }
 
-__global__ void k_poison(const int* __restrict__ info, int64_t m, int n, double* Q, int64_t ldq,
-                         double* R, int64_t ldr) {
+__global__ __launch_bounds__(256) void k_trmm_upper(int n, const double* __restrict__ A,
+                                                    int64_t lda, const double* __restrict__ B,
+                                                    int64_t ldb, double* __restrict__ C,
+                                                    int64_t ldc) {
+  trmm_upper_body(n, A, lda, B, ldb, C, ldc, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+__device__ __forceinline__ void poison_body(const int* __restrict__ info, int64_t m, int n, double* Q, int64_t ldq,
+                         double* R, int64_t ldr, int bx, int nbx) {
   if (*info == 0) return;
   const int64_t tq = m * n, tr = R ? (int64_t)n * n : 0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tq + tr;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t e = (int64_t)bx * blockDim.x + threadIdx.x; e < tq + tr;
+       e += (int64_t)nbx * blockDim.x) {
     if (e < tq) Q[(e / m) * ldq + (e % m)] = NAN;
     else {
       const int64_t f = e - tq;
       R[(f / n) * ldr + (f % n)] = NAN;
     }
   }
+}
+
+__global__ void k_poison(const int* __restrict__ info, int64_t m, int n, double* Q, int64_t ldq,
+                         double* R, int64_t ldr) {
+  poison_body(info, m, n, Q, ldq, R, ldr, (int)blockIdx.x, (int)gridDim.x);
 }
 
 __global__ void k_set_int(int* p, int v) { *p = v; }
@@ -1200,6 +1237,104 @@ hipError_t launch_pass_decide(int n, const double* W, int64_t ldw, const int* lp
                               hipStream_t st) {
   hipLaunchKernelGGL(k_pass_decide, dim3(1), dim3(256), 0, st, n, W, ldw, lp_info, info, thresh,
                      need, dev_out);
+  return hipGetLastError();
+}
+
+// ---- batched forms ----------------------------------------------------------------------
+template <int RPL, int CPW>
+__global__ __launch_bounds__(kSmallThreads) void k_b_geqrf(const BItem* __restrict__ items,
+                                                           const BProb* __restrict__ probs) {
+  const BProb& p = probs[items[blockIdx.x].pid];
+  geqrf_reg_body<RPL, CPW>(p.s, p.n, p.B, p.s, p.R0, p.n, p.info);
+}
+
+template <int RPL, int CPW>
+__global__ __launch_bounds__(kSmallThreads) void k_b_getrf(const BItem* __restrict__ items,
+                                                           const BProb* __restrict__ probs) {
+  const BProb& p = probs[items[blockIdx.x].pid];
+  getrf_reg_body<RPL, CPW>(p.s, p.n, p.B, p.s, p.R0, p.n, p.info);
+}
+
+template <int RPL, int CPW>
+__global__ __launch_bounds__(kSmallThreads) void k_b_potrf(int which, int stage,
+                                                           const BItem* __restrict__ items,
+                                                           const BProb* __restrict__ probs) {
+  const BProb& p = probs[items[blockIdx.x].pid];
+  potrf_reg_body<RPL, CPW>(p.n, p.W, p.n, which == 1 ? p.R1 : p.R2, p.n, stage, p.info, 0.0);
+}
+
+__global__ __launch_bounds__(256) void k_b_trmm(int which, const BItem* __restrict__ items,
+                                                const BProb* __restrict__ probs) {
+  const BItem it = items[blockIdx.x];
+  const BProb& p = probs[it.pid];
+  if (which == 0)
+    trmm_upper_body(p.n, p.R1, p.n, p.R0, p.n, p.R10, p.n, it.x, it.y);
+  else if (p.R)
+    trmm_upper_body(p.n, p.R2, p.n, p.R10, p.n, p.R, p.ldr, it.x, it.y);
+}
+
+__global__ __launch_bounds__(256) void k_b_poison(const BItem* __restrict__ items,
+                                                  const BProb* __restrict__ probs) {
+  const BItem it = items[blockIdx.x];
+  const BProb& p = probs[it.pid];
+  poison_body(p.info, p.m, p.n, p.Q, p.ldq, p.R, p.ldr, it.x, p.poison_wgs);
+}
+
+__global__ void k_b_set_info(const BItem* __restrict__ items, const BProb* __restrict__ probs) {
+  if (threadIdx.x == 0) *probs[items[blockIdx.x].pid].info = 0;
+}
+
+hipError_t launch_b_factor(int variant, int RPL, int CPW, const BItem* items, int nitems,
+                           const BProb* probs, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+#define TSQR_BF(RPL_, CPW_)                                                                   \
+  if (RPL == RPL_ && CPW == CPW_) {                                                           \
+    if (variant == 1)                                                                         \
+      hipLaunchKernelGGL((k_b_getrf<RPL_, CPW_>), dim3(nitems), dim3(kSmallThreads), 0, st,    \
+                         items, probs);                                                       \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_b_geqrf<RPL_, CPW_>), dim3(nitems), dim3(kSmallThreads), 0, st,    \
+                         items, probs);                                                       \
+    return hipGetLastError();                                                                 \
+  }
+  TSQR_BF(1, 1) TSQR_BF(1, 2) TSQR_BF(1, 4) TSQR_BF(1, 8)
+  TSQR_BF(2, 1) TSQR_BF(2, 2) TSQR_BF(2, 4) TSQR_BF(2, 8)
+  TSQR_BF(4, 1) TSQR_BF(4, 2) TSQR_BF(4, 4) TSQR_BF(4, 8)
+  TSQR_BF(8, 1) TSQR_BF(8, 2) TSQR_BF(8, 4)
+#undef TSQR_BF
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_b_potrf(int RPL, int CPW, int which, int stage, const BItem* items,
+                          int nitems, const BProb* probs, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+#define TSQR_BP(RPL_, CPW_)                                                                   \
+  if (RPL == RPL_ && CPW == CPW_) {                                                           \
+    hipLaunchKernelGGL((k_b_potrf<RPL_, CPW_>), dim3(nitems), dim3(kSmallThreads), 0, st,      \
+                       which, stage, items, probs);                                           \
+    return hipGetLastError();                                                                 \
+  }
+  TSQR_BP(1, 1) TSQR_BP(1, 2) TSQR_BP(1, 4) TSQR_BP(2, 8)
+#undef TSQR_BP
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_b_trmm(int which, const BItem* items, int nitems, const BProb* probs,
+                         hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_trmm, dim3(nitems), dim3(256), 0, st, which, items, probs);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_poison(const BItem* items, int nitems, const BProb* probs, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_poison, dim3(nitems), dim3(256), 0, st, items, probs);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_set_info(const BItem* items, int nitems, const BProb* probs, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_set_info, dim3(nitems), dim3(64), 0, st, items, probs);
   return hipGetLastError();
 }
 

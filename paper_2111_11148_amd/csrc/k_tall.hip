@@ -50,9 +50,9 @@ __host__ __device__ constexpr size_t trsm_prep_doubles(int jt) {
   return (size_t)(jt * (jt - 1) / 2 + 2 * jt) * 256 + (size_t)(jt + 1) / 2 + 1;
 }
 
-__global__ __launch_bounds__(256) void k_trsm_prep(int n, int jt, const double* __restrict__ T,
-                                                   int64_t ldt, double* __restrict__ P) {
-  const int b = blockIdx.x;  // block column handled by this workgroup
+__device__ __forceinline__ void trsm_prep_body(int n, int jt, const double* __restrict__ T,
+                                               int64_t ldt, double* __restrict__ P, int b) {
+  // b: block column handled by this workgroup
   const int noff = jt * (jt - 1) / 2;
   auto Tg = [&](int i, int j) -> double {
     return (i < n && j < n) ? T[(int64_t)j * ldt + i] : (i == j ? 1.0 : 0.0);
@@ -101,11 +101,16 @@ __global__ __launch_bounds__(256) void k_trsm_prep(int n, int jt, const double* 
   }
 }
 
+__global__ __launch_bounds__(256) void k_trsm_prep(int n, int jt, const double* __restrict__ T,
+                                                   int64_t ldt, double* __restrict__ P) {
+  trsm_prep_body(n, jt, T, ldt, P, (int)blockIdx.x);
+}
+
+// Body of workgroup `wg` of `nwg` (persistent over 16-row tiles).
 template <int JT, bool kLds>
-__global__ __launch_bounds__(512, 1) void k_trsm_mfma(int64_t m, int n,
-                                                      const double* __restrict__ Y, int64_t ldy,
-                                                      const double* __restrict__ P,
-                                                      double* X, int64_t ldx) {
+__device__ __forceinline__ void trsm_mfma_body(int64_t m, int n, const double* __restrict__ Y,
+                                               int64_t ldy, const double* __restrict__ P,
+                                               double* X, int64_t ldx, int wg, int nwg) {
   constexpr int NOFF = JT * (JT - 1) / 2;
   constexpr int NTILE = NOFF + 2 * JT;
   extern __shared__ double tl[];
@@ -120,8 +125,8 @@ __global__ __launch_bounds__(512, 1) void k_trsm_mfma(int64_t m, int n,
   const int q = lane >> 4, c16 = lane & 15;
   const int64_t ntiles = (m + 15) / 16;
   const int nw = blockDim.x / kWave;
-  const int64_t wstride = (int64_t)gridDim.x * nw;
-  for (int64_t tile = (int64_t)blockIdx.x * nw + wave_id(); tile < ntiles; tile += wstride) {
+  const int64_t wstride = (int64_t)nwg * nw;
+  for (int64_t tile = (int64_t)wg * nw + wave_id(); tile < ntiles; tile += wstride) {
     // opaque per-iteration bases: the tiles are loop invariant and would otherwise be
     // hoisted into registers
     lds_f64* tlp = (lds_f64*)tl;
@@ -175,6 +180,14 @@ __global__ __launch_bounds__(512, 1) void k_trsm_mfma(int64_t m, int n,
         }
     }
   }
+}
+
+template <int JT, bool kLds>
+__global__ __launch_bounds__(512, 1) void k_trsm_mfma(int64_t m, int n,
+                                                      const double* __restrict__ Y, int64_t ldy,
+                                                      const double* __restrict__ P,
+                                                      double* X, int64_t ldx) {
+  trsm_mfma_body<JT, kLds>(m, n, Y, ldy, P, X, ldx, (int)blockIdx.x, (int)gridDim.x);
 }
 
 // ------------------------------------------------------------------------------------
@@ -374,11 +387,11 @@ __device__ __forceinline__ void gram_chunk(const lds_f64* lds, int q, int c16, v
 // VEC: X is 16-byte aligned, ldx and m are even, so every in-range row pair is one
 // aligned 16-byte load (chosen on the host; the loads stay branch-free either way, so the
 // prefetch is never waited for before the MFMA work that should hide it).
+// Body of workgroup (row block bx, tile share by).
 template <int JT, int NW, int NS, bool VEC>
-__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) void k_gram_f64(int64_t m, int n,
-                                                      const double* __restrict__ X, int64_t ldx,
-                                                      int64_t rows_per_block, int ntiles,
-                                                      double* __restrict__ part) {
+__device__ __forceinline__ void gram_f64_body(int64_t m, int n, const double* __restrict__ X,
+                                              int64_t ldx, int64_t rows_per_block, int ntiles,
+                                              double* __restrict__ part, int bx, int by) {
   constexpr int KC = 32;
   constexpr int NC = JT * 16;
   constexpr int LDN = NC + 1;
@@ -393,8 +406,8 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
 
   const int lane = lane_id(), wave = wave_id();
   const int q = lane >> 4, c16 = lane & 15;
-  const int slot = (int)blockIdx.y * NW + wave;
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int slot = by * NW + wave;
+  const int64_t r0 = (int64_t)bx * rows_per_block;
   const int64_t r1 = min(m, r0 + rows_per_block);
 
   v4d acc[TPW];
@@ -455,7 +468,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
 
   // tiles are enumerated column by column, so the first `ntiles` are those of the
   // n x n matrix (the rest only exist in the padded template size)
-  double* dst = part + (size_t)blockIdx.x * ntiles * 256;
+  double* dst = part + (size_t)bx * ntiles * 256;
 #pragma unroll
   for (int u = 0; u < TPW; ++u) {
     const int t = slot + u * STRIDE;
@@ -463,15 +476,23 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
   }
 }
 
+template <int JT, int NW, int NS, bool VEC>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) void k_gram_f64(
+    int64_t m, int n, const double* __restrict__ X, int64_t ldx, int64_t rows_per_block,
+    int ntiles, double* __restrict__ part) {
+  gram_f64_body<JT, NW, NS, VEC>(m, n, X, ldx, rows_per_block, ntiles, part, (int)blockIdx.x,
+                                 (int)blockIdx.y);
+}
+
 // W(i, j) = W(j, i) = sum_kb part[kb][tile][lane][reg]; same deterministic two-level
 // order as the sketch reduction (16 strided groups, then the groups in order).
-__global__ __launch_bounds__(256) void k_gram_reduce(int kblocks, int ntiles, int n,
-                                                     const double* __restrict__ part,
-                                                     double* __restrict__ W, int64_t ldw) {
+__device__ __forceinline__ void gram_reduce_body(int kblocks, int ntiles, int n,
+                                                 const double* __restrict__ part,
+                                                 double* __restrict__ W, int64_t ldw, int bx) {
   __shared__ double red[16][17];
   const size_t E = (size_t)ntiles * 256;
   const int g = threadIdx.x / 16, o = threadIdx.x % 16;
-  const size_t e = (size_t)blockIdx.x * 16 + o;
+  const size_t e = (size_t)bx * 16 + o;
   double acc = 0.0;
   if (e < E)
     for (int kb = g; kb < kblocks; kb += 16) acc += part[(size_t)kb * E + e];
@@ -488,6 +509,12 @@ __global__ __launch_bounds__(256) void k_gram_reduce(int kblocks, int ntiles, in
       W[(int64_t)i * ldw + j] = t;
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_gram_reduce(int kblocks, int ntiles, int n,
+                                                     const double* __restrict__ part,
+                                                     double* __restrict__ W, int64_t ldw) {
+  gram_reduce_body(kblocks, ntiles, n, part, W, ldw, (int)blockIdx.x);
 }
 
 GramPlan plan_gram(int64_t m, int n) {
@@ -532,6 +559,86 @@ hipError_t launch_gram_reduce(const GramPlan& p, int n, const double* part, doub
   const int blocks = (int)((E + 15) / 16);
   hipLaunchKernelGGL(k_gram_reduce, dim3(blocks), dim3(256), 0, st, p.kblocks, p.ntiles, n, part,
                      W, ldw);
+  return hipGetLastError();
+}
+
+// ---- batched forms ----------------------------------------------------------------------
+__device__ __forceinline__ const double* b_factor(const BProb& p, int which) {
+  return which == 0 ? p.R0 : (which == 1 ? p.R1 : p.R2);
+}
+
+__global__ __launch_bounds__(256) void k_b_trsm_prep(int which, const BItem* __restrict__ items,
+                                                     const BProb* __restrict__ probs) {
+  const BItem it = items[blockIdx.x];
+  const BProb& p = probs[it.pid];
+  int jt = 1;
+  while (jt < (p.n + 15) / 16) jt <<= 1;
+  trsm_prep_body(p.n, jt, b_factor(p, which), p.n, p.P, it.x);
+}
+
+template <int JT>
+__global__ __launch_bounds__(512, 1) void k_b_trsm(int src, const BItem* __restrict__ items,
+                                                   const BProb* __restrict__ probs) {
+  const BItem it = items[blockIdx.x];
+  const BProb& p = probs[it.pid];
+  const double* Y = src == 0 ? p.A : p.Q;
+  const int64_t ldy = src == 0 ? p.lda : p.ldq;
+  trsm_mfma_body<JT, true>(p.m, p.n, Y, ldy, p.P, p.Q, p.ldq, it.x, p.trsm_wgs);
+}
+
+template <int JT, int NW>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) void k_b_gram(
+    const BItem* __restrict__ items, const BProb* __restrict__ probs) {
+  const BItem it = items[blockIdx.x];
+  const BProb& p = probs[it.pid];
+  gram_f64_body<JT, NW, 1, false>(p.m, p.n, p.Q, p.ldq, p.gr_rpb, p.gr_ntiles, p.part, it.x, 0);
+}
+
+__global__ __launch_bounds__(256) void k_b_gram_reduce(const BItem* __restrict__ items,
+                                                       const BProb* __restrict__ probs) {
+  const BItem it = items[blockIdx.x];
+  const BProb& p = probs[it.pid];
+  gram_reduce_body(p.gr_kblocks, p.gr_ntiles, p.n, p.part, p.W, p.n, it.x);
+}
+
+hipError_t launch_b_trsm_prep(int which, const BItem* items, int nitems, const BProb* probs,
+                              hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_trsm_prep, dim3(nitems), dim3(256), 0, st, which, items, probs);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_trsm(int JT, int src, const BItem* items, int nitems, const BProb* probs,
+                         hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+#define TSQR_BTR(J)                                                                           \
+  if (JT == J) {                                                                              \
+    const size_t sh = (size_t)(J * (J - 1) / 2 + 2 * J) * 256 * sizeof(double);               \
+    hipLaunchKernelGGL((k_b_trsm<J>), dim3(nitems), dim3(512), sh, st, src, items, probs);    \
+    return hipGetLastError();                                                                 \
+  }
+  TSQR_BTR(1) TSQR_BTR(2) TSQR_BTR(4) TSQR_BTR(8)
+#undef TSQR_BTR
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_b_gram(int JT, const BItem* items, int nitems, const BProb* probs,
+                         hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+#define TSQR_BGR(J)                                                                           \
+  if (JT == J) {                                                                              \
+    hipLaunchKernelGGL((k_b_gram<J, 4>), dim3(nitems), dim3(256), 0, st, items, probs);       \
+    return hipGetLastError();                                                                 \
+  }
+  TSQR_BGR(1) TSQR_BGR(2) TSQR_BGR(4) TSQR_BGR(8)
+#undef TSQR_BGR
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_b_gram_reduce(const BItem* items, int nitems, const BProb* probs,
+                                hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_gram_reduce, dim3(nitems), dim3(256), 0, st, items, probs);
   return hipGetLastError();
 }
 

@@ -1,0 +1,357 @@
+// Batched randomized XR-preconditioned CholeskyQR: many independent problems of uneven
+// sizes factored together (each problem is the method of paper Algorithm rQR- or
+// rLU-CholeskyQR with the Gaussian sketch of Section 2.3 and one more CholeskyQR pass).
+//
+// Every phase of the chain is one launch per width class over a work list that holds the
+// workgroups of all problems of that class, so the machine is filled by the batch rather
+// than by any single problem.  A plan (built once on the host) groups the problems into
+// classes, sizes each problem's split-K blocking and triangular-solve grid, lays out the
+// workspace and uploads the problem descriptors and work lists into it.  Running a plan
+// only enqueues kernels: no allocation, no copy and no host synchronisation, so the whole
+// batch can be captured into one HIP graph and replayed.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "tsqr_launch.hpp"
+
+namespace tsqr {
+namespace {
+
+size_t align256b(size_t b) { return (b + 255) & ~(size_t)255; }
+
+int pow2_ceil(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+size_t trsm_tiles_doubles(int jt) {
+  return (size_t)(jt * (jt - 1) / 2 + 2 * jt) * 256 + (size_t)(jt + 1) / 2 + 1;
+}
+
+// Width class of a problem: everything that selects a kernel instantiation.
+struct ClassKey {
+  int jt;               // 16-column tiles of the panel (power of two)
+  int sk_it, sk_nw;     // sketch: i-tiles per wave, waves per workgroup
+  int sk_jt;            // sketch: column tiles per workgroup
+  int qr_rpl, qr_cpw;   // register factorization of the sketch
+  int po_rpl, po_cpw;   // register Cholesky
+  bool operator<(const ClassKey& o) const {
+    return std::tie(jt, sk_it, sk_nw, sk_jt, qr_rpl, qr_cpw, po_rpl, po_cpw) <
+           std::tie(o.jt, o.sk_it, o.sk_nw, o.sk_jt, o.qr_rpl, o.qr_cpw, o.po_rpl, o.po_cpw);
+  }
+};
+
+struct Launch {
+  int phase;  // see run()
+  ClassKey key;
+  size_t first;  // offset into the item array
+  int count;
+};
+
+}  // namespace
+}  // namespace tsqr
+
+struct tsqr_batch {
+  int variant = 0;
+  int64_t count = 0;
+  size_t probs_off = 0, items_off = 0;
+  tsqr::BProb* probs_dev = nullptr;
+  tsqr::BItem* items_dev = nullptr;
+  std::vector<tsqr::Launch> launches;
+};
+
+namespace tsqr {
+namespace {
+
+enum Phase {
+  kSetInfo, kSketch, kSketchReduce, kFactor, kPrep0, kTrsmA, kGram1, kGramReduce1, kPotrf1,
+  kTrmm10, kPrep1, kTrsm1, kGram2, kGramReduce2, kPotrf2, kTrmmR, kPrep2, kTrsm2, kPoison,
+  kNumPhases
+};
+
+// rows per split-K workgroup of the sketch and of the Gram kernels, and the triangular-solve
+// workgroups per problem: fixed here, chosen so that one workgroup streams a few thousand
+// rows (enough to amortise its partial-sum write) while the batch still spreads over the
+// whole GPU
+constexpr int64_t kSketchRows = 2048;
+constexpr int64_t kGramRows = 2048;
+constexpr int kTrsmTilesPerWg = 64;
+
+struct Layout {
+  size_t total = 0;
+  std::vector<size_t> off;  // per problem: start of its buffers
+};
+
+size_t problem_doubles(int64_t m, int n, int s) {
+  const int jt = pow2_ceil((n + 15) / 16);
+  const int it_total = (s + 15) / 16, jt_total = (n + 15) / 16;
+  const int sk_k = (int)((m + kSketchRows - 1) / kSketchRows);
+  const int gr_k = (int)((m + kGramRows - 1) / kGramRows);
+  const size_t sk_part = (size_t)sk_k * it_total * jt_total * 256;
+  const size_t gr_part = (size_t)gr_k * (jt_total * (jt_total + 1) / 2) * 256;
+  const size_t nn = (size_t)n * n;
+  size_t d = 0;
+  d += align256b((size_t)s * n * 8) / 8;             // B
+  d += 5 * (align256b(nn * 8) / 8);                  // R0 R1 R2 R10 W
+  d += align256b(trsm_tiles_doubles(jt) * 8) / 8;    // P
+  d += align256b(std::max(sk_part, gr_part) * 8) / 8;
+  return d;
+}
+
+int validate(int64_t count, const tsqr_problem* pr) {
+  if (count < 1) return -2;
+  if (!pr) return -3;
+  for (int64_t i = 0; i < count; ++i) {
+    const tsqr_problem& q = pr[i];
+    if (q.n < 1 || q.n > 128 || q.m < q.n || q.s < q.n || q.s > 512 || !q.A || q.lda < q.m ||
+        !q.Q || q.ldq < q.m || (q.R && q.ldr < q.n))
+      return -3;
+    // the register-resident factorization of the sketch holds s x n in one workgroup:
+    // 8 rows and 8 columns per lane do not fit, so s <= 256 when n > 64
+    if (q.n > 64 && q.s > 256) return -3;
+  }
+  return 0;
+}
+
+size_t header_bytes(int64_t count, size_t nitems) {
+  return align256b((size_t)count * sizeof(BProb)) + align256b(nitems * sizeof(BItem));
+}
+
+}  // namespace
+}  // namespace tsqr
+
+using namespace tsqr;
+
+extern "C" {
+
+size_t tsqr_batched_workspace_bytes(int64_t count, const tsqr_problem* problems) {
+  if (validate(count, problems) != 0) return 0;
+  size_t items = 0, bufs = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    const tsqr_problem& q = problems[i];
+    const int n = (int)q.n, s = (int)q.s;
+    const int it_total = (s + 15) / 16, jt_total = (n + 15) / 16;
+    const int jt = pow2_ceil(jt_total);
+    const int sk_jt = std::min(jt, 8);
+    const int sk_it = it_total >= 16 ? 2 : 1;
+    const int waves = (it_total + sk_it - 1) / sk_it;
+    const int sk_nw = waves >= 8 ? 8 : 4;
+    const int ig = (it_total + sk_nw * sk_it - 1) / (sk_nw * sk_it);
+    const int jg = (jt_total + sk_jt - 1) / sk_jt;
+    const int sk_k = (int)((q.m + kSketchRows - 1) / kSketchRows);
+    const int gr_k = (int)((q.m + kGramRows - 1) / kGramRows);
+    const int64_t ntiles = (q.m + 15) / 16;
+    const int twg = (int)std::min<int64_t>(256, (ntiles + kTrsmTilesPerWg - 1) / kTrsmTilesPerWg);
+    const size_t e_sk = (size_t)it_total * jt_total * 256, e_gr = (size_t)(jt_total * (jt_total + 1) / 2) * 256;
+    items += 1 + (size_t)sk_k * ig * jg + (e_sk + 15) / 16 + 1 + 3 * jt + 3 * twg +
+             2 * ((size_t)gr_k + (e_gr + 15) / 16) + 2 + 2 * (size_t)jt_total * jt_total + 4;
+    bufs += align256b(problem_doubles(q.m, n, s) * 8);
+  }
+  return header_bytes(count, items) + bufs;
+}
+
+int tsqr_batched_create(int variant, int64_t count, const tsqr_problem* problems, void* work,
+                        size_t work_bytes, int* d_info, tsqr_batch** out) {
+  if (variant != TSQR_VARIANT_RQR && variant != TSQR_VARIANT_RLU) return -1;
+  const int v = validate(count, problems);
+  if (v) return v;
+  if (!work) return -4;
+  if (!d_info) return -6;
+  if (!out) return -7;
+  *out = nullptr;
+  const size_t need = tsqr_batched_workspace_bytes(count, problems);
+  if (work_bytes < need) return TSQR_ERR_WORKSPACE;
+
+  std::vector<BProb> probs((size_t)count);
+  std::vector<ClassKey> keys((size_t)count);
+  // per phase, per class: the items
+  std::map<ClassKey, std::vector<BItem>> items[kNumPhases];
+  size_t nitems = 0;
+  // buffers after the header; the header size depends on the item count, so lay buffers
+  // out relative to a base fixed after counting
+  std::vector<size_t> buf_off((size_t)count);
+  size_t bufs = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    const tsqr_problem& q = problems[i];
+    BProb& p = probs[(size_t)i];
+    const int n = (int)q.n, s = (int)q.s;
+    p.A = q.A;
+    p.Q = q.Q;
+    p.R = q.R;
+    p.m = q.m;
+    p.lda = q.lda;
+    p.ldq = q.ldq;
+    p.ldr = q.R ? q.ldr : n;
+    p.n = n;
+    p.s = s;
+    p.k0 = (uint32_t)q.seed;
+    p.k1 = (uint32_t)(q.seed >> 32);
+    p.scale = 1.0 / std::sqrt((double)s);
+    p.info = d_info + i;
+    const int it_total = (s + 15) / 16, jt_total = (n + 15) / 16;
+    ClassKey k{};
+    k.jt = pow2_ceil(jt_total);
+    k.sk_jt = std::min(k.jt, 8);
+    k.sk_it = it_total >= 16 ? 2 : 1;
+    const int waves = (it_total + k.sk_it - 1) / k.sk_it;
+    k.sk_nw = waves >= 8 ? 8 : 4;
+    k.qr_rpl = pow2_ceil((s + 63) / 64);
+    k.qr_cpw = pow2_ceil((n + 15) / 16);
+    k.po_rpl = pow2_ceil((n + 63) / 64);
+    k.po_cpw = pow2_ceil((n + 15) / 16);
+    keys[(size_t)i] = k;
+    p.sk_it = it_total;
+    p.sk_jt = jt_total;
+    p.sk_rpb = kSketchRows;
+    p.sk_kblocks = (int)((q.m + kSketchRows - 1) / kSketchRows);
+    p.gr_rpb = kGramRows;
+    p.gr_kblocks = (int)((q.m + kGramRows - 1) / kGramRows);
+    p.gr_ntiles = jt_total * (jt_total + 1) / 2;
+    const int64_t ntiles = (q.m + 15) / 16;
+    p.trsm_wgs = (int)std::min<int64_t>(256, (ntiles + kTrsmTilesPerWg - 1) / kTrsmTilesPerWg);
+    p.poison_wgs = 4;
+    buf_off[(size_t)i] = bufs;
+    bufs += align256b(problem_doubles(q.m, n, s) * 8);
+
+    const int pid = (int)i;
+    auto add = [&](int phase, int x, int y, int z) {
+      items[phase][k].push_back(BItem{pid, x, y, z});
+      ++nitems;
+    };
+    add(kSetInfo, 0, 0, 0);
+    const int ig = (it_total + k.sk_nw * k.sk_it - 1) / (k.sk_nw * k.sk_it);
+    const int jg = (jt_total + k.sk_jt - 1) / k.sk_jt;
+    for (int kb = 0; kb < p.sk_kblocks; ++kb)
+      for (int a = 0; a < ig; ++a)
+        for (int b = 0; b < jg; ++b) add(kSketch, kb, a, b);
+    const size_t e_sk = (size_t)it_total * jt_total * 256;
+    for (size_t g = 0; g < (e_sk + 15) / 16; ++g) add(kSketchReduce, (int)g, 0, 0);
+    add(kFactor, 0, 0, 0);
+    for (int b = 0; b < k.jt; ++b) {
+      add(kPrep0, b, 0, 0);
+      add(kPrep1, b, 0, 0);
+      add(kPrep2, b, 0, 0);
+    }
+    for (int w = 0; w < p.trsm_wgs; ++w) {
+      add(kTrsmA, w, 0, 0);
+      add(kTrsm1, w, 0, 0);
+      add(kTrsm2, w, 0, 0);
+    }
+    for (int kb = 0; kb < p.gr_kblocks; ++kb) {
+      add(kGram1, kb, 0, 0);
+      add(kGram2, kb, 0, 0);
+    }
+    const size_t e_gr = (size_t)p.gr_ntiles * 256;
+    for (size_t g = 0; g < (e_gr + 15) / 16; ++g) {
+      add(kGramReduce1, (int)g, 0, 0);
+      add(kGramReduce2, (int)g, 0, 0);
+    }
+    add(kPotrf1, 0, 0, 0);
+    add(kPotrf2, 0, 0, 0);
+    for (int a = 0; a < jt_total; ++a)
+      for (int b = 0; b < jt_total; ++b) {
+        add(kTrmm10, a, b, 0);
+        add(kTrmmR, a, b, 0);
+      }
+    for (int w = 0; w < p.poison_wgs; ++w) add(kPoison, w, 0, 0);
+  }
+
+  // workspace: [descriptors | work items | per-problem buffers]
+  char* base = (char*)work;
+  const size_t probs_bytes = align256b((size_t)count * sizeof(BProb));
+  const size_t items_bytes = align256b(nitems * sizeof(BItem));
+  char* bufbase = base + probs_bytes + items_bytes;
+  if (probs_bytes + items_bytes + bufs > work_bytes) return TSQR_ERR_WORKSPACE;
+  for (int64_t i = 0; i < count; ++i) {
+    BProb& p = probs[(size_t)i];
+    const int n = p.n, s = p.s;
+    const size_t nn = (size_t)n * n;
+    char* c = bufbase + buf_off[(size_t)i];
+    p.B = (double*)c;
+    c += align256b((size_t)s * n * 8);
+    p.R0 = (double*)c;
+    c += align256b(nn * 8);
+    p.R1 = (double*)c;
+    c += align256b(nn * 8);
+    p.R2 = (double*)c;
+    c += align256b(nn * 8);
+    p.R10 = (double*)c;
+    c += align256b(nn * 8);
+    p.W = (double*)c;
+    c += align256b(nn * 8);
+    p.P = (double*)c;
+    c += align256b(trsm_tiles_doubles(pow2_ceil((n + 15) / 16)) * 8);
+    p.part = (double*)c;
+  }
+
+  tsqr_batch* plan = new (std::nothrow) tsqr_batch;
+  if (!plan) return TSQR_ERR_HIP;
+  plan->variant = variant;
+  plan->count = count;
+  plan->probs_dev = (BProb*)base;
+  plan->items_dev = (BItem*)(base + probs_bytes);
+  std::vector<BItem> all;
+  all.reserve(nitems);
+  for (int ph = 0; ph < kNumPhases; ++ph)
+    for (auto& kv : items[ph]) {
+      plan->launches.push_back(Launch{ph, kv.first, all.size(), (int)kv.second.size()});
+      all.insert(all.end(), kv.second.begin(), kv.second.end());
+    }
+  if (hipMemcpy(plan->probs_dev, probs.data(), (size_t)count * sizeof(BProb),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(plan->items_dev, all.data(), all.size() * sizeof(BItem), hipMemcpyHostToDevice) !=
+          hipSuccess) {
+    delete plan;
+    return TSQR_ERR_HIP;
+  }
+  *out = plan;
+  return TSQR_OK;
+}
+
+int tsqr_batched_run(tsqr_batch* plan, void* stream) {
+  if (!plan) return -1;
+  hipStream_t st = (hipStream_t)stream;
+  const BProb* P = plan->probs_dev;
+  for (const Launch& L : plan->launches) {
+    const BItem* it = plan->items_dev + L.first;
+    const ClassKey& k = L.key;
+    hipError_t e = hipSuccess;
+    switch (L.phase) {
+      case kSetInfo: e = launch_b_set_info(it, L.count, P, st); break;
+      case kSketch: e = launch_b_sketch(k.sk_it, k.sk_jt, k.sk_nw, it, L.count, P, st); break;
+      case kSketchReduce: e = launch_b_sketch_reduce(it, L.count, P, st); break;
+      case kFactor: e = launch_b_factor(plan->variant, k.qr_rpl, k.qr_cpw, it, L.count, P, st); break;
+      case kPrep0: e = launch_b_trsm_prep(0, it, L.count, P, st); break;
+      case kTrsmA: e = launch_b_trsm(k.jt, 0, it, L.count, P, st); break;
+      case kGram1:
+      case kGram2: e = launch_b_gram(k.jt, it, L.count, P, st); break;
+      case kGramReduce1:
+      case kGramReduce2: e = launch_b_gram_reduce(it, L.count, P, st); break;
+      case kPotrf1: e = launch_b_potrf(k.po_rpl, k.po_cpw, 1, 2, it, L.count, P, st); break;
+      case kPotrf2: e = launch_b_potrf(k.po_rpl, k.po_cpw, 2, 3, it, L.count, P, st); break;
+      case kTrmm10: e = launch_b_trmm(0, it, L.count, P, st); break;
+      case kPrep1: e = launch_b_trsm_prep(1, it, L.count, P, st); break;
+      case kTrsm1: e = launch_b_trsm(k.jt, 1, it, L.count, P, st); break;
+      case kTrmmR: e = launch_b_trmm(1, it, L.count, P, st); break;
+      case kPrep2: e = launch_b_trsm_prep(2, it, L.count, P, st); break;
+      case kTrsm2: e = launch_b_trsm(k.jt, 1, it, L.count, P, st); break;
+      case kPoison: e = launch_b_poison(it, L.count, P, st); break;
+      default: e = hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return TSQR_ERR_HIP;
+  }
+  return TSQR_OK;
+}
+
+int tsqr_batched_launches(const tsqr_batch* plan) {
+  return plan ? (int)plan->launches.size() : 0;
+}
+
+void tsqr_batched_destroy(tsqr_batch* plan) { delete plan; }
+
+}  // extern "C"

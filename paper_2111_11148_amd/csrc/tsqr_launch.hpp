@@ -85,6 +85,65 @@ hipError_t launch_apply_rinv_lowp(int prec, int64_t m, int n, const double* Y, i
 hipError_t launch_gram_lowp(int prec, const GramPlan& p, int64_t m, int n, const void* X,
                             int64_t ldx, double* part, hipStream_t st);
 
+// ---- batched factorizations -------------------------------------------------------------
+// One problem of a batch as the batched kernels see it (device copy in the workspace).
+struct BProb {
+  const double* A;  // caller's input (m x n, ld lda)
+  double* Q;        // caller's output (ld ldq)
+  double* R;        // caller's output (ld ldr) or null
+  int64_t m, lda, ldq, ldr;
+  int n, s;
+  uint32_t k0, k1;  // sketch seed halves
+  double scale;     // 1 / sqrt(s)
+  double* B;        // s x n sketch (ld s)
+  double* R0;       // n x n factors (ld n)
+  double* R1;
+  double* R2;
+  double* R10;
+  double* W;        // Gram matrix (ld n)
+  double* P;        // prepared triangular-solve tiles
+  double* part;     // split-K partial sums
+  int* info;
+  int64_t sk_rpb;   // sketch: rows per block, row blocks, tile counts
+  int sk_kblocks, sk_it, sk_jt;
+  int gr_kblocks;   // Gram: row blocks, tiles
+  int64_t gr_rpb;
+  int gr_ntiles;
+  int trsm_wgs;     // workgroups of each triangular solve
+  int poison_wgs;
+  int pad;
+};
+// One workgroup's share: problem index and block coordinates.
+struct BItem {
+  int pid, x, y, z;
+};
+
+hipError_t launch_b_sketch(int IT, int JT, int NW, const BItem* items, int nitems,
+                           const BProb* probs, hipStream_t st);
+hipError_t launch_b_sketch_reduce(const BItem* items, int nitems, const BProb* probs,
+                                  hipStream_t st);
+// variant 0: Householder QR, 1: LU (register kernels, s <= 512, n <= 128)
+hipError_t launch_b_factor(int variant, int RPL, int CPW, const BItem* items, int nitems,
+                           const BProb* probs, hipStream_t st);
+// which: 0 = R0, 1 = R1, 2 = R2
+hipError_t launch_b_trsm_prep(int which, const BItem* items, int nitems, const BProb* probs,
+                              hipStream_t st);
+// src: 0 = A (lda), 1 = Q (ldq); X = Q
+hipError_t launch_b_trsm(int JT, int src, const BItem* items, int nitems, const BProb* probs,
+                         hipStream_t st);
+hipError_t launch_b_gram(int JT, const BItem* items, int nitems, const BProb* probs,
+                         hipStream_t st);
+hipError_t launch_b_gram_reduce(const BItem* items, int nitems, const BProb* probs,
+                                hipStream_t st);
+// which: 1 = R1, 2 = R2
+hipError_t launch_b_potrf(int RPL, int CPW, int which, int stage, const BItem* items,
+                          int nitems, const BProb* probs, hipStream_t st);
+// which: 0 = R10 = R1 R0, 1 = R = R2 R10 (problems without R skip)
+hipError_t launch_b_trmm(int which, const BItem* items, int nitems, const BProb* probs,
+                         hipStream_t st);
+hipError_t launch_b_poison(const BItem* items, int nitems, const BProb* probs, hipStream_t st);
+hipError_t launch_b_set_info(const BItem* items, int nitems, const BProb* probs, hipStream_t st);
+
 // ---- test / debug kernels -------------------------------------------------------------
 hipError_t launch_philox_words(int64_t count, const uint32_t* ctr, uint64_t seed, uint32_t* out,
                                hipStream_t st);

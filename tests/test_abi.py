@@ -88,3 +88,30 @@ def test_workspace_bytes_monotone(lib):
     small = lib.tsqr_workspace_bytes(4096, 32, 64)
     big = lib.tsqr_workspace_bytes(1 << 20, 128, 256)
     assert 0 < small < big
+
+
+def test_batched_descriptor_validation(lib):
+    """Host-only checks of the batched entry points: invalid problems give a zero workspace
+    size and argument codes, before any device work."""
+    import paper_2111_11148_amd as tsqr
+
+    P = tsqr._Problem
+    good = P(1000, 32, 1000, 64, 1, 16, 1 << 20, 1000, 0, 32)  # fake, non-null pointers
+    arr = (P * 2)(good, good)
+    assert lib.tsqr_batched_workspace_bytes(2, ctypes.cast(arr, ctypes.c_void_p)) > 0
+    for bad in (P(1000, 129, 1000, 258, 1, 16, 32, 1000, 0, 129),   # n > 128
+                P(1000, 32, 1000, 600, 1, 16, 32, 1000, 0, 32),     # s > 512
+                P(1000, 32, 1000, 16, 1, 16, 32, 1000, 0, 32),      # s < n
+                P(1000, 32, 999, 64, 1, 16, 32, 1000, 0, 32),       # lda < m
+                P(1000, 32, 1000, 64, 1, 0, 32, 1000, 0, 32),       # A null
+                P(20, 32, 20, 64, 1, 16, 32, 20, 0, 32),            # m < n
+                P(1000, 100, 1000, 300, 1, 16, 32, 1000, 0, 100)):  # s > 256 with n > 64
+        arr = (P * 2)(good, bad)
+        assert lib.tsqr_batched_workspace_bytes(2, ctypes.cast(arr, ctypes.c_void_p)) == 0
+        plan = ctypes.c_void_p()
+        rc = lib.tsqr_batched_create(0, 2, ctypes.cast(arr, ctypes.c_void_p), 16, 1 << 30, 16,
+                                     ctypes.byref(plan))
+        assert rc == -3 and plan.value is None
+    assert lib.tsqr_batched_workspace_bytes(0, ctypes.cast(arr, ctypes.c_void_p)) == 0
+    assert lib.tsqr_batched_run(None, None) == -1
+    assert lib.tsqr_batched_launches(None) == 0
