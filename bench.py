@@ -12,7 +12,8 @@ roofline of the dominant kernel (average duration from HIP events recorded on th
 library's stream during the timed steps), the CPU oracle timed on a bounded sample, and
 the mixed-precision comparison: time to ||Q^T Q - I||_F <= 1e-12 on the mixed256 workload
 (m = 2^20, n = 256, s = 512, kappa in {1e4, 1e8, 1e12}) for FP64 and for the FP32 / BF16
-mixed variant.
+mixed variant, and the batched workload (512 uneven problems, one HIP graph per batch,
+problems/s against a per-problem loop).
 """
 from __future__ import annotations
 
@@ -209,6 +210,74 @@ def mixed_comparison(args, kappas):
             "target_ortho": 1e-12, "results": out}
 
 
+def batched_comparison(args):
+    """The batched workload: 512 independent problems (m ~ U[4096, 65536], n in
+    {16, 32, 64, 128}, kappa = 10^U(2,10), s = 2n, rQR + one pass, FP64).  The batch is
+    planned once, autotuned, captured into one HIP graph and replayed; the baseline is the
+    same factorizations issued one problem at a time through the explicit-workspace call."""
+    import torch
+
+    import paper_2111_11148_amd as tsqr
+    from inputs import batched_problems, gen_matrix
+
+    descs = batched_problems(args.batch_count, 211105)
+    t0 = time.perf_counter()
+    As = [tsqr.to_device_colmajor(gen_matrix(d["m"], d["n"], d["kappa"], d["gen_seed"]))
+          for d in descs]
+    print(f"# generated the batch ({len(descs)} problems) in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    ss = [d["s"] for d in descs]
+    seeds = [d["sketch_seed"] for d in descs]
+    F = sum(flops(d["m"], d["n"], d["s"], "rqr", True)["total"] for d in descs)
+
+    b = tsqr.Batch(As, ss, seeds)
+    tuning, tuned_ms = b.autotune()
+    torch.cuda.synchronize()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        b.run(stream=st)
+    torch.cuda.current_stream().wait_stream(st)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=st):
+        b.run(stream=st)
+    ms = timed(g.replay, args.batch_steps, 2)
+    info_ok = bool(torch.all(b.info == 0).item())
+    worst = 0.0
+    for i in range(len(descs)):
+        worst = max(worst, gpu_metrics(As[i], b.Q[i], b.R[i])[0])
+
+    # baseline: one explicit-workspace call per problem, workspaces and outputs preallocated
+    Qs = [tsqr.colmajor(A.shape[0], A.shape[1]) for A in As]
+    Rs = [tsqr.colmajor(A.shape[1], A.shape[1]) for A in As]
+    works = {}
+    for A, s_ in zip(As, ss):
+        key = (A.shape[0], A.shape[1], s_)
+        if key not in works:
+            works[key] = tsqr.alloc_workspace(*key)
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def loop():
+        for i, A in enumerate(As):
+            tsqr.rxr_cholqr(A, ss[i], seeds[i], Q=Qs[i], R=Rs[i],
+                            workspace=works[(A.shape[0], A.shape[1], ss[i])], info=info)
+
+    ms_loop = timed(loop, 2, 1)
+    print(f"# batched: {ms:.3f} ms per batch ({len(descs) / ms * 1e3:.0f} problems/s), loop "
+          f"{ms_loop:.3f} ms", file=sys.stderr, flush=True)
+    del works
+    return {"workload": f"{len(descs)} uneven problems, m in [4096, 65536], n in {{16,32,64,128}}, "
+                        "kappa 1e2..1e10, s = 2n, rqr + 1 pass, fp64",
+            "problems_per_s": round(len(descs) / ms * 1e3, 1), "ms_per_batch": round(ms, 4),
+            "gflops": round(F / ms / 1e6, 2), "flops_per_batch": F,
+            "loop_problems_per_s": round(len(descs) / ms_loop * 1e3, 1),
+            "loop_ms_per_batch": round(ms_loop, 4), "speedup_vs_loop": round(ms_loop / ms, 3),
+            "launches_per_run": b.launches, "tuning": tuning.as_dict(),
+            "autotune_ms": round(tuned_ms, 4), "graph": True, "all_info_zero": info_ok,
+            "worst_ortho": worst}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,6 +293,9 @@ def main() -> int:
                     help="condition numbers of the mixed-precision comparison (mixed256 "
                          "workload, m=2^20, n=256, s=512); empty to skip it")
     ap.add_argument("--mixed-steps", type=int, default=5)
+    ap.add_argument("--batch-count", type=int, default=512,
+                    help="problems of the batched workload (0 to skip it)")
+    ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -342,6 +414,11 @@ def main() -> int:
         torch.cuda.empty_cache()
         mixed = mixed_comparison(args, kappas)
 
+    batched = None
+    if args.batch_count > 0:
+        torch.cuda.empty_cache()
+        batched = batched_comparison(args)
+
     line = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -366,6 +443,7 @@ def main() -> int:
         "info": binfo,
         "phases_ms": {k: round(v, 4) for k, v in per_step.items()},
         "mixed_vs_fp64": mixed,
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
     return 0 if binfo == 0 else 1

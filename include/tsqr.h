@@ -174,17 +174,37 @@ typedef struct {
 
 typedef struct tsqr_batch tsqr_batch; /* opaque plan */
 
-/* Workspace bytes for a batch (0 if any problem is invalid).  `problems` is a host array. */
+/* Blocking of a batch plan: rows of A per split-K workgroup of the sketch and of the Gram
+ * kernels (multiples of 64, >= 1024), 16-row tiles per triangular-solve workgroup (>= 32). */
+typedef struct {
+  int64_t sketch_rows;
+  int64_t gram_rows;
+  int trsm_tiles;
+} tsqr_batch_tuning;
+
+/* Workspace bytes for a batch (0 if any problem is invalid); enough for every tuning.
+ * `problems` is a host array. */
 size_t tsqr_batched_workspace_bytes(int64_t count, const tsqr_problem* problems);
 
 /* Plan a batch: groups the problems by width, sizes their blockings, lays out `work` and
  * uploads the problem descriptors and work lists into it (synchronously).  Arguments:
  * variant (1), count (2), problems (3, host array, not kept), work / work_bytes (4, 5),
  * d_info (6: device int[count], one breakdown code per problem as for tsqr_rxr_cholqr_ws),
- * out (7: receives the plan).  The plan refers to `work`, `d_info` and the problems' device
- * buffers: they must stay valid and unmoved while the plan is used. */
+ * tuning (7: NULL for the defaults 2048 / 2048 / 64), out (8: receives the plan).  The plan
+ * refers to `work`, `d_info` and the problems' device buffers: they must stay valid and
+ * unmoved while the plan is used. */
 int tsqr_batched_create(int variant, int64_t count, const tsqr_problem* problems, void* work,
-                        size_t work_bytes, int* d_info, tsqr_batch** out);
+                        size_t work_bytes, int* d_info, const tsqr_batch_tuning* tuning,
+                        tsqr_batch** out);
+
+/* Autotuner: plans and runs the batch with candidate blockings (coordinate search over
+ * the sketch rows, the Gram rows and the solve tiles, each from four values) and returns
+ * the fastest in *best and its time per run in *best_ms (may be NULL).  Runs the batch
+ * (writes Q, R and d_info) and waits for the stream: call it outside any capture.
+ * Arguments as tsqr_batched_create, then stream (7), best (8), best_ms (9). */
+int tsqr_batched_autotune(int variant, int64_t count, const tsqr_problem* problems, void* work,
+                          size_t work_bytes, int* d_info, void* stream, tsqr_batch_tuning* best,
+                          double* best_ms);
 
 /* Enqueue the whole batch on `stream`.  Kernel launches only (no allocation, copy or host
  * synchronisation), so a stream capture of this call records the batch as one graph. */

@@ -58,7 +58,9 @@ _SIGS = {
                                     _vp]),
     "tsqr_gram_lowp": (_int, [_int, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp]),
     "tsqr_batched_workspace_bytes": (_sz, [_i64, _vp]),
-    "tsqr_batched_create": (_int, [_int, _i64, _vp, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
+    "tsqr_batched_create": (_int, [_int, _i64, _vp, _vp, _sz, _vp, _vp, ctypes.POINTER(_vp)]),
+    "tsqr_batched_autotune": (_int, [_int, _i64, _vp, _vp, _sz, _vp, _vp, _vp,
+                                     ctypes.POINTER(ctypes.c_double)]),
     "tsqr_batched_run": (_int, [_vp, _vp]),
     "tsqr_batched_launches": (_int, [_vp]),
     "tsqr_batched_destroy": (None, [_vp]),
@@ -406,6 +408,15 @@ class _Problem(ctypes.Structure):
                 ("A", _vp), ("Q", _vp), ("ldq", _i64), ("R", _vp), ("ldr", _i64)]
 
 
+class BatchTuning(ctypes.Structure):
+    """Mirror of tsqr_batch_tuning (include/tsqr.h)."""
+    _fields_ = [("sketch_rows", _i64), ("gram_rows", _i64), ("trsm_tiles", _int)]
+
+    def as_dict(self):
+        return {"sketch_rows": self.sketch_rows, "gram_rows": self.gram_rows,
+                "trsm_tiles": self.trsm_tiles}
+
+
 class Batch:
     """A planned batch of independent factorizations (tsqr_batched_create).
 
@@ -414,7 +425,8 @@ class Batch:
     plan, which refers to them.  run() enqueues the whole batch (kernel launches only, so it
     may be captured into a HIP graph); info is a (count,) int32 device tensor."""
 
-    def __init__(self, As, sketch_rows, seeds, variant: int = RQR, want_r: bool = True):
+    def __init__(self, As, sketch_rows, seeds, variant: int = RQR, want_r: bool = True,
+                 tuning: "BatchTuning | None" = None):
         count = len(As)
         if count < 1:
             raise ValueError("empty batch")
@@ -437,12 +449,32 @@ class Batch:
             raise ValueError("invalid problem in the batch")
         self.work = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self.info = torch.zeros(count, dtype=torch.int32, device=dev)
+        self._probs, self._variant, self._nbytes = probs, variant, nbytes
         plan = _vp()
         _check(load().tsqr_batched_create(variant, count, ctypes.cast(probs, _vp),
                                           self.work.data_ptr(), nbytes, self.info.data_ptr(),
+                                          ctypes.byref(tuning) if tuning is not None else None,
                                           ctypes.byref(plan)), "tsqr_batched_create")
         self._plan = plan
         self.count = count
+
+    def autotune(self, stream=None):
+        """Measure candidate blockings on this batch; returns (BatchTuning, ms per run).
+        Re-plans this batch with the winner."""
+        best, ms = BatchTuning(), ctypes.c_double(0.0)
+        _check(load().tsqr_batched_autotune(self._variant, self.count,
+                                            ctypes.cast(self._probs, _vp), self.work.data_ptr(),
+                                            self._nbytes, self.info.data_ptr(), _stream(stream),
+                                            ctypes.byref(best), ctypes.byref(ms)),
+               "tsqr_batched_autotune")
+        plan = _vp()
+        _check(load().tsqr_batched_create(self._variant, self.count,
+                                          ctypes.cast(self._probs, _vp), self.work.data_ptr(),
+                                          self._nbytes, self.info.data_ptr(), ctypes.byref(best),
+                                          ctypes.byref(plan)), "tsqr_batched_create")
+        load().tsqr_batched_destroy(self._plan)
+        self._plan = plan
+        return best, ms.value
 
     def run(self, stream=None):
         _check(load().tsqr_batched_run(self._plan, _stream(stream)), "tsqr_batched_run")

@@ -74,24 +74,25 @@ enum Phase {
   kNumPhases
 };
 
-// rows per split-K workgroup of the sketch and of the Gram kernels, and the triangular-solve
-// workgroups per problem: fixed here, chosen so that one workgroup streams a few thousand
-// rows (enough to amortise its partial-sum write) while the batch still spreads over the
-// whole GPU
-constexpr int64_t kSketchRows = 2048;
-constexpr int64_t kGramRows = 2048;
-constexpr int kTrsmTilesPerWg = 64;
+// Blocking of a plan: rows per split-K workgroup of the sketch and of the Gram kernels,
+// 16-row tiles per triangular-solve workgroup.  The defaults let one workgroup stream a
+// few thousand rows (enough to amortise its partial-sum write) while the batch still
+// spreads over the whole GPU; tsqr_batched_autotune measures the alternatives.
+constexpr tsqr_batch_tuning kDefaultTuning = {2048, 2048, 64};
+// smallest blockings the autotuner tries (they bound the workspace)
+constexpr int64_t kMinRows = 1024;
+constexpr int kMinTiles = 32;
 
 struct Layout {
   size_t total = 0;
   std::vector<size_t> off;  // per problem: start of its buffers
 };
 
-size_t problem_doubles(int64_t m, int n, int s) {
+size_t problem_doubles(int64_t m, int n, int s, const tsqr_batch_tuning& t) {
   const int jt = pow2_ceil((n + 15) / 16);
   const int it_total = (s + 15) / 16, jt_total = (n + 15) / 16;
-  const int sk_k = (int)((m + kSketchRows - 1) / kSketchRows);
-  const int gr_k = (int)((m + kGramRows - 1) / kGramRows);
+  const int sk_k = (int)((m + t.sketch_rows - 1) / t.sketch_rows);
+  const int gr_k = (int)((m + t.gram_rows - 1) / t.gram_rows);
   const size_t sk_part = (size_t)sk_k * it_total * jt_total * 256;
   const size_t gr_part = (size_t)gr_k * (jt_total * (jt_total + 1) / 2) * 256;
   const size_t nn = (size_t)n * n;
@@ -131,6 +132,8 @@ extern "C" {
 
 size_t tsqr_batched_workspace_bytes(int64_t count, const tsqr_problem* problems) {
   if (validate(count, problems) != 0) return 0;
+  // sized for the smallest blockings, so that every tuning fits
+  const tsqr_batch_tuning t{kMinRows, kMinRows, kMinTiles};
   size_t items = 0, bufs = 0;
   for (int64_t i = 0; i < count; ++i) {
     const tsqr_problem& q = problems[i];
@@ -143,26 +146,31 @@ size_t tsqr_batched_workspace_bytes(int64_t count, const tsqr_problem* problems)
     const int sk_nw = waves >= 8 ? 8 : 4;
     const int ig = (it_total + sk_nw * sk_it - 1) / (sk_nw * sk_it);
     const int jg = (jt_total + sk_jt - 1) / sk_jt;
-    const int sk_k = (int)((q.m + kSketchRows - 1) / kSketchRows);
-    const int gr_k = (int)((q.m + kGramRows - 1) / kGramRows);
+    const int sk_k = (int)((q.m + t.sketch_rows - 1) / t.sketch_rows);
+    const int gr_k = (int)((q.m + t.gram_rows - 1) / t.gram_rows);
     const int64_t ntiles = (q.m + 15) / 16;
-    const int twg = (int)std::min<int64_t>(256, (ntiles + kTrsmTilesPerWg - 1) / kTrsmTilesPerWg);
+    const int twg = (int)std::min<int64_t>(256, (ntiles + t.trsm_tiles - 1) / t.trsm_tiles);
     const size_t e_sk = (size_t)it_total * jt_total * 256, e_gr = (size_t)(jt_total * (jt_total + 1) / 2) * 256;
     items += 1 + (size_t)sk_k * ig * jg + (e_sk + 15) / 16 + 1 + 3 * jt + 3 * twg +
              2 * ((size_t)gr_k + (e_gr + 15) / 16) + 2 + 2 * (size_t)jt_total * jt_total + 4;
-    bufs += align256b(problem_doubles(q.m, n, s) * 8);
+    bufs += align256b(problem_doubles(q.m, n, s, t) * 8);
   }
   return header_bytes(count, items) + bufs;
 }
 
 int tsqr_batched_create(int variant, int64_t count, const tsqr_problem* problems, void* work,
-                        size_t work_bytes, int* d_info, tsqr_batch** out) {
+                        size_t work_bytes, int* d_info, const tsqr_batch_tuning* tuning,
+                        tsqr_batch** out) {
   if (variant != TSQR_VARIANT_RQR && variant != TSQR_VARIANT_RLU) return -1;
   const int v = validate(count, problems);
   if (v) return v;
   if (!work) return -4;
   if (!d_info) return -6;
-  if (!out) return -7;
+  const tsqr_batch_tuning t = tuning ? *tuning : kDefaultTuning;
+  if (t.sketch_rows < kMinRows || t.sketch_rows % 64 || t.gram_rows < kMinRows ||
+      t.gram_rows % 64 || t.trsm_tiles < kMinTiles)
+    return -7;
+  if (!out) return -8;
   *out = nullptr;
   const size_t need = tsqr_batched_workspace_bytes(count, problems);
   if (work_bytes < need) return TSQR_ERR_WORKSPACE;
@@ -207,16 +215,16 @@ int tsqr_batched_create(int variant, int64_t count, const tsqr_problem* problems
     keys[(size_t)i] = k;
     p.sk_it = it_total;
     p.sk_jt = jt_total;
-    p.sk_rpb = kSketchRows;
-    p.sk_kblocks = (int)((q.m + kSketchRows - 1) / kSketchRows);
-    p.gr_rpb = kGramRows;
-    p.gr_kblocks = (int)((q.m + kGramRows - 1) / kGramRows);
+    p.sk_rpb = t.sketch_rows;
+    p.sk_kblocks = (int)((q.m + t.sketch_rows - 1) / t.sketch_rows);
+    p.gr_rpb = t.gram_rows;
+    p.gr_kblocks = (int)((q.m + t.gram_rows - 1) / t.gram_rows);
     p.gr_ntiles = jt_total * (jt_total + 1) / 2;
     const int64_t ntiles = (q.m + 15) / 16;
-    p.trsm_wgs = (int)std::min<int64_t>(256, (ntiles + kTrsmTilesPerWg - 1) / kTrsmTilesPerWg);
+    p.trsm_wgs = (int)std::min<int64_t>(256, (ntiles + t.trsm_tiles - 1) / t.trsm_tiles);
     p.poison_wgs = 4;
     buf_off[(size_t)i] = bufs;
-    bufs += align256b(problem_doubles(q.m, n, s) * 8);
+    bufs += align256b(problem_doubles(q.m, n, s, t) * 8);
 
     const int pid = (int)i;
     auto add = [&](int phase, int x, int y, int z) {
@@ -345,6 +353,63 @@ int tsqr_batched_run(tsqr_batch* plan, void* stream) {
     }
     if (e != hipSuccess) return TSQR_ERR_HIP;
   }
+  return TSQR_OK;
+}
+
+int tsqr_batched_autotune(int variant, int64_t count, const tsqr_problem* problems, void* work,
+                          size_t work_bytes, int* d_info, void* stream, tsqr_batch_tuning* best,
+                          double* best_ms) {
+  if (!best) return -8;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return TSQR_ERR_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return TSQR_ERR_HIP;
+  }
+  // time of one run of the batch planned with `t` (warm-up run, then the mean of two)
+  auto measure = [&](const tsqr_batch_tuning& t, double* ms) -> int {
+    tsqr_batch* plan = nullptr;
+    int rc = tsqr_batched_create(variant, count, problems, work, work_bytes, d_info, &t, &plan);
+    if (rc) return rc;
+    rc = tsqr_batched_run(plan, st);
+    if (!rc && hipEventRecord(e0, st) != hipSuccess) rc = TSQR_ERR_HIP;
+    for (int r = 0; r < 2 && !rc; ++r) rc = tsqr_batched_run(plan, st);
+    if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = TSQR_ERR_HIP;
+    if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = TSQR_ERR_HIP;
+    float f = 0.f;
+    if (!rc && hipEventElapsedTime(&f, e0, e1) != hipSuccess) rc = TSQR_ERR_HIP;
+    tsqr_batched_destroy(plan);
+    *ms = f / 2.0;
+    return rc;
+  };
+  // coordinate search: sketch blocking, then Gram blocking, then solve grid
+  tsqr_batch_tuning cur = kDefaultTuning;
+  double cur_ms = 0.0;
+  int rc = measure(cur, &cur_ms);
+  const int64_t rows[] = {1024, 2048, 4096, 8192};
+  const int tiles[] = {32, 64, 128, 256};
+  for (int dim = 0; dim < 3 && !rc; ++dim)
+    for (int c = 0; c < 4 && !rc; ++c) {
+      tsqr_batch_tuning t = cur;
+      if (dim == 0) t.sketch_rows = rows[c];
+      if (dim == 1) t.gram_rows = rows[c];
+      if (dim == 2) t.trsm_tiles = tiles[c];
+      if (t.sketch_rows == cur.sketch_rows && t.gram_rows == cur.gram_rows &&
+          t.trsm_tiles == cur.trsm_tiles)
+        continue;
+      double ms = 0.0;
+      rc = measure(t, &ms);
+      if (!rc && ms < cur_ms) {
+        cur = t;
+        cur_ms = ms;
+      }
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  *best = cur;
+  if (best_ms) *best_ms = cur_ms;
   return TSQR_OK;
 }
 
