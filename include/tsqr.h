@@ -59,7 +59,8 @@ extern "C" {
  *   B = S A (s x n);  R0 = R factor of B (Householder, diag > 0);  A1 = A R0^{-1};
  *   R1 = chol(A1^T A1);  Q1 = A1 R1^{-1};  R2 = chol(Q1^T Q1);  Q = Q1 R2^{-1};
  *   R = R2 (R1 R0).
- * m, n        : rows and columns of A, 1 <= n <= m.                       (args 1, 2)
+ * m, n        : rows and columns of A, 1 <= n <= m, n <= 1024 (TSQR_ERR_UNSUPPORTED
+ *               above).                                                    (args 1, 2)
  * A, lda      : input, read only, lda >= m.                               (args 3, 4)
  * sketch_rows : s, rows of the sketch, n <= s <= 8192 (the paper uses 2n). (arg 5)
  * seed        : sketch seed (see the stream definition above).            (arg 6)
@@ -124,7 +125,8 @@ int tsqr_rxr_cholqr_ws(int variant, int64_t m, int64_t n, const double* A, int64
  * passes_out (arg 16): host int receiving the number of FP64 passes run, or NULL.
  * lowp (arg 2): TSQR_LOWP_FP32 or TSQR_LOWP_BF16.  Other arguments as in
  * tsqr_rxr_cholqr_ws (shifted by one position); info stages 3 and 4 are the FP64 passes.
- * Workspace: tsqr_mixed_workspace_bytes(m, n, s, lowp) bytes. */
+ * Workspace: tsqr_mixed_workspace_bytes(m, n, s, lowp) bytes.  n <= 256 (the
+ * low-precision kernels; TSQR_ERR_UNSUPPORTED above). */
 size_t tsqr_mixed_workspace_bytes(int64_t m, int64_t n, int64_t sketch_rows, int lowp);
 int tsqr_rxr_cholqr_mixed_ws(int variant, int lowp, int64_t m, int64_t n, const double* A,
                              int64_t lda, int64_t sketch_rows, uint64_t seed, int fp64_passes,
@@ -241,14 +243,15 @@ int tsqr_sketch_factor(int variant, int64_t s, int64_t n, const double* B, int64
 /* Right-side upper triangular solve X = Y T^{-1} by row-wise substitution (paper
  * Algorithm CholeskyQR, step 3; row-wise backward stable, no explicit inverse).
  * Y, X: m x n (ldy, ldx >= m); X may be the same buffer as Y with ldx == ldy (in place);
- * T: n x n upper, only its upper triangle is read.  n <= 256.
+ * T: n x n upper, only its upper triangle is read.  n <= 1024 (above 128 columns the
+ * solve runs by 128-column blocks with an MFMA update between them).
  * Workspace (args 9, 10): tsqr_trsm_workspace_bytes(n) bytes (a transposed copy of T). */
 size_t tsqr_trsm_workspace_bytes(int64_t n);
 int tsqr_trsm(int64_t m, int64_t n, const double* Y, int64_t ldy, const double* T, int64_t ldt,
               double* X, int64_t ldx, void* work, size_t work_bytes, void* stream);
 
 /* Gram matrix W = X^T X (paper Algorithm CholeskyQR, step 1), both triangles written
- * (ldw >= n).  Split over row blocks, fixed-order reduction.  n <= 256.
+ * (ldw >= n).  Split over row blocks, fixed-order reduction.  n <= 1024.
  * Workspace: tsqr_gram_workspace_bytes(m, n). */
 size_t tsqr_gram_workspace_bytes(int64_t m, int64_t n);
 int tsqr_gram(int64_t m, int64_t n, const double* X, int64_t ldx, double* W, int64_t ldw,

@@ -1189,6 +1189,11 @@ hipError_t launch_potrf(int n, const double* W, int64_t ldw, double* R, int64_t 
                        st, n, W, ldw, R, ldr, stage, info, shift);
     return hipGetLastError();
   }
+  if (n > 512 && n <= 1024) {  // narrower panels keep the panel row in LDS
+    hipLaunchKernelGGL(k_potrf_blk<16>, grid, block, potrf_blk_lds_doubles<16>(n) * sizeof(double),
+                       st, n, W, ldw, R, ldr, stage, info, shift);
+    return hipGetLastError();
+  }
   TSQR_POTRF(1, 1) TSQR_POTRF(1, 2) TSQR_POTRF(1, 4) TSQR_POTRF(2, 8)
 #undef TSQR_POTRF
   if (n > kMaxS) return hipErrorInvalidValue;

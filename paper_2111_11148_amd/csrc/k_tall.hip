@@ -517,10 +517,130 @@ __global__ __launch_bounds__(256) void k_gram_reduce(int kblocks, int ntiles, in
   gram_reduce_body(kblocks, ntiles, n, part, W, ldw, (int)blockIdx.x);
 }
 
+// ------------------------------------------------------------------------------------
+// Wide Gram matrix (n > 256): W is cut into 128 x 128 blocks.  Workgroup (row block bx,
+// block pair by = (bi <= bj)) accumulates X(:, block bi)^T X(:, block bj) over its rows;
+// its eight wavefronts own the eight 16-row strips of the block pair (wave a: tiles (a, b)
+// for b = 0..7).  Rows are streamed in 32-row chunks through LDS with register prefetch as
+// in k_gram_f64; partials are written tile-natively per (row block, pair, tile) and summed
+// in a fixed order by k_gram_wide_reduce.
+// ------------------------------------------------------------------------------------
+constexpr int kWideBlk = 128;
+
+__host__ __device__ inline void wide_pair(int t, int& bi, int& bj) {
+  int b = 0;
+  while ((b + 1) * (b + 2) / 2 <= t) ++b;
+  bj = b;
+  bi = t - b * (b + 1) / 2;
+}
+
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k_gram_wide(
+    int64_t m, int n, const double* __restrict__ X, int64_t ldx, int64_t rows_per_block,
+    int npairs, double* __restrict__ part) {
+  constexpr int KC = 32, NC = kWideBlk, LDN = NC + 1;
+  constexpr int THREADS = 512;
+  constexpr int CPP = THREADS / (KC / 2);      // 32 columns per pass
+  constexpr int PASSES = 2 * NC / CPP;         // both blocks: 8 passes
+  __shared__ double la[KC * LDN];
+  __shared__ double lb[KC * LDN];
+  const int lane = lane_id(), wave = wave_id();
+  const int q = lane >> 4, c16 = lane & 15;
+  int bi, bj;
+  wide_pair((int)blockIdx.y, bi, bj);
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = min(m, r0 + rows_per_block);
+  v4d acc[8];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) acc[b] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int rp = (int)threadIdx.x % (KC / 2), cb = (int)threadIdx.x / (KC / 2);
+  double pre[PASSES][2];
+  auto load_chunk = [&](int64_t rb) {
+#pragma unroll
+    for (int ps = 0; ps < PASSES; ++ps) {
+      const int cc = cb + ps * CPP;  // 0..255: first block bi, then block bj
+      const int col = (cc < NC) ? kWideBlk * bi + cc : kWideBlk * bj + (cc - NC);
+      const int64_t row = rb + 2 * rp;
+      const bool okc = col < n;
+      const double* src = X + (int64_t)(okc ? col : 0) * ldx;
+      pre[ps][0] = (okc && row < r1) ? src[row] : 0.0;
+      pre[ps][1] = (okc && row + 1 < r1) ? src[row + 1] : 0.0;
+    }
+  };
+  if (r0 < r1) load_chunk(r0);
+  for (int64_t rb = r0; rb < r1; rb += KC) {
+    __syncthreads();
+#pragma unroll
+    for (int ps = 0; ps < PASSES; ++ps) {
+      const int cc = cb + ps * CPP;
+      double* dst = (cc < NC) ? la + cc : lb + (cc - NC);
+      dst[(2 * rp) * LDN] = pre[ps][0];
+      dst[(2 * rp + 1) * LDN] = pre[ps][1];
+    }
+    __syncthreads();
+    if (rb + KC < r1) load_chunk(rb + KC);
+    const lds_f64* pa = (const lds_f64*)la + q * LDN + 16 * wave + c16;
+    const lds_f64* pb = (const lds_f64*)lb + q * LDN + c16;
+#pragma unroll
+    for (int kk = 0; kk < KC / 4; ++kk) {
+      const double a = pa[4 * kk * LDN];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) acc[b] = mfma_f64(a, pb[4 * kk * LDN + 16 * b], acc[b]);
+    }
+  }
+  double* dst = part + ((size_t)blockIdx.x * npairs + blockIdx.y) * 64 * 256;
+#pragma unroll
+  for (int b = 0; b < 8; ++b)
+    *reinterpret_cast<v4d*>(dst + (size_t)(wave * 8 + b) * 256 + lane * 4) = acc[b];
+}
+
+// W(i, j) = W(j, i) = sum_kb part[kb][pair][tile][lane][reg], fixed two-level order; in a
+// diagonal block pair only the entries with i <= j are taken (each written once).
+__global__ __launch_bounds__(256) void k_gram_wide_reduce(int kblocks, int npairs, int n,
+                                                          const double* __restrict__ part,
+                                                          double* __restrict__ W, int64_t ldw) {
+  __shared__ double red[16][17];
+  const size_t E = (size_t)npairs * 64 * 256;
+  const int g = threadIdx.x / 16, o = threadIdx.x % 16;
+  const size_t e = (size_t)blockIdx.x * 16 + o;
+  double acc = 0.0;
+  if (e < E)
+    for (int kb = g; kb < kblocks; kb += 16) acc += part[(size_t)kb * E + e];
+  red[g][o] = acc;
+  __syncthreads();
+  if (g == 0 && e < E) {
+    double t = 0.0;
+    for (int k = 0; k < 16; ++k) t += red[k][o];
+    const int pair = (int)(e / (64 * 256)), tile = (int)((e / 256) % 64);
+    const int lane = (int)((e / 4) % 64), r = (int)(e % 4);
+    int bi, bj;
+    wide_pair(pair, bi, bj);
+    const int i = kWideBlk * bi + 16 * (tile / 8) + 4 * r + (lane >> 4);
+    const int j = kWideBlk * bj + 16 * (tile % 8) + (lane & 15);
+    if (i < n && j < n && (bi != bj || i <= j)) {
+      W[(int64_t)j * ldw + i] = t;
+      W[(int64_t)i * ldw + j] = t;
+    }
+  }
+}
+
 GramPlan plan_gram(int64_t m, int n) {
   GramPlan p{};
   p.jt_total = (n + 15) / 16;
   p.ntiles = p.jt_total * (p.jt_total + 1) / 2;
+  if (n > 256) {
+    const int nb = (n + kWideBlk - 1) / kWideBlk;
+    p.wide = 1;
+    p.npairs = nb * (nb + 1) / 2;
+    int64_t kb = (int64_t)device_cu_count() * 2 / p.npairs;
+    if (kb < 1) kb = 1;
+    int64_t rpb = (m + kb - 1) / kb;
+    rpb = ((rpb + 63) / 64) * 64;
+    if (rpb < 64) rpb = 64;
+    p.rows_per_block = rpb;
+    p.kblocks = (int)((m + rpb - 1) / rpb);
+    p.part_doubles = (size_t)p.kblocks * p.npairs * 64 * 256;
+    return p;
+  }
   const int64_t target = (int64_t)device_cu_count() * 2;
   int64_t rpb = (m + target - 1) / target;
   rpb = ((rpb + 63) / 64) * 64;
@@ -534,6 +654,11 @@ GramPlan plan_gram(int64_t m, int n) {
 
 hipError_t launch_gram(const GramPlan& p, int64_t m, int n, const double* X, int64_t ldx,
                        double* part, hipStream_t st) {
+  if (p.wide) {
+    hipLaunchKernelGGL(k_gram_wide, dim3(p.kblocks, p.npairs), dim3(512), 0, st, m, n, X, ldx,
+                       p.rows_per_block, p.npairs, part);
+    return hipGetLastError();
+  }
   const bool vec = ((reinterpret_cast<uintptr_t>(X) & 15) == 0) && ((ldx & 1) == 0) &&
                    ((m & 1) == 0);
 #define TSQR_GRAM(J, NW_, NS_)                                                              \
@@ -555,6 +680,12 @@ hipError_t launch_gram(const GramPlan& p, int64_t m, int n, const double* X, int
 
 hipError_t launch_gram_reduce(const GramPlan& p, int n, const double* part, double* W,
                               int64_t ldw, hipStream_t st) {
+  if (p.wide) {
+    const size_t E = (size_t)p.npairs * 64 * 256;
+    hipLaunchKernelGGL(k_gram_wide_reduce, dim3((unsigned)((E + 15) / 16)), dim3(256), 0, st,
+                       p.kblocks, p.npairs, n, part, W, ldw);
+    return hipGetLastError();
+  }
   const size_t E = (size_t)p.ntiles * 256;
   const int blocks = (int)((E + 15) / 16);
   hipLaunchKernelGGL(k_gram_reduce, dim3(blocks), dim3(256), 0, st, p.kblocks, p.ntiles, n, part,

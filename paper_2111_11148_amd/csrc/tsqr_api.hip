@@ -31,7 +31,8 @@ int device_cu_count() {
 namespace {
 
 constexpr int64_t kMaxSketchRows = 8192;
-constexpr int64_t kMaxN = 256;  // widest n of the tall-skinny kernels in this build
+constexpr int64_t kMaxN = 1024;     // widest n of the FP64 path
+constexpr int64_t kMaxNLowp = 256;  // widest n of the low-precision kernels
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -442,7 +443,7 @@ int tsqr_rxr_cholqr_ws(int variant, int64_t m, int64_t n, const double* A, int64
 }
 
 size_t tsqr_mixed_workspace_bytes(int64_t m, int64_t n, int64_t sketch_rows, int lowp) {
-  if (n < 1 || m < n || sketch_rows < n || sketch_rows > kMaxSketchRows) return 0;
+  if (n < 1 || n > kMaxNLowp || m < n || sketch_rows < n || sketch_rows > kMaxSketchRows) return 0;
   if (lowp != TSQR_LOWP_FP32 && lowp != TSQR_LOWP_BF16) return 0;
   return make_mixed_layout(m, n, sketch_rows, lowp).total;
 }
@@ -468,7 +469,7 @@ int tsqr_rxr_cholqr_mixed_ws(int variant, int lowp, int64_t m, int64_t n, const 
   }
   if (fp64_passes < 0 || fp64_passes > 3) return -9;
   if (!work) return -14;
-  if (n > kMaxN) return TSQR_ERR_UNSUPPORTED;
+  if (n > kMaxNLowp) return TSQR_ERR_UNSUPPORTED;
   if (work_bytes < make_mixed_layout(m, n, sketch_rows, lowp).total) return TSQR_ERR_WORKSPACE;
   return run_chain_mixed(variant, lowp, m, n, A, lda, sketch_rows, seed, fp64_passes, Q, ldq, R,
                          ldr, work, d_info, passes_out, (hipStream_t)stream);
@@ -479,7 +480,7 @@ int tsqr_sketch_lowp(int lowp, int64_t m, int64_t n, const double* A, int64_t ld
                      void* stream) {
   if (lowp != TSQR_LOWP_FP32 && lowp != TSQR_LOWP_BF16) return -1;
   if (m < 1) return -2;
-  if (n < 1 || n > kMaxN) return -3;
+  if (n < 1 || n > kMaxNLowp) return -3;
   if (!A) return -4;
   if (lda < m) return -5;
   if (s < 1 || s > kMaxSketchRows) return -6;
@@ -497,7 +498,7 @@ int tsqr_sketch_lowp(int lowp, int64_t m, int64_t n, const double* A, int64_t ld
 }
 
 size_t tsqr_rinv_lowp_bytes(int64_t n, int lowp) {
-  if (n < 1 || n > kMaxN || (lowp != TSQR_LOWP_FP32 && lowp != TSQR_LOWP_BF16)) return 0;
+  if (n < 1 || n > kMaxNLowp || (lowp != TSQR_LOWP_FP32 && lowp != TSQR_LOWP_BF16)) return 0;
   return rinv_lowp_bytes(lowp, (int)n);
 }
 
@@ -506,7 +507,7 @@ int tsqr_apply_rinv_lowp(int lowp, int64_t m, int64_t n, const double* Y, int64_
                          size_t work_bytes, void* stream) {
   if (lowp != TSQR_LOWP_FP32 && lowp != TSQR_LOWP_BF16) return -1;
   if (m < 1) return -2;
-  if (n < 1 || n > kMaxN) return -3;
+  if (n < 1 || n > kMaxNLowp) return -3;
   if (!Y) return -4;
   if (ldy < m) return -5;
   if (!Rinv) return -6;
@@ -526,7 +527,7 @@ int tsqr_gram_lowp(int lowp, int64_t m, int64_t n, const void* X, int64_t ldx, d
                    int64_t ldw, void* work, size_t work_bytes, void* stream) {
   if (lowp != TSQR_LOWP_FP32 && lowp != TSQR_LOWP_BF16) return -1;
   if (m < 1) return -2;
-  if (n < 1 || n > kMaxN) return -3;
+  if (n < 1 || n > kMaxNLowp) return -3;
   if (!X) return -4;
   if (ldx < m) return -5;
   if (!W) return -6;

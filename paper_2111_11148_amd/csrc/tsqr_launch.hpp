@@ -29,6 +29,8 @@ struct GramPlan {
   int64_t rows_per_block;
   int kblocks;
   size_t part_doubles;
+  int wide;      // n > 256: 128-column block pairs (npairs of them), 64 tiles each
+  int npairs;
 };
 GramPlan plan_gram(int64_t m, int n);
 

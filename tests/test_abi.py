@@ -78,7 +78,7 @@ def test_workspace_form_argument_codes(lib):
     assert call(ldr=7) == -12
     assert call(work=None) == -13
     assert call() == -101  # TSQR_ERR_WORKSPACE: 1 byte is too small
-    assert call(m=1000, lda=1000, ldq=1000, n=300, s=600, ldr=300) == -102  # too wide
+    assert call(m=3000, lda=3000, ldq=3000, n=1100, s=2200, ldr=1100) == -102  # too wide
 
 
 def test_workspace_bytes_monotone(lib):
@@ -120,3 +120,10 @@ def test_batched_descriptor_validation(lib):
                                    ctypes.byref(bad_t), ctypes.byref(plan)) == -7
     assert lib.tsqr_batched_run(None, None) == -1
     assert lib.tsqr_batched_launches(None) == 0
+
+
+def test_mixed_width_limit(lib):
+    """The low-precision kernels stop at n = 256: no workspace size above."""
+    assert lib.tsqr_mixed_workspace_bytes(4096, 256, 512, 1) > 0
+    assert lib.tsqr_mixed_workspace_bytes(4096, 300, 600, 1) == 0
+    assert lib.tsqr_workspace_bytes(4096, 1024, 2048) > 0

@@ -65,7 +65,8 @@ def test_sketch_normals_match_oracle(i0, ni, j0, nj):
 
 # ---------------------------------------------------------------------------- sketch --
 @pytest.mark.parametrize("m,n,s", [(4096, 32, 64), (1000, 5, 7), (1027, 17, 40), (3000, 128, 256),
-                                   (777, 1, 1), (2050, 100, 100), (513, 64, 129), (4100, 200, 400)])
+                                   (777, 1, 1), (2050, 100, 100), (513, 64, 129), (4100, 200, 400),
+                                   (2000, 600, 1200)])
 def test_sketch_parity(m, n, s):
     """|B_gpu - B_or| <= rs * (NORMAL_ABS_TOL sum_j |A_jc| + 4 m u sum_j |z_ij A_jc|)."""
     A = gen_matrix(m, n, 1e6, 300 + m)
@@ -119,7 +120,7 @@ def test_sketch_factor_breakdown():
 # ---------------------------------------------------------------------------- TRSM ----
 @pytest.mark.parametrize("m,n", [(4096, 32), (1000, 5), (1027, 17), (5000, 128), (333, 1),
                                  (2049, 100), (700, 256), (64, 64), (3001, 129), (2000, 200),
-                                 (4100, 256)])
+                                 (4100, 256), (3000, 1024), (1500, 555)])
 def test_trsm_parity(m, n):
     """Row-wise backward error |Y - X T| <= c n u |X||T| (as for the oracle's own solve;
     the column-blocked solve used above 128 columns has the same bound), and X agrees
@@ -147,7 +148,8 @@ def test_trsm_in_place_and_ld(n):
 
 # ---------------------------------------------------------------------------- Gram ----
 @pytest.mark.parametrize("m,n", [(4096, 32), (1000, 5), (1027, 17), (6000, 128), (129, 1),
-                                 (2049, 100), (1500, 256), (64, 64)])
+                                 (2049, 100), (1500, 256), (64, 64), (3000, 300), (2000, 1024),
+                                 (700, 513)])
 def test_gram_parity(m, n):
     """|W_gpu - X^T X| <= 2 m u |X|^T |X| (any summation order), symmetric."""
     X = gen_matrix(m, n, 1e4, 9 + n)
@@ -158,7 +160,7 @@ def test_gram_parity(m, n):
 
 
 # ------------------------------------------------------------------------ Cholesky ----
-@pytest.mark.parametrize("n", [1, 5, 16, 32, 64, 65, 100, 128, 129, 200, 256])
+@pytest.mark.parametrize("n", [1, 5, 16, 32, 64, 65, 100, 128, 129, 200, 256, 600, 1024])
 def test_potrf_parity(n):
     """R^T R = W to c n u ||W||; R agrees with the oracle within c n u cond(W)."""
     X = gen_matrix(4 * n + 10, n, 30.0, n)
@@ -243,6 +245,43 @@ def test_end_to_end_parity(variant, m, n, s, kappa):
     assert rd <= 100 * n * EPS * kappa + 1e-14
     if kappa <= 1e4:  # well-conditioned: Q agrees elementwise too
         assert np.max(np.abs(Q - ref["Q"])) <= 100 * n * EPS * kappa
+
+
+@pytest.mark.parametrize("m,n,s,kappa", [(3000, 600, 1200, 1e12), (2100, 1024, 2048, 1e8)])
+def test_end_to_end_wide_plain(m, n, s, kappa):
+    """The wide configuration's method (no extra pass) at sizes the oracle finishes:
+    column-blocked solves, the wide Gram kernel, blocked QR with narrow panels and the
+    16-column Cholesky panels."""
+    A = gen_matrix(m, n, kappa, 211103 + n)
+    Qd, Rd, info = tsqr.rxr_cholqr(dev(A), s, 11103, extra_pass=False)
+    Q, R = host(Qd), host(Rd)
+    assert int(info.item()) == 0
+    ref = oracle.rxr_cholqr(A, s, 11103, extra_pass=False)
+    ortho, res = oracle.orthogonality(Q), oracle.residual(A, Q, R)
+    rd = rel_fro(R, ref["R"])
+    print(f"m={m} n={n} s={s} kappa={kappa:g}: ortho={ortho:.2e} (oracle "
+          f"{oracle.orthogonality(ref['Q']):.2e}) res={res:.2e} relR={rd:.2e}")
+    assert np.all(np.tril(R, -1) == 0) and np.all(np.diag(R) > 0)
+    # one CholeskyQR pass on the preconditioned matrix: orthogonality ~ u cond(A1)^2, with
+    # cond(A1) = O(1) (Section 3); residual at the FP64 level
+    assert ortho <= 1e-12 and res <= 1e-13
+    assert rd <= 100 * n * EPS * kappa + 1e-14
+
+
+def test_end_to_end_wide_full_size():
+    """The wide configuration at full size (2^18 x 1024, s = 2048, kappa = 1e12, no extra
+    pass): FP64 targets on the device metrics."""
+    m, n, s = 1 << 18, 1024, 2048
+    A = gen_matrix(m, n, 1e12, 211103)
+    Ad = dev(A)
+    del A
+    Qd, Rd, info = tsqr.rxr_cholqr(Ad, s, 11103, extra_pass=False)
+    assert int(info.item()) == 0
+    ortho, res = gpu_orthogonality(Qd), gpu_residual(Ad, Qd, Rd)
+    print(f"wide full size: ortho={ortho:.2e} res={res:.2e}")
+    assert ortho <= 1e-12 and res <= 1e-13
+    R = host(Rd)
+    assert np.all(np.tril(R, -1) == 0) and np.all(np.diag(R) > 0)
 
 
 def test_end_to_end_plain_forms_and_rless():
