@@ -169,11 +169,156 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_lowp(
   }
 }
 
+// Wide sketch (129..256 columns): every normal is generated once. A workgroup owns NW*IT
+// i-tiles (IT per wavefront) and all 16 column tiles of a row block, so the igroups
+// workgroups of one row block each read the whole block. They get consecutive slots on
+// one XCD (workgroup L runs on XCD L % 8), start together and read the block in the same
+// order, so all but one of them find it in that XCD's L2. A is staged through LDS in
+// 32-row chunks, the next chunk's loads in flight during the current chunk's products;
+// the FP32 accumulators are flushed into FP64 every two chunks (64 rows).
+template <int PREC, int NW, int IT>
+__global__ __launch_bounds__(NW * 64) void k_sketch_lowp_wide(
+    int64_t m, int n, const double* __restrict__ A, int64_t lda, uint32_t k0, uint32_t k1,
+    int64_t rows_per_block, int it_total, int jt_total, int igroups, int kblocks,
+    double* __restrict__ part) {
+  typedef typename LowT<PREC>::E E;
+  typedef __attribute__((address_space(1))) const double g_f64;
+  constexpr int JT = 16, KC = 32, T = NW * 64;
+  constexpr int LDR = KC + (PREC == TSQR_LOWP_FP32 ? 4 : 8);
+  constexpr int PF = KC * 16 * JT / T;  // prefetched doubles per thread
+  __shared__ __attribute__((aligned(16))) E lds[16 * JT * LDR];
+
+  const int G = kblocks * igroups;
+  const int gp8 = (G + 7) / 8;
+  const int v = (int)(blockIdx.x % 8) * gp8 + (int)(blockIdx.x / 8);
+  if (v >= G) return;  // padding workgroup: exits before any barrier
+  const int kb = v / igroups, ig = v % igroups;
+
+  const int lane = lane_id(), wave = wave_id();
+  const int q = lane >> 4, c16 = lane & 15;
+  const int64_t r0 = (int64_t)kb * rows_per_block;
+  const int64_t r1 = min(m, r0 + rows_per_block);
+  const int it0 = (ig * NW + wave) * IT;
+  // staging: thread t moves row t % 32 of columns t / 32 + (T/32) k, k = 0..PF-1
+  const int srow = (int)threadIdx.x % KC, scol = (int)threadIdx.x / KC;
+
+  v4f acc[IT][JT];
+  v4d acc64[IT][JT];
+#pragma unroll
+  for (int ii = 0; ii < IT; ++ii)
+#pragma unroll
+    for (int jt = 0; jt < JT; ++jt) {
+      acc[ii][jt] = v4f{0.f, 0.f, 0.f, 0.f};
+      acc64[ii][jt] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+
+  double pf[PF];
+  auto fetch = [&](int64_t rb) {
+    const int64_t row = rb + srow;
+    // a row past the block reads row r0 and a column past n reads column scol (< n): both
+    // valid addresses, zeroed when staged
+    g_f64* bp = (g_f64*)(A + (int64_t)scol * lda + (row < r1 ? row : r0));
+    int lim = n - scol;  // column scol + (T/KC) k exists iff (T/KC) k < lim
+    int64_t cstep = (int64_t)(T / KC) * lda;  // uniform: the offsets stay scalar per fetch
+    asm volatile("" : "+v"(bp), "+v"(lim), "+s"(cstep));
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const bool ok = (T / KC) * k < lim;
+      pf[k] = bp[ok ? k * cstep : 0];
+    }
+  };
+  fetch(r0);
+  // 64 rows (two chunks) per iteration, then the flush; a chunk past r1 stages zeros
+  for (int64_t rb0 = r0; rb0 < r1; rb0 += 2 * KC) {
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      const int64_t rb = rb0 + hh * KC;
+      __syncthreads();
+      {
+        const bool rok = rb + srow < r1;
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+          const int col = scol + (T / KC) * k;
+          lds[col * LDR + srow] = LowT<PREC>::from_double((rok && col < n) ? pf[k] : 0.0);
+        }
+      }
+      __syncthreads();
+      fetch(rb + KC);  // clamped: always valid addresses
+      if constexpr (PREC == TSQR_LOWP_FP32) {
+#pragma unroll
+        for (int g = 0; g < KC / 16; ++g) {
+          float z[IT][4];
+#pragma unroll
+          for (int ii = 0; ii < IT; ++ii)
+            sketch_normals4((uint64_t)((rb + 16 * g) >> 2) + (uint64_t)q,
+                            (uint32_t)((it0 + ii) * 16 + c16), k0, k1, z[ii]);
+#pragma unroll
+          for (int jt = 0; jt < JT; ++jt) {
+            typedef __attribute__((address_space(3))) const v4f lds_v4f;
+            const v4f b4 = *(lds_v4f*)((__attribute__((address_space(3))) const E*)lds +
+                                       (16 * jt + c16) * LDR + 16 * g + 4 * q);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+              for (int ii = 0; ii < IT; ++ii)
+                acc[ii][jt] = mfma_f32(z[ii][t], b4[t], acc[ii][jt]);
+            // bounded look-ahead of the operand reads (registers)
+            if (jt % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+      } else {
+        v8bf a8[IT];
+#pragma unroll
+        for (int ii = 0; ii < IT; ++ii) {
+          float z[8];
+          const uint32_t irow = (uint32_t)((it0 + ii) * 16 + c16);
+          const uint64_t p = (uint64_t)(rb >> 2) + 2 * (uint64_t)q;
+          sketch_normals4(p, irow, k0, k1, z);
+          sketch_normals4(p + 1, irow, k0, k1, z + 4);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) a8[ii][e] = (__bf16)z[e];
+        }
+#pragma unroll
+        for (int jt = 0; jt < JT; ++jt) {
+          typedef __attribute__((address_space(3))) const v8bf lds_v8bf;
+          const v8bf b8 = *(lds_v8bf*)((__attribute__((address_space(3))) const E*)lds +
+                                       (16 * jt + c16) * LDR + 8 * q);
+#pragma unroll
+          for (int ii = 0; ii < IT; ++ii) acc[ii][jt] = mfma_bf16(a8[ii], b8, acc[ii][jt]);
+          if (jt % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    }
+    // FP32 accumulation over 64 rows, then into FP64
+#pragma unroll
+    for (int ii = 0; ii < IT; ++ii)
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc64[ii][jt][r] += (double)acc[ii][jt][r];
+        acc[ii][jt] = v4f{0.f, 0.f, 0.f, 0.f};
+      }
+  }
+
+#pragma unroll
+  for (int ii = 0; ii < IT; ++ii) {
+    const int it = it0 + ii;
+    double* dst = part + ((size_t)kb * it_total + it) * jt_total * 256;
+#pragma unroll
+    for (int jt = 0; jt < JT; ++jt)
+      if (it < it_total && jt < jt_total)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          dst[(size_t)jt * 256 + lowp_to_f64_tile_index(lane, r)] = acc64[ii][jt][r];
+  }
+}
+
 // ======================================================== apply A1 = A R0^{-1} ====
 // Rinv (n x n upper, FP64) is rounded into the input type and laid out for the A
-// operand: FP32 as upper 16x16 tiles (tile (a,b) row-major at tri_index(a,b)*256), BF16
-// as a padded column-major matrix (ld = rinv_bf16_ld(JT)) so eight consecutive k of a
-// column are one 16-byte read.
+// operand. FP32: upper 16x16 tiles, tile (a,b) at tri_index(a,b)*256, and inside a tile
+// entry (k, c) at c*16 + (k%4)*4 + k/4, so the four K-steps one lane feeds for a tile are
+// one 16-byte read. BF16: a padded column-major matrix (ld = rinv_bf16_ld(JT)) so eight
+// consecutive k of a column are one 16-byte read.
 __host__ __device__ constexpr int lp_tri_index(int a, int b) { return b * (b + 1) / 2 + a; }
 
 // BF16 layout leading dimension: every K-group of 32 rows that a column tile reads must lie
@@ -198,8 +343,8 @@ __global__ void k_rinv_prep(int n, int jt, const double* __restrict__ Rinv, int6
       int b = 0;
       while ((b + 1) * (b + 2) / 2 <= t) ++b;
       const int a = t - b * (b + 1) / 2;
-      k = 16 * a + w / 16;
-      c = 16 * b + w % 16;
+      k = 16 * a + 4 * (w % 4) + (w % 16) / 4;
+      c = 16 * b + w / 16;
     } else {
       const int ld = rinv_bf16_ld(jt);
       c = (int)(e / ld);
@@ -211,14 +356,28 @@ __global__ void k_rinv_prep(int n, int jt, const double* __restrict__ Rinv, int6
 }
 
 // One wavefront per 16-row tile; output X = Y Rinv in the input type (column-major).
+// Rinv sits once per workgroup in LDS and the workgroup is persistent over the row tiles.
+// Each wavefront computes its output blocks in two halves (b < JT/2, then b >= JT/2) so
+// that half the accumulators suffice, and loads a half's new K-columns of Y only once the
+// previous half is stored, which caps the FP64 values in flight at half a tile.
 // FP32: K-step kk of block a feeds Y(row, 16a + 4kk + q) as the B operand.
 // BF16: K-group g feeds Y(row, 32g + 8q .. 32g + 8q + 7).
-template <int PREC, int JT>
-__global__ __launch_bounds__(256) void k_apply_rinv_lowp(
+// FULL (n == 16 JT, and JT even for BF16): no column bounds. Otherwise a column past n
+// loads column 0 of the same row (always a valid address) and is replaced by zero, without
+// branches.
+// 16 wavefronts per workgroup up to 64 columns; the wider blocks need more registers per
+// lane, so they run 8 wavefronts (two per SIMD) with a 256-register budget.
+__host__ __device__ constexpr int apply_threads(int jt) { return jt >= 8 ? 512 : 1024; }
+
+template <int PREC, int JT, bool FULL>
+__global__ __launch_bounds__(apply_threads(JT)) void k_apply_rinv_lowp(
     int64_t m, int n, const double* __restrict__ Y, int64_t ldy,
     const typename LowT<PREC>::E* __restrict__ Ri, typename LowT<PREC>::E* X, int64_t ldx) {
   typedef typename LowT<PREC>::E E;
+  typedef __attribute__((address_space(1))) const double g_f64;
+  typedef __attribute__((address_space(3))) E lds_e;
   constexpr size_t NE = rinv_elems<PREC>(JT);
+  constexpr int HB = JT > 1 ? JT / 2 : 1;  // output blocks per half
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   E* rl = reinterpret_cast<E*>(smem);
   for (size_t e = threadIdx.x; e < NE; e += blockDim.x) rl[e] = Ri[e];
@@ -230,58 +389,111 @@ __global__ __launch_bounds__(256) void k_apply_rinv_lowp(
   const int64_t wstride = (int64_t)gridDim.x * (blockDim.x / kWave);
   for (int64_t tile = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); tile < ntiles;
        tile += wstride) {
-    typedef __attribute__((address_space(3))) E lds_e;
-    lds_e* rp = (lds_e*)rl;
-    asm volatile("" : "+v"(rp));
     const int64_t row = tile * 16 + c16;
     const bool rok = row < m;
-    v4f acc[JT];
-#pragma unroll
-    for (int b = 0; b < JT; ++b) acc[b] = v4f{0.f, 0.f, 0.f, 0.f};
-    if (PREC == TSQR_LOWP_FP32) {
+    const int64_t rowc = rok ? row : 0;  // clamped, always a valid address
+    if constexpr (PREC == TSQR_LOWP_FP32) {
+      g_f64* yb = (g_f64*)(Y + rowc + (int64_t)q * ldy);  // this lane's column q
+      const int64_t back = -(int64_t)q * ldy;              // column 0 of the same row
       float yv[JT][4];
 #pragma unroll
-      for (int a = 0; a < JT; ++a)
+      for (int h = 0; h < JT; h += HB) {
+        // opaque per half: keeps the address arithmetic and the column masks (which do
+        // not change over tiles) from being hoisted out of the tile loop into registers
+        int lim = n - q;  // this lane's column 16a + 4kk + q exists iff 16a + 4kk < lim
+        asm volatile("" : "+v"(yb), "+v"(lim));
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const int col = 16 * a + 4 * kk + q;
-          yv[a][kk] = (rok && col < n) ? (float)Y[(int64_t)col * ldy + row] : 0.f;
+        for (int a = h; a < h + HB; ++a)
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const int c0 = 16 * a + 4 * kk;
+            double v;
+            if constexpr (FULL) {
+              v = yb[(int64_t)c0 * ldy];
+            } else {
+              const bool ok = c0 < lim;
+              v = yb[ok ? (int64_t)c0 * ldy : back];
+              v = ok ? v : 0.0;
+            }
+            yv[a][kk] = rok ? (float)v : 0.f;
+          }
+        v4f acc[HB];
+#pragma unroll
+        for (int u = 0; u < HB; ++u) acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int u = 0; u < HB; ++u) {
+          const int b = h + u;
+          // opaque per-block pointer: the block's operand reads stay next to its MFMAs
+          lds_e* rp = (lds_e*)rl + c16 * 16 + q * 4;
+          asm volatile("" : "+v"(rp));
+#pragma unroll
+          for (int a = 0; a <= b; ++a) {
+            typedef __attribute__((address_space(3))) v4f lds_v4f;
+            const v4f r4 = *(lds_v4f*)(rp + lp_tri_index(a, b) * 256);
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) acc[u] = mfma_f32(r4[kk], yv[a][kk], acc[u]);
+          }
         }
+        if (rok)
 #pragma unroll
-      for (int b = 0; b < JT; ++b)
+          for (int u = 0; u < HB; ++u)
 #pragma unroll
-        for (int a = 0; a <= b; ++a)
-#pragma unroll
-          for (int kk = 0; kk < 4; ++kk)
-            acc[b] = mfma_f32((float)rp[lp_tri_index(a, b) * 256 + (4 * kk + q) * 16 + c16],
-                              yv[a][kk], acc[b]);
+            for (int r = 0; r < 4; ++r) {
+              const int col = 16 * (h + u) + 4 * q + r;
+              if (FULL || col < n) X[(int64_t)col * ldx + row] = acc[u][r];
+            }
+      }
     } else {
       constexpr int NG = (JT + 1) / 2;  // K-groups of 32 columns
       constexpr int LD = rinv_bf16_ld(JT);
+      g_f64* yb = (g_f64*)(Y + rowc + (int64_t)(8 * q) * ldy);  // this lane's column 8q
+      const int64_t back = -(int64_t)(8 * q) * ldy;
       v8bf yv[NG];
 #pragma unroll
-      for (int g = 0; g < NG; ++g)
+      for (int h = 0; h < JT; h += HB) {
+        int lim = n - 8 * q;  // this lane's column c0 + 8q exists iff c0 < lim
+        asm volatile("" : "+v"(yb), "+v"(lim));
+        // the half's new K-groups (blocks before h already loaded theirs)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int col = 32 * g + 8 * q + e;
-          yv[g][e] = LowT<PREC>::from_double((rok && col < n) ? Y[(int64_t)col * ldy + row] : 0.0);
+        for (int g = (h + 1) / 2; g < (h + HB + 1) / 2 && g < NG; ++g)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int c0 = 32 * g + e;  // this lane's column is c0 + 8q
+            double v;
+            if constexpr (FULL) {
+              v = yb[(int64_t)c0 * ldy];
+            } else {
+              const bool ok = c0 < lim;
+              v = yb[ok ? (int64_t)c0 * ldy : back];
+              v = ok ? v : 0.0;
+            }
+            yv[g][e] = LowT<PREC>::from_double(rok ? v : 0.0);
+          }
+        v4f acc[HB];
+#pragma unroll
+        for (int u = 0; u < HB; ++u) acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int u = 0; u < HB; ++u) {
+          const int b = h + u;
+          lds_e* rp = (lds_e*)rl + (16 * b + c16) * LD + 8 * q;
+          asm volatile("" : "+v"(rp));
+#pragma unroll
+          for (int g = 0; g <= b / 2; ++g) {
+            typedef __attribute__((address_space(3))) v8bf lds_v8bf;
+            const v8bf a8 = *(lds_v8bf*)(rp + 32 * g);
+            acc[u] = mfma_bf16(a8, yv[g], acc[u]);
+          }
         }
+        if (rok)
 #pragma unroll
-      for (int b = 0; b < JT; ++b)
+          for (int u = 0; u < HB; ++u)
 #pragma unroll
-        for (int g = 0; g <= b / 2; ++g) {
-          const v8bf a8 = *reinterpret_cast<const v8bf*>((const E*)rp + (16 * b + c16) * LD + 32 * g + 8 * q);
-          acc[b] = mfma_bf16(a8, yv[g], acc[b]);
-        }
-    }
-    if (rok) {
-#pragma unroll
-      for (int b = 0; b < JT; ++b)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int col = 16 * b + 4 * q + r;
-          if (col < n) X[(int64_t)col * ldx + row] = LowT<PREC>::from_float(acc[b][r]);
-        }
+            for (int r = 0; r < 4; ++r) {
+              const int col = 16 * (h + u) + 4 * q + r;
+              if (FULL || col < n)
+                X[(int64_t)col * ldx + row] = LowT<PREC>::from_float(acc[u][r]);
+            }
+      }
     }
   }
 }
@@ -481,8 +693,31 @@ static hipError_t sketch_lowp_t(const SketchPlan& p, int64_t m, int n, const dou
   return hipGetLastError();
 }
 
+#ifndef TSQR_SKW_NW
+#define TSQR_SKW_NW 8
+#define TSQR_SKW_IT 1
+#endif
+constexpr int kSkwNW = TSQR_SKW_NW, kSkwIT = TSQR_SKW_IT;
+
 hipError_t launch_sketch_lowp(int prec, const SketchPlan& p, int64_t m, int n, const double* A,
                               int64_t lda, uint64_t seed, double* part, hipStream_t st) {
+  if (p.jt_total > 8) {
+    // all columns per workgroup; same row blocks (and partial layout) as the plan
+    constexpr int NW = kSkwNW, IT = kSkwIT;
+    const int igroups = (p.it_total + NW * IT - 1) / (NW * IT);
+    const int G = p.kblocks * igroups;
+    const dim3 grid((unsigned)((G + 7) / 8 * 8)), block(NW * 64);
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    if (prec == TSQR_LOWP_FP32)
+      hipLaunchKernelGGL((k_sketch_lowp_wide<TSQR_LOWP_FP32, NW, IT>), grid, block, 0, st, m, n,
+                         A, lda, k0, k1, p.rows_per_block, p.it_total, p.jt_total, igroups,
+                         p.kblocks, part);
+    else
+      hipLaunchKernelGGL((k_sketch_lowp_wide<TSQR_LOWP_BF16, NW, IT>), grid, block, 0, st, m, n,
+                         A, lda, k0, k1, p.rows_per_block, p.it_total, p.jt_total, igroups,
+                         p.kblocks, part);
+    return hipGetLastError();
+  }
 #define TSQR_SKL(PR, IT_, JT_, NW_)                                                           \
   if (prec == PR && p.IT == IT_ && p.JT == JT_ && p.NW == NW_)                                \
     return sketch_lowp_t<PR, IT_, JT_, NW_>(p, m, n, A, lda, seed, part, st);
@@ -519,16 +754,24 @@ hipError_t launch_apply_rinv_lowp(int prec, int64_t m, int n, const double* Y, i
                                   const void* Ri, void* X, int64_t ldx, hipStream_t st) {
   const int jt = jt_pow2(n);
   const int64_t ntiles = (m + 15) / 16;
-  int64_t blocks = (ntiles + 3) / 4;
-  const int64_t cap = (int64_t)device_cu_count() * 4;
+  const int nt = apply_threads(jt);
+  int64_t blocks = (ntiles + nt / kWave - 1) / (nt / kWave);
+  const int64_t cap = (int64_t)device_cu_count();  // one workgroup (and one Rinv copy) per CU
   if (blocks > cap) blocks = cap;
-  dim3 grid((unsigned)blocks), block(256);
+  dim3 grid((unsigned)blocks), block(nt);
+  // FULL drops the column bounds: every column a K-step reads must exist (BF16 reads whole
+  // 32-column groups, so a single 16-column tile never qualifies)
+  const bool full = n == 16 * jt && (prec == TSQR_LOWP_FP32 || jt % 2 == 0);
 #define TSQR_APL(PR, J)                                                                        \
   if (prec == PR && jt == J) {                                                                 \
     typedef typename LowT<PR>::E E;                                                            \
     const size_t sh = rinv_elems<PR>(J) * sizeof(E);                                           \
-    hipLaunchKernelGGL((k_apply_rinv_lowp<PR, J>), grid, block, sh, st, m, n, Y, ldy,           \
-                       (const E*)Ri, (E*)X, ldx);                                              \
+    if (full)                                                                                  \
+      hipLaunchKernelGGL((k_apply_rinv_lowp<PR, J, true>), grid, block, sh, st, m, n, Y, ldy,   \
+                         (const E*)Ri, (E*)X, ldx);                                            \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_apply_rinv_lowp<PR, J, false>), grid, block, sh, st, m, n, Y, ldy,  \
+                         (const E*)Ri, (E*)X, ldx);                                            \
     return hipGetLastError();                                                                  \
   }
   TSQR_APL(TSQR_LOWP_FP32, 1) TSQR_APL(TSQR_LOWP_FP32, 2) TSQR_APL(TSQR_LOWP_FP32, 4)

@@ -126,7 +126,37 @@ __device__ __forceinline__ void trsm_mfma_body(int64_t m, int n, const double* _
   const int64_t ntiles = (m + 15) / 16;
   const int nw = blockDim.x / kWave;
   const int64_t wstride = (int64_t)nwg * nw;
-  for (int64_t tile = (int64_t)wg * nw + wave_id(); tile < ntiles; tile += wstride) {
+  typedef __attribute__((address_space(1))) const double g_f64;
+  // Y(row, 16b + 4q + r) of a tile into x[b][r]; a row past m reads row 0 and a column
+  // past n reads column 0 of the same row (valid addresses: column 4q itself need not
+  // exist when n <= 12), both replaced by zero
+  auto load_tile = [&](int64_t tile, v4d (&x)[JT]) {
+    const int64_t row = tile * 16 + c16;
+    const bool rok = row < m;
+    g_f64* yb = (g_f64*)(Y + (rok ? row : 0) + (int64_t)(4 * q) * ldy);
+    int lim = n - 4 * q;  // column 16b + 4q + r exists iff 16b + r < lim
+    int64_t cstep = ldy;
+    asm volatile("" : "+v"(yb), "+v"(lim), "+s"(cstep));
+    const int64_t back = -(int64_t)(4 * q) * cstep;  // from column 4q back to column 0
+#pragma unroll
+    for (int b = 0; b < JT; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const bool ok = 16 * b + r < lim;
+        const double v = yb[ok ? (16 * b + r) * cstep : back];
+        x[b][r] = (rok && ok) ? v : 0.0;
+      }
+  };
+
+  int64_t tile = (int64_t)wg * nw + wave_id();
+  v4d xr[JT];
+  if (tile < ntiles) load_tile(tile, xr);
+  for (; tile < ntiles; tile += wstride) {
+    // the next tile's loads are in flight while this tile is solved (the last tile
+    // re-reads itself instead: always a valid address)
+    const int64_t nxt = tile + wstride < ntiles ? tile + wstride : tile;
+    v4d xn[JT];
+    load_tile(nxt, xn);
     // opaque per-iteration bases: the tiles are loop invariant and would otherwise be
     // hoisted into registers
     lds_f64* tlp = (lds_f64*)tl;
@@ -138,14 +168,6 @@ __device__ __forceinline__ void trsm_mfma_body(int64_t m, int n, const double* _
     };
     const int64_t row = tile * 16 + c16;
     const bool rok = row < m;
-    v4d xr[JT];
-#pragma unroll
-    for (int b = 0; b < JT; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int col = 16 * b + 4 * q + r;
-        xr[b][r] = (rok && col < n) ? Y[(int64_t)col * ldy + row] : 0.0;
-      }
 
 #pragma unroll
     for (int b = 0; b < JT; ++b) {
@@ -179,6 +201,8 @@ __device__ __forceinline__ void trsm_mfma_body(int64_t m, int n, const double* _
           if (col < n) X[(int64_t)col * ldx + row] = xr[b][r];
         }
     }
+#pragma unroll
+    for (int b = 0; b < JT; ++b) xr[b] = xn[b];
   }
 }
 

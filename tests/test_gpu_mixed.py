@@ -81,7 +81,8 @@ def to_lowp_device(Xh, prec):
 # ---------------------------------------------------------------------------- sketch --
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("m,n,s", [(4096, 32, 64), (1000, 5, 7), (1027, 17, 40), (3000, 128, 256),
-                                   (777, 1, 1), (2050, 100, 100), (4100, 256, 512)])
+                                   (777, 1, 1), (2050, 100, 100), (4100, 256, 512),
+                                   (3001, 200, 300), (5000, 144, 150), (700, 130, 20)])
 def test_sketch_lowp_parity(prec, m, n, s):
     A = gen_matrix(m, n, 1e6, 400 + m)
     seed = 11104 + n

@@ -284,6 +284,44 @@ def test_end_to_end_wide_full_size():
     assert np.all(np.tril(R, -1) == 0) and np.all(np.diag(R) > 0)
 
 
+@pytest.fixture(scope="module")
+def tall128():
+    m, n, s = 1 << 20, 128, 256
+    A = gen_matrix(m, n, 1e14, 211102)
+    return A, dev(A), s
+
+
+@pytest.mark.parametrize("variant", [tsqr.RQR, tsqr.RLU])
+def test_end_to_end_tall128_full_size(tall128, variant):
+    """The benchmark's workload (2^20 x 128, s = 256, kappa = 1e14, one extra pass) through
+    the same explicit-workspace call the benchmark times: FP64 targets on the device
+    metrics, R upper with a positive diagonal."""
+    A, Ad, s = tall128
+    m, n = A.shape
+    work = tsqr.alloc_workspace(m, n, s)
+    Qd, Rd, info = tsqr.rxr_cholqr(Ad, s, 11102, variant=variant, workspace=work)
+    assert int(info.item()) == 0
+    ortho, res = gpu_orthogonality(Qd), gpu_residual(Ad, Qd, Rd)
+    print(f"tall128 variant={variant}: ortho={ortho:.2e} res={res:.2e}")
+    assert ortho <= 1e-12 and res <= 1e-13
+    R = host(Rd)
+    assert np.all(np.tril(R, -1) == 0) and np.all(np.diag(R) > 0)
+
+
+def test_tall128_sketch_sampled_rows(tall128):
+    """Rows of the full-size sketch against the oracle's normals, one row at a time."""
+    A, Ad, s = tall128
+    m = A.shape[0]
+    Bg = host(tsqr.sketch(Ad, s, 11102))
+    absA = np.abs(A)
+    rs = 1.0 / math.sqrt(s)
+    for i in (0, 63, 200, 255):
+        z = oracle.sketch_normals(11102, i, 1, 0, m)[0]
+        exact = rs * (z @ A)
+        tol = rs * (NORMAL_ABS_TOL * absA.sum(axis=0) + 4 * m * U * (np.abs(z) @ absA))
+        assert np.all(np.abs(Bg[i] - exact) <= tol), i
+
+
 def test_end_to_end_plain_forms_and_rless():
     m, n, s = 4096, 32, 64
     A = gen_matrix(m, n, 1e10, 211101)
