@@ -357,27 +357,33 @@ __global__ void k_rinv_prep(int n, int jt, const double* __restrict__ Rinv, int6
 
 // One wavefront per 16-row tile; output X = Y Rinv in the input type (column-major).
 // Rinv sits once per workgroup in LDS and the workgroup is persistent over the row tiles.
-// Each wavefront computes its output blocks in two halves (b < JT/2, then b >= JT/2) so
-// that half the accumulators suffice, and loads a half's new K-columns of Y only once the
-// previous half is stored, which caps the FP64 values in flight at half a tile.
+// K-outer order: K-block a of Y (FP32: 16 columns; BF16: a group of 32) adds its products
+// to every output block b >= a, after which output block a is final and stored. Only the
+// accumulators stay resident; Y streams through a ring of D blocks, each loaded D steps
+// ahead (past the tile's last block: the next tile's first blocks), so the loads overlap
+// the products of the blocks before them.
 // FP32: K-step kk of block a feeds Y(row, 16a + 4kk + q) as the B operand.
-// BF16: K-group g feeds Y(row, 32g + 8q .. 32g + 8q + 7).
+// BF16: group g feeds Y(row, 32g + 8q .. 32g + 8q + 7).
 // FULL (n == 16 JT, and JT even for BF16): no column bounds. Otherwise a column past n
 // loads column 0 of the same row (always a valid address) and is replaced by zero, without
-// branches.
-// 16 wavefronts per workgroup up to 64 columns; the wider blocks need more registers per
-// lane, so they run 8 wavefronts (two per SIMD) with a 256-register budget.
-__host__ __device__ constexpr int apply_threads(int jt) { return jt >= 8 ? 512 : 1024; }
+// branches; a row past m loads row 0 and is not stored.
+constexpr int kApplyThreads = 1024;
 
 template <int PREC, int JT, bool FULL>
-__global__ __launch_bounds__(apply_threads(JT)) void k_apply_rinv_lowp(
+__global__ __launch_bounds__(kApplyThreads) void k_apply_rinv_lowp(
     int64_t m, int n, const double* __restrict__ Y, int64_t ldy,
     const typename LowT<PREC>::E* __restrict__ Ri, typename LowT<PREC>::E* X, int64_t ldx) {
   typedef typename LowT<PREC>::E E;
   typedef __attribute__((address_space(1))) const double g_f64;
   typedef __attribute__((address_space(3))) E lds_e;
+  constexpr bool F32 = PREC == TSQR_LOWP_FP32;
   constexpr size_t NE = rinv_elems<PREC>(JT);
-  constexpr int HB = JT > 1 ? JT / 2 : 1;  // output blocks per half
+  constexpr int NK = F32 ? JT : (JT + 1) / 2;  // K-steps: blocks (FP32) or groups (BF16)
+  constexpr int CW = F32 ? 16 : 32;            // columns per K-step
+  constexpr int PL = F32 ? 4 : 8;              // doubles per lane per K-step
+  constexpr int QS = F32 ? 1 : 8;              // lane column stride in q
+  constexpr int D = NK < 2 ? NK : 2;           // ring depth (divides NK)
+  constexpr int LD = rinv_bf16_ld(JT);
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   E* rl = reinterpret_cast<E*>(smem);
   for (size_t e = threadIdx.x; e < NE; e += blockDim.x) rl[e] = Ri[e];
@@ -387,113 +393,85 @@ __global__ __launch_bounds__(apply_threads(JT)) void k_apply_rinv_lowp(
   const int q = lane >> 4, c16 = lane & 15;
   const int64_t ntiles = (m + 15) / 16;
   const int64_t wstride = (int64_t)gridDim.x * (blockDim.x / kWave);
-  for (int64_t tile = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); tile < ntiles;
-       tile += wstride) {
+
+  // column of element j of K-step k for this lane: CW k + QS q + (F32 ? 4 j : j)
+  auto col_of = [&](int k, int j) { return CW * k + QS * q + (F32 ? 4 * j : j); };
+  auto load_step = [&](int64_t t, int k, double (&d)[PL]) {
+    const int64_t row = t * 16 + c16;
+    g_f64* yb = (g_f64*)(Y + (row < m ? row : 0) + (int64_t)(QS * q) * ldy);
+    int lim = n - QS * q;  // column c0 + QS q exists iff c0 < lim
+    int64_t cstep = ldy;
+    asm volatile("" : "+v"(yb), "+v"(lim), "+s"(cstep));
+    const int64_t back = -(int64_t)(QS * q) * cstep;  // column 0 of the same row
+#pragma unroll
+    for (int j = 0; j < PL; ++j) {
+      const int c0 = CW * k + (F32 ? 4 * j : j);
+      const bool ok = FULL || c0 < lim;
+      d[j] = yb[ok ? c0 * cstep : back];
+    }
+  };
+
+  int64_t tile = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+  double ring[D][PL];
+  if (tile < ntiles) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) load_step(tile, k, ring[k]);
+  }
+  for (; tile < ntiles; tile += wstride) {
+    const int64_t nxt = tile + wstride < ntiles ? tile + wstride : tile;  // valid address
     const int64_t row = tile * 16 + c16;
     const bool rok = row < m;
-    const int64_t rowc = rok ? row : 0;  // clamped, always a valid address
-    if constexpr (PREC == TSQR_LOWP_FP32) {
-      g_f64* yb = (g_f64*)(Y + rowc + (int64_t)q * ldy);  // this lane's column q
-      const int64_t back = -(int64_t)q * ldy;              // column 0 of the same row
-      float yv[JT][4];
+    v4f acc[JT];
 #pragma unroll
-      for (int h = 0; h < JT; h += HB) {
-        // opaque per half: keeps the address arithmetic and the column masks (which do
-        // not change over tiles) from being hoisted out of the tile loop into registers
-        int lim = n - q;  // this lane's column 16a + 4kk + q exists iff 16a + 4kk < lim
-        asm volatile("" : "+v"(yb), "+v"(lim));
+    for (int b = 0; b < JT; ++b) acc[b] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int a = h; a < h + HB; ++a)
+    for (int k = 0; k < NK; ++k) {
+      // this step's operand in the input type, then its ring slot refilled D steps ahead
+      typename std::conditional<F32, v4f, v8bf>::type yv;
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) {
-            const int c0 = 16 * a + 4 * kk;
-            double v;
-            if constexpr (FULL) {
-              v = yb[(int64_t)c0 * ldy];
-            } else {
-              const bool ok = c0 < lim;
-              v = yb[ok ? (int64_t)c0 * ldy : back];
-              v = ok ? v : 0.0;
-            }
-            yv[a][kk] = rok ? (float)v : 0.f;
-          }
-        v4f acc[HB];
-#pragma unroll
-        for (int u = 0; u < HB; ++u) acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int u = 0; u < HB; ++u) {
-          const int b = h + u;
-          // opaque per-block pointer: the block's operand reads stay next to its MFMAs
-          lds_e* rp = (lds_e*)rl + c16 * 16 + q * 4;
-          asm volatile("" : "+v"(rp));
-#pragma unroll
-          for (int a = 0; a <= b; ++a) {
-            typedef __attribute__((address_space(3))) v4f lds_v4f;
-            const v4f r4 = *(lds_v4f*)(rp + lp_tri_index(a, b) * 256);
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) acc[u] = mfma_f32(r4[kk], yv[a][kk], acc[u]);
-          }
-        }
-        if (rok)
-#pragma unroll
-          for (int u = 0; u < HB; ++u)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int col = 16 * (h + u) + 4 * q + r;
-              if (FULL || col < n) X[(int64_t)col * ldx + row] = acc[u][r];
-            }
+      for (int j = 0; j < PL; ++j) {
+        const bool ok = rok && (FULL || col_of(k, j) < n);
+        if constexpr (F32) yv[j] = ok ? (float)ring[k % D][j] : 0.f;
+        else yv[j] = LowT<PREC>::from_double(ok ? ring[k % D][j] : 0.0);
       }
-    } else {
-      constexpr int NG = (JT + 1) / 2;  // K-groups of 32 columns
-      constexpr int LD = rinv_bf16_ld(JT);
-      g_f64* yb = (g_f64*)(Y + rowc + (int64_t)(8 * q) * ldy);  // this lane's column 8q
-      const int64_t back = -(int64_t)(8 * q) * ldy;
-      v8bf yv[NG];
+      if (k + D < NK) load_step(tile, k + D, ring[k % D]);
+      else load_step(nxt, k + D - NK, ring[k % D]);
+      if constexpr (F32) {
+        lds_e* rp = (lds_e*)rl + c16 * 16 + q * 4;
+        asm volatile("" : "+v"(rp));
 #pragma unroll
-      for (int h = 0; h < JT; h += HB) {
-        int lim = n - 8 * q;  // this lane's column c0 + 8q exists iff c0 < lim
-        asm volatile("" : "+v"(yb), "+v"(lim));
-        // the half's new K-groups (blocks before h already loaded theirs)
+        for (int b = k; b < JT; ++b) {
+          typedef __attribute__((address_space(3))) v4f lds_v4f;
+          const v4f r4 = *(lds_v4f*)(rp + lp_tri_index(k, b) * 256);
 #pragma unroll
-        for (int g = (h + 1) / 2; g < (h + HB + 1) / 2 && g < NG; ++g)
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const int c0 = 32 * g + e;  // this lane's column is c0 + 8q
-            double v;
-            if constexpr (FULL) {
-              v = yb[(int64_t)c0 * ldy];
-            } else {
-              const bool ok = c0 < lim;
-              v = yb[ok ? (int64_t)c0 * ldy : back];
-              v = ok ? v : 0.0;
-            }
-            yv[g][e] = LowT<PREC>::from_double(rok ? v : 0.0);
-          }
-        v4f acc[HB];
-#pragma unroll
-        for (int u = 0; u < HB; ++u) acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int u = 0; u < HB; ++u) {
-          const int b = h + u;
-          lds_e* rp = (lds_e*)rl + (16 * b + c16) * LD + 8 * q;
-          asm volatile("" : "+v"(rp));
-#pragma unroll
-          for (int g = 0; g <= b / 2; ++g) {
-            typedef __attribute__((address_space(3))) v8bf lds_v8bf;
-            const v8bf a8 = *(lds_v8bf*)(rp + 32 * g);
-            acc[u] = mfma_bf16(a8, yv[g], acc[u]);
-          }
+          for (int kk = 0; kk < 4; ++kk) acc[b] = mfma_f32(r4[kk], yv[kk], acc[b]);
+          if ((b - k) % 4 == 3) __builtin_amdgcn_sched_barrier(0);  // bounded look-ahead
         }
-        if (rok)
+      } else {
+        lds_e* rp = (lds_e*)rl + c16 * LD + 8 * q + 32 * k;
+        asm volatile("" : "+v"(rp));
 #pragma unroll
-          for (int u = 0; u < HB; ++u)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int col = 16 * (h + u) + 4 * q + r;
-              if (FULL || col < n)
-                X[(int64_t)col * ldx + row] = LowT<PREC>::from_float(acc[u][r]);
-            }
+        for (int b = 2 * k; b < JT; ++b) {
+          typedef __attribute__((address_space(3))) v8bf lds_v8bf;
+          const v8bf a8 = *(lds_v8bf*)(rp + 16 * b * LD);
+          acc[b] = mfma_bf16(a8, yv, acc[b]);
+          if ((b - 2 * k) % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+        }
       }
+      // output blocks completed by this step: an opaque per-step base and uniform column
+      // offsets (the per-lane column products would otherwise be hoisted for all blocks)
+      if (rok) {
+        E* xb = X + row + (int64_t)(4 * q) * ldx;
+        int64_t xs = ldx;
+        asm volatile("" : "+v"(xb), "+s"(xs));
+#pragma unroll
+        for (int b = F32 ? k : 2 * k; b < (F32 ? k + 1 : 2 * k + 2) && b < JT; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (FULL || 16 * b + 4 * q + r < n)
+              xb[(16 * b + r) * xs] = LowT<PREC>::from_float(acc[b][r]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
@@ -754,7 +732,7 @@ hipError_t launch_apply_rinv_lowp(int prec, int64_t m, int n, const double* Y, i
                                   const void* Ri, void* X, int64_t ldx, hipStream_t st) {
   const int jt = jt_pow2(n);
   const int64_t ntiles = (m + 15) / 16;
-  const int nt = apply_threads(jt);
+  const int nt = kApplyThreads;
   int64_t blocks = (ntiles + nt / kWave - 1) / (nt / kWave);
   const int64_t cap = (int64_t)device_cu_count();  // one workgroup (and one Rinv copy) per CU
   if (blocks > cap) blocks = cap;

@@ -106,6 +106,10 @@ __global__ __launch_bounds__(256) void k_trsm_prep(int n, int jt, const double* 
   trsm_prep_body(n, jt, T, ldt, P, (int)blockIdx.x);
 }
 
+#ifndef TSQR_TRSM_PF
+#define TSQR_TRSM_PF 1
+#define TSQR_TRSM_THREADS 512
+#endif
 // Body of workgroup `wg` of `nwg` (persistent over 16-row tiles).
 template <int JT, bool kLds>
 __device__ __forceinline__ void trsm_mfma_body(int64_t m, int n, const double* __restrict__ Y,
@@ -150,13 +154,14 @@ __device__ __forceinline__ void trsm_mfma_body(int64_t m, int n, const double* _
 
   int64_t tile = (int64_t)wg * nw + wave_id();
   v4d xr[JT];
-  if (tile < ntiles) load_tile(tile, xr);
+  if (TSQR_TRSM_PF && tile < ntiles) load_tile(tile, xr);
   for (; tile < ntiles; tile += wstride) {
     // the next tile's loads are in flight while this tile is solved (the last tile
     // re-reads itself instead: always a valid address)
     const int64_t nxt = tile + wstride < ntiles ? tile + wstride : tile;
     v4d xn[JT];
-    load_tile(nxt, xn);
+    if (TSQR_TRSM_PF) load_tile(nxt, xn);
+    else load_tile(tile, xr);
     // opaque per-iteration bases: the tiles are loop invariant and would otherwise be
     // hoisted into registers
     lds_f64* tlp = (lds_f64*)tl;
@@ -193,21 +198,24 @@ __device__ __forceinline__ void trsm_mfma_body(int64_t m, int n, const double* _
     }
 
     if (rok) {
+      // opaque base and uniform column offsets (per-lane column products would be hoisted)
+      double* xb = X + row + (int64_t)(4 * q) * ldx;
+      int64_t xs = ldx;
+      asm volatile("" : "+v"(xb), "+s"(xs));
 #pragma unroll
       for (int b = 0; b < JT; ++b)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int col = 16 * b + 4 * q + r;
-          if (col < n) X[(int64_t)col * ldx + row] = xr[b][r];
-        }
+        for (int r = 0; r < 4; ++r)
+          if (16 * b + 4 * q + r < n) xb[(16 * b + r) * xs] = xr[b][r];
     }
+    if (TSQR_TRSM_PF)
 #pragma unroll
-    for (int b = 0; b < JT; ++b) xr[b] = xn[b];
+      for (int b = 0; b < JT; ++b) xr[b] = xn[b];
   }
 }
 
 template <int JT, bool kLds>
-__global__ __launch_bounds__(512, 1) void k_trsm_mfma(int64_t m, int n,
+__global__ __launch_bounds__(TSQR_TRSM_THREADS, 1) void k_trsm_mfma(int64_t m, int n,
                                                       const double* __restrict__ Y, int64_t ldy,
                                                       const double* __restrict__ P,
                                                       double* X, int64_t ldx) {
@@ -354,10 +362,10 @@ static hipError_t launch_trsm_block(int64_t m, int n, const double* Y, int64_t l
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t ntiles = (m + 15) / 16;
-  int64_t blocks = (ntiles + 7) / 8;
+  int64_t blocks = (ntiles + TSQR_TRSM_THREADS / 64 - 1) / (TSQR_TRSM_THREADS / 64);
   const int64_t cap = (int64_t)device_cu_count();
   if (blocks > cap) blocks = cap;
-  dim3 grid((unsigned)blocks), block(512);
+  dim3 grid((unsigned)blocks), block(TSQR_TRSM_THREADS);
 #define TSQR_TRSM(J, L)                                                                    \
   if (jt == J) {                                                                           \
     const size_t sh = L ? (size_t)(J * (J - 1) / 2 + 2 * J) * 256 * sizeof(double) : 0;    \
@@ -426,7 +434,7 @@ __device__ __forceinline__ void gram_f64_body(int64_t m, int n, const double* __
   constexpr int CPP = THREADS / (KC / 2);  // columns loaded per pass
   constexpr int PASSES = (NC + CPP - 1) / CPP;
   static_assert(STRIDE <= 16, "slot dispatch covers at most 16 slots");
-  __shared__ double lds[KC * LDN];
+  __shared__ double lds[2][KC * LDN];  // double buffer: one barrier per chunk
 
   const int lane = lane_id(), wave = wave_id();
   const int q = lane >> 4, c16 = lane & 15;
@@ -462,20 +470,28 @@ __device__ __forceinline__ void gram_f64_body(int64_t m, int n, const double* __
     }
   };
 
-  if (r0 < r1) load_chunk(r0);
-  for (int64_t rb = r0; rb < r1; rb += KC) {
-    __syncthreads();
+  auto stage = [&](double* buf) {
 #pragma unroll
     for (int ps = 0; ps < PASSES; ++ps) {
       const int cc = cb + ps * CPP;
       if (cc < NC) {
-        lds[(2 * rp) * LDN + cc] = pre[ps][0];
-        lds[(2 * rp + 1) * LDN + cc] = pre[ps][1];
+        buf[(2 * rp) * LDN + cc] = pre[ps][0];
+        buf[(2 * rp + 1) * LDN + cc] = pre[ps][1];
       }
     }
-    __syncthreads();
-    if (rb + KC < r1) load_chunk(rb + KC);
-    const lds_f64* lp = (const lds_f64*)lds;
+  };
+  // chunk c is staged in buffer c % 2 at the end of chunk c - 1's products (every wave has
+  // passed the barrier after chunk c - 2, the buffer's previous user), and chunk c + 2's
+  // loads are issued once chunk c + 1 is staged
+  if (r0 < r1) {
+    load_chunk(r0);
+    stage(lds[0]);
+    if (r0 + KC < r1) load_chunk(r0 + KC);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int64_t rb = r0; rb < r1; rb += KC, cur ^= 1) {
+    const lds_f64* lp = (const lds_f64*)lds[cur];
     switch (slot) {
 #define TSQR_GRAM_SLOT(W_)                                                             \
   case W_:                                                                             \
@@ -488,6 +504,9 @@ __device__ __forceinline__ void gram_f64_body(int64_t m, int n, const double* __
 #undef TSQR_GRAM_SLOT
       default: break;
     }
+    if (rb + KC < r1) stage(lds[cur ^ 1]);
+    __syncthreads();
+    if (rb + 2 * KC < r1) load_chunk(rb + 2 * KC);
   }
 
   // tiles are enumerated column by column, so the first `ntiles` are those of the
