@@ -193,11 +193,12 @@ def mixed_comparison(args, kappas):
             ms_m = timed(mixed, args.mixed_steps, 2)
             o_m, r_m = gpu_metrics(A, Q, R)
             ok = o_m <= 1e-12 and row["fp64"]["ortho"] <= 1e-12 and int(info.item()) == 0
+            ph = phases_of(mixed)
             row[name] = {"ms": round(ms_m, 4), "gflops_equiv": round(F / ms_m / 1e6, 2),
-                         "fp64_passes": npass[-1], "ortho": o_m, "residual": r_m,
-                         "info": int(info.item()),
+                         "fp64_passes": npass[-1], "lowp_stage": "apply_lowp" in ph,
+                         "ortho": o_m, "residual": r_m, "info": int(info.item()),
                          "speedup_vs_fp64": round(ms / ms_m, 3) if ok else None,
-                         "phases_ms": phases_of(mixed)}
+                         "phases_ms": ph}
             del ws
         out.append(row)
         print(f"# mixed kappa={kappa:g}: fp64 {row['fp64']['ms']:.3f} ms, fp32 "

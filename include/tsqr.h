@@ -120,8 +120,12 @@ int tsqr_rxr_cholqr_ws(int variant, int64_t m, int64_t n, const double* A, int64
  *     FP64 A, W = Q1^T Q1, Rk = chol(W), Q = Q1 Rk^{-1}, R = Rk ... R01.
  * fp64_passes (arg 9): 1, 2 or 3 fixed FP64 passes, or 0 = automatic: a further pass runs
  *   while the Gram matrix of a pass's input deviates from I by more than 1/2 in Frobenius
- *   norm (or a breakdown occurred), at most 3 passes.  The automatic mode waits on the
- *   host once per pass for that decision; the fixed modes never wait.
+ *   norm (or a breakdown occurred), at most 3 passes.  The automatic mode also skips the
+ *   low-precision A1/W1/R1 stage (R01 = R0, low precision for the sketch only) unless
+ *   ||R0||_F ||R0^{-1}||_F u_p <= 1 (u_p = 2^-24 for FP32, 2^-8 for BF16): beyond that
+ *   bound on cond(R0) u_p the stage cannot save an FP64 pass.  The automatic mode waits
+ *   on the host for that decision and once per pass; the fixed modes never wait and
+ *   always run the stage.
  * passes_out (arg 16): host int receiving the number of FP64 passes run, or NULL.
  * lowp (arg 2): TSQR_LOWP_FP32 or TSQR_LOWP_BF16.  Other arguments as in
  * tsqr_rxr_cholqr_ws (shifted by one position); info stages 3 and 4 are the FP64 passes.

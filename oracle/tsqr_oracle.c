@@ -620,9 +620,20 @@ void or_trtri_upper(int64_t n, const double *T, int64_t ldt, double *X, int64_t 
  *   A1 = lowp(A R0inv);  W1 = lowp Gram of A1;  R1 = chol(W1)  (breakdown -> R01 = R0);
  *   R01 = R1 R0;  Q = A R01^{-1};  passes: W = Q^T Q, Rk = chol(W), Q = Q Rk^{-1},
  *   R = Rk ... R01.
+ * Automatic mode (fp64_passes = 0) first decides whether the low-precision stage (A1, W1,
+ * R1) is run at all: only if ||R0||_F ||R0^{-1}||_F u_p <= 1 (u_p = 2^-24 for FP32 inputs,
+ * 2^-8 for BF16), an upper bound of cond(R0) u_p, i.e. if the rounding of A to the input
+ * type perturbs A R0^{-1} by well under one.  Otherwise R01 = R0 and *lp_info = -1.
  * Returns info as or_rxr_cholqr (stages 3, 4 = first, further FP64 passes); *lp_info
- * receives the low-precision Cholesky's breakdown column (0 if none), *passes_out the
- * number of FP64 passes completed. */
+ * receives the low-precision Cholesky's breakdown column (0 if none, -1 if the stage was
+ * not run), *passes_out the number of FP64 passes completed. */
+static double or_fro(int64_t n, const double *X, int64_t ldx) {
+    double acc = 0.0;
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i) acc += X[IDX(i, j, ldx)] * X[IDX(i, j, ldx)];
+    return sqrt(acc);
+}
+
 int or_rxr_cholqr_mixed(int variant, int prec, int64_t m, int64_t n, const double *A,
                         int64_t lda, int64_t s, uint64_t seed, int fp64_passes, double *Q,
                         int64_t ldq, double *R, int64_t ldr, int *lp_info, int *passes_out) {
@@ -642,9 +653,18 @@ int or_rxr_cholqr_mixed(int variant, int prec, int64_t m, int64_t n, const doubl
     info = (variant == 1) ? or_lu_r(s, n, B, s, R0, n, NULL) : or_householder_r(s, n, B, s, R0, n);
     if (!info) {
         or_trtri_upper(n, R0, n, R0inv, n);
-        or_apply_rinv_lowp(prec, m, n, A, lda, R0inv, n, A1, m);
-        or_gram_lowp(prec, m, n, A1, m, W, n);
-        lp = or_cholesky_upper(n, W, n, R1, n);
+        int stage = 1;
+        if (fp64_passes == 0) {
+            const double up = (prec == OR_BF16) ? 0x1p-8 : 0x1p-24;
+            stage = or_fro(n, R0, n) * or_fro(n, R0inv, n) * up <= 1.0;
+        }
+        if (stage) {
+            or_apply_rinv_lowp(prec, m, n, A, lda, R0inv, n, A1, m);
+            or_gram_lowp(prec, m, n, A1, m, W, n);
+            lp = or_cholesky_upper(n, W, n, R1, n);
+        } else {
+            lp = -1;
+        }
         if (lp) memcpy(Racc, R0, nn * sizeof(double));
         else or_trmm_upper(n, R1, n, R0, n, Racc, n);
         or_trsm_ru(m, n, A, lda, Racc, n, Q, ldq);

@@ -106,9 +106,12 @@ __global__ __launch_bounds__(256) void k_trsm_prep(int n, int jt, const double* 
   trsm_prep_body(n, jt, T, ldt, P, (int)blockIdx.x);
 }
 
+// TRSM launch shape: 16 wavefronts per workgroup, each tile loaded at the start of its own
+// iteration (measured: loading the next tile one iteration ahead, with 8 wavefronts for
+// the registers it needs, is not faster)
 #ifndef TSQR_TRSM_PF
-#define TSQR_TRSM_PF 1
-#define TSQR_TRSM_THREADS 512
+#define TSQR_TRSM_PF 0
+#define TSQR_TRSM_THREADS 1024
 #endif
 // Body of workgroup `wg` of `nwg` (persistent over 16-row tiles).
 template <int JT, bool kLds>

@@ -258,6 +258,16 @@ MixedLayout make_mixed_layout(int64_t m, int64_t n, int64_t s, int lowp) {
 // automatic mode: ||W - I||_F <= 1/2 gives cond(W) <= 3, i.e. cond(Q1) <= 1.8.
 constexpr double kPassThresh = 0.5;
 
+// Automatic mode: the low-precision stage (A1 = A R0^{-1}, its Gram matrix and Cholesky)
+// runs only when ||R0||_F ||R0^{-1}||_F u_p <= 1, an upper bound of cond(R0) u_p: then the
+// rounding of A to the input type perturbs A R0^{-1} by well under one and the stage can
+// leave a single FP64 pass. Otherwise it could not save a pass, and the FP64 passes start
+// from A R0^{-1} (low precision for the sketch only).
+inline bool use_lowp_stage(int lowp, double r0_fro, double rinv_fro) {
+  const double up = lowp == TSQR_LOWP_BF16 ? 0x1p-8 : 0x1p-24;
+  return r0_fro * rinv_fro * up <= 1.0;
+}
+
 int run_chain_mixed(int variant, int lowp, int64_t m, int64_t n, const double* A, int64_t lda,
                     int64_t s, uint64_t seed, int fp64_passes, double* Q, int64_t ldq,
                     double* R, int64_t ldr, void* work, int* d_info, int* passes_out,
@@ -298,13 +308,28 @@ int run_chain_mixed(int variant, int lowp, int64_t m, int64_t n, const double* A
              launch_sketch_factor(variant, si, ni, B, s, R0, n, info, fac, st));
   TSQR_CHECK(launch_identity(ni, Id, st));
   TSQR_PHASE("trtri_r0", launch_trsm(n, ni, Id, n, R0, n, Rinv, n, Tt, st));
-  TSQR_PHASE("rinv_round", launch_rinv_prep(lowp, ni, Rinv, n, Ri_lp, st));
-  // low-precision preconditioner apply and first Gram matrix
-  TSQR_PHASE("apply_lowp", launch_apply_rinv_lowp(lowp, m, ni, A, lda, Ri_lp, A1, m, st));
-  TSQR_PHASE("gram_lowp", launch_gram_lowp(lowp, L.gp, m, ni, A1, m, part, st));
-  TSQR_PHASE("gram1_reduce", launch_gram_reduce(L.gp, ni, part, W, n, st));
-  TSQR_PHASE("potrf1", launch_potrf(ni, W, n, R1, n, 2, lp_info, fac, st));
-  // R01 = R1 R0, or R0 alone when the low-precision Cholesky broke down
+  bool stage = true;
+  if (fp64_passes == 0) {
+    // ||R0||_F into dev[1], ||R0^{-1}||_F into dev[3] (dev[0], dev[2] and need[0] are
+    // scratch here), read on the host
+    double h[4] = {0.0, 0.0, 0.0, 0.0};
+    TSQR_CHECK(launch_pass_decide(ni, R0, n, nullptr, nullptr, 0.0, need, dev, st));
+    TSQR_CHECK(launch_pass_decide(ni, Rinv, n, nullptr, nullptr, 0.0, need, dev + 2, st));
+    TSQR_CHECK(hipMemcpyAsync(h, dev, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    TSQR_CHECK(hipStreamSynchronize(st));
+    stage = use_lowp_stage(lowp, h[1], h[3]);
+  }
+  if (stage) {
+    TSQR_PHASE("rinv_round", launch_rinv_prep(lowp, ni, Rinv, n, Ri_lp, st));
+    // low-precision preconditioner apply and first Gram matrix
+    TSQR_PHASE("apply_lowp", launch_apply_rinv_lowp(lowp, m, ni, A, lda, Ri_lp, A1, m, st));
+    TSQR_PHASE("gram_lowp", launch_gram_lowp(lowp, L.gp, m, ni, A1, m, part, st));
+    TSQR_PHASE("gram1_reduce", launch_gram_reduce(L.gp, ni, part, W, n, st));
+    TSQR_PHASE("potrf1", launch_potrf(ni, W, n, R1, n, 2, lp_info, fac, st));
+  } else {
+    TSQR_CHECK(launch_set_int(lp_info, -1, st));  // stage not run: R01 = R0
+  }
+  // R01 = R1 R0, or R0 alone when the low-precision Cholesky broke down or did not run
   TSQR_PHASE("trmm", launch_trmm_or_copy(lp_info, ni, R1, n, R0, n, R01, n, st));
   // FP64 CholeskyQR passes on A R01^{-1}
   TSQR_PHASE("trsm_r01", launch_trsm(m, ni, A, lda, R01, n, Q, ldq, Tt, st));

@@ -178,13 +178,36 @@ def test_mixed_driver_pass_counts():
 def test_mixed_driver_low_precision_breakdown_falls_back():
     """Two columns equal to 1e-9 collapse after rounding to BF16: the low-precision
     Cholesky breaks down, R0 alone preconditions, and the FP64 passes still give an
-    orthonormal Q."""
-    A = gen_matrix(4096, 32, 1e4, 5)
+    orthonormal Q.  (A fixed pass count always runs the low-precision stage; the automatic
+    mode would skip it for this cond(R0).)"""
+    A = gen_matrix(4096, 32, 1e3, 3)
     A[:, 5] = A[:, 4] * (1 + 1e-9)
-    r = oracle.rxr_cholqr_mixed(F(A), 64, 7, prec=BF16, fp64_passes=0)
+    r = oracle.rxr_cholqr_mixed(F(A), 64, 7, prec=BF16, fp64_passes=3)
     assert r["lp_info"] > 0
-    assert r["info"] == 0
+    assert r["info"] == 0 and r["passes"] == 3
     assert oracle.orthogonality(r["Q"]) <= 1e-13
+
+
+@pytest.mark.parametrize("prec,kappa,runs", [(FP32, 1e4, True), (FP32, 1e10, False),
+                                             (BF16, 2.0, True), (BF16, 1e4, False)])
+def test_mixed_driver_auto_stage_rule(prec, kappa, runs):
+    """Automatic mode runs the low-precision stage iff ||R0||_F ||R0^-1||_F u_p <= 1.
+    Checked on inputs far from the threshold against LAPACK's R factor of A itself (the
+    sketch changes the singular values of R0 by a modest factor only): >= 10x below it the
+    stage runs (lp_info 0), >= 10x above it it is skipped (lp_info -1); the result is a
+    QR factorization either way."""
+    m, n, s = 2048, 16, 32
+    A = gen_matrix(m, n, kappa, 311104)
+    Rl = np.linalg.qr(A, mode="r")
+    up = 2.0 ** -24 if prec == FP32 else 2.0 ** -8
+    est = np.linalg.norm(Rl) * np.linalg.norm(np.linalg.inv(Rl)) * up
+    assert (est <= 0.1) if runs else (est >= 10.0)
+    r = oracle.rxr_cholqr_mixed(A, s, 11104, prec=prec, fp64_passes=0)
+    assert r["info"] == 0
+    assert r["lp_info"] == (0 if runs else -1)
+    assert oracle.orthogonality(r["Q"]) <= 1e-13
+    if runs:
+        assert r["passes"] == 1
 
 
 def test_mixed_driver_fixed_single_pass_fails_loudly_or_not_at_all():
