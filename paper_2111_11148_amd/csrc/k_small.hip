@@ -1062,24 +1062,26 @@ __global__ __launch_bounds__(256) void k_trmm_or_copy(const int* __restrict__ fl
 // *need = 1 when the preconditioned matrix Q1 with Gram W = Q1^T Q1 is not close enough
 // to orthonormal for one CholeskyQR pass (||W - I||_F > thresh), or when `lp_info` or
 // `info` report a breakdown.  One workgroup.
-__global__ __launch_bounds__(256) void k_pass_decide(int n, const double* __restrict__ W,
+__global__ __launch_bounds__(1024) void k_pass_decide(int n, const double* __restrict__ W,
                                                      int64_t ldw, const int* __restrict__ lp_info,
                                                      const int* __restrict__ info, double thresh,
                                                      int* __restrict__ need,
                                                      double* __restrict__ dev_out) {
-  __shared__ double red[256], red2[256];
+  __shared__ double red[1024], red2[1024];
   double acc = 0.0, acc2 = 0.0;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int i = e % n, j = e / n;
-    const double w = W[(int64_t)j * ldw + i];
-    const double d = w - (i == j ? 1.0 : 0.0);
-    acc += d * d;
-    acc2 += w * w;
-  }
+  // a column per 64-lane group (rows coalesced, no index division)
+  const int g = threadIdx.x / 64, ng = blockDim.x / 64;
+  for (int j = g; j < n; j += ng)
+    for (int i = threadIdx.x % 64; i < n; i += 64) {
+      const double w = W[(int64_t)j * ldw + i];
+      const double d = w - (i == j ? 1.0 : 0.0);
+      acc += d * d;
+      acc2 += w * w;
+    }
   red[threadIdx.x] = acc;
   red2[threadIdx.x] = acc2;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = 512; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) {
       red[threadIdx.x] += red[threadIdx.x + s];
       red2[threadIdx.x] += red2[threadIdx.x + s];
@@ -1240,7 +1242,7 @@ hipError_t launch_trmm_or_copy(const int* flag, int n, const double* A, int64_t 
 hipError_t launch_pass_decide(int n, const double* W, int64_t ldw, const int* lp_info,
                               const int* info, double thresh, int* need, double* dev_out,
                               hipStream_t st) {
-  hipLaunchKernelGGL(k_pass_decide, dim3(1), dim3(256), 0, st, n, W, ldw, lp_info, info, thresh,
+  hipLaunchKernelGGL(k_pass_decide, dim3(1), dim3(1024), 0, st, n, W, ldw, lp_info, info, thresh,
                      need, dev_out);
   return hipGetLastError();
 }

@@ -256,56 +256,71 @@ __global__ __launch_bounds__(512) void k_trsm_update(int64_t m, int nb,
   const int64_t ntiles = (m + 15) / 16;
   const int nw = blockDim.x / kWave;
   const int64_t wstride = (int64_t)gridDim.x * nw;
-  for (int64_t tile = (int64_t)blockIdx.x * nw + wave_id(); tile < ntiles; tile += wstride) {
+  // X(row, k) for k = 4kk + q, in chunks of KC K-steps; chunk c+1 is loaded while chunk c
+  // feeds the matrix cores, and the next tile's first chunk while the last one does
+  constexpr int KC = 8;
+  auto load_x = [&](int64_t t, int c, double (&xb)[KC]) {
+    const int64_t row = t * 16 + c16;
+    // per-lane base (row, column q of the chunk), then uniform strides of 4 columns
+    const double* xp = X + (int64_t)(4 * c * KC + q) * ldx + (row < m ? row : 0);
+    int64_t xs = ldx;
+    asm volatile("" : "+v"(xp), "+s"(xs));
+#pragma unroll
+    for (int j = 0; j < KC; ++j) xb[j] = xp[(4 * j) * xs];
+  };
+  int64_t tile = (int64_t)blockIdx.x * nw + wave_id();
+  double xa[KC], xn[KC];
+  if (tile < ntiles) load_x(tile, 0, xa);
+  for (; tile < ntiles; tile += wstride) {
+    const int64_t nxt = tile + wstride < ntiles ? tile + wstride : tile;  // valid address
     const int64_t row = tile * 16 + c16;
     const bool rok = row < m;
     const int64_t rowc = rok ? row : 0;  // clamped, always a valid address
-    // X(row, k) for k = 4kk + q, in chunks of KC K-steps; chunk c+1 is loaded while chunk
-    // c feeds the matrix cores
-    constexpr int KC = 8;
-    auto load_x = [&](int c, double (&xb)[KC]) {
-      // per-lane base (row, column q of the chunk), then uniform strides of 4 columns
-      const double* xp = X + (int64_t)(4 * c * KC + q) * ldx + rowc;
-      asm volatile("" : "+v"(xp));
+    // Y(row, 16b + 4r + q) for the whole tile, issued now and used at the end; a column
+    // past nb reads column 0 (valid) and is never stored
+    double yv[NB][4];
+    {
+      const double* yp = Y + (int64_t)q * ldy + rowc;
+      int64_t ys = ldy;
+      int lim = nb - q;
+      asm volatile("" : "+v"(yp), "+s"(ys), "+v"(lim));
+      const int64_t back = -(int64_t)q * ys;
 #pragma unroll
-      for (int j = 0; j < KC; ++j) {
-        const double v = xp[(int64_t)(4 * j) * ldx];
-        xb[j] = rok ? v : 0.0;
-      }
-    };
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int c0 = 16 * b + 4 * r;
+          yv[b][r] = yp[c0 < lim ? c0 * ys : back];
+        }
+    }
     v4d acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = v4d{0.0, 0.0, 0.0, 0.0};
-    double xa[KC], xn[KC];
-    load_x(0, xa);
 #pragma unroll
     for (int c = 0; c < KS / KC; ++c) {
-      if (c + 1 < KS / KC) load_x(c + 1, xn);
+      if (c + 1 < KS / KC) load_x(tile, c + 1, xn);
+      else load_x(nxt, 0, xn);
 #pragma unroll
       for (int j = 0; j < KC; ++j) {
         // opaque per-step row pointer: keeps the step's operand reads next to its MFMAs
         const lds_f64* tp = (const lds_f64*)ts + (4 * (c * KC + j) + q) * LDT + c16;
         asm volatile("" : "+v"(tp));
+        const double xv = rok ? xa[j] : 0.0;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) acc[b] = mfma_f64(tp[16 * b], xa[j], acc[b]);
+        for (int b = 0; b < NB; ++b) acc[b] = mfma_f64(tp[16 * b], xv, acc[b]);
       }
 #pragma unroll
       for (int j = 0; j < KC; ++j) xa[j] = xn[j];
     }
+    if (rok) {
+      double* cp = C + (int64_t)q * ldc + row;
+      int64_t cs = ldc;
+      asm volatile("" : "+v"(cp), "+s"(cs));
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      double yv[4];
+      for (int b = 0; b < NB; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int col = 16 * b + 4 * r + q;
-        yv[r] = Y[(int64_t)(col < nb ? col : 0) * ldy + rowc];
-      }
-      if (rok)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int col = 16 * b + 4 * r + q;
-          if (col < nb) C[(int64_t)col * ldc + row] = yv[r] - acc[b][r];
-        }
+        for (int r = 0; r < 4; ++r)
+          if (16 * b + 4 * r + q < nb) cp[(16 * b + 4 * r) * cs] = yv[b][r] - acc[b][r];
     }
   }
 }
