@@ -822,16 +822,18 @@ __global__ __launch_bounds__(kSmallThreads) void k_potrf_glb(int n, const double
 //  (c) the trailing update W22 -= R12^T R12 on FP64 MFMA (upper 16x16 tiles, round-robin
 //      over the wavefronts; operand layout as in the Gram kernel), read-modify-write in R.
 // Three barriers per panel instead of one per column.  LDS: potrf_blk_lds_doubles(n).
-template <int NB>
+// LDSM: the whole matrix is factored in LDS (ld n + 1) and copied to R at the end, so the
+// three phases never wait on global memory (for n up to 128 with NB = 16).
+template <int NB, bool LDSM = false>
 __host__ __device__ constexpr size_t potrf_blk_lds_doubles(int n) {
-  return (size_t)NB * (NB + 1) + (size_t)NB * (n + 1);
+  return (size_t)NB * (NB + 1) + (size_t)NB * (n + 1) + (LDSM ? (size_t)n * (n + 1) : 0);
 }
 
 constexpr int kTiles = 4;  // trailing tiles a wavefront updates together
 
-template <int NB>
+template <int NB, bool LDSM>
 __global__ __launch_bounds__(kSmallThreads) void k_potrf_blk(int n, const double* __restrict__ W,
-                                                             int64_t ldw, double* R, int64_t ldr,
+                                                             int64_t ldw, double* Rg, int64_t ldrg,
                                                              int stage, int* __restrict__ info,
                                                              double shift) {
   extern __shared__ double sm[];
@@ -839,6 +841,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_potrf_blk(int n, const double
   double* D = sm;                  // D[k * LDD + c] = R11(k, c)
   double* Pn = sm + NB * LDD;      // Pn[k * ldpn + c] = R12(k, c), zero-padded rows/cols
   const int ldpn = n + 1;
+  // the matrix being factored: LDS (ld n + 1) or R itself
+  double* const R = LDSM ? sm + NB * LDD + NB * ldpn : Rg;
+  const int64_t ldr = LDSM ? (int64_t)(n + 1) : ldrg;
   __shared__ int fail_sh;
   const int lane = lane_id(), wave = wave_id();
   const int q = lane >> 4, c16 = lane & 15;
@@ -965,6 +970,12 @@ __global__ __launch_bounds__(kSmallThreads) void k_potrf_blk(int n, const double
       }
     }
     __syncthreads();
+  }
+  if constexpr (LDSM) {
+    for (int e = threadIdx.x; e < n * n; e += kSmallThreads) {
+      const int c = e / n, i = e - c * n;
+      Rg[(int64_t)c * ldrg + i] = R[(int64_t)c * ldr + i];
+    }
   }
   if (threadIdx.x == 0 && info && fail_sh >= 0 && *info == 0) *info = 1000 * stage + fail_sh + 1;
 }
@@ -1186,14 +1197,22 @@ hipError_t launch_potrf(int n, const double* W, int64_t ldw, double* R, int64_t 
                        info, shift);                                                           \
     return hipGetLastError();                                                                  \
   }
-  if (n > 64 && n <= 512) {
-    hipLaunchKernelGGL(k_potrf_blk<32>, grid, block, potrf_blk_lds_doubles<32>(n) * sizeof(double),
-                       st, n, W, ldw, R, ldr, stage, info, shift);
+  if (n > 64 && n <= 128) {  // the whole matrix in LDS
+    hipLaunchKernelGGL((k_potrf_blk<16, true>), grid, block,
+                       (potrf_blk_lds_doubles<16, true>(n)) * sizeof(double), st, n, W, ldw, R, ldr,
+                       stage, info, shift);
+    return hipGetLastError();
+  }
+  if (n > 128 && n <= 512) {
+    hipLaunchKernelGGL((k_potrf_blk<32, false>), grid, block,
+                       potrf_blk_lds_doubles<32>(n) * sizeof(double), st, n, W, ldw, R, ldr, stage,
+                       info, shift);
     return hipGetLastError();
   }
   if (n > 512 && n <= 1024) {  // narrower panels keep the panel row in LDS
-    hipLaunchKernelGGL(k_potrf_blk<16>, grid, block, potrf_blk_lds_doubles<16>(n) * sizeof(double),
-                       st, n, W, ldw, R, ldr, stage, info, shift);
+    hipLaunchKernelGGL((k_potrf_blk<16, false>), grid, block,
+                       potrf_blk_lds_doubles<16>(n) * sizeof(double), st, n, W, ldw, R, ldr, stage,
+                       info, shift);
     return hipGetLastError();
   }
   TSQR_POTRF(1, 1) TSQR_POTRF(1, 2) TSQR_POTRF(1, 4) TSQR_POTRF(2, 8)

@@ -186,12 +186,13 @@ def test_potrf_breakdown_and_upper_only():
     assert np.array_equal(Rh[:3, :3], np.eye(3))
 
 
-def test_potrf_breakdown_blocked_panel():
-    """Breakdown inside the second 32-column panel of the blocked factorization."""
-    n = 200
+@pytest.mark.parametrize("n", [100, 200])
+def test_potrf_breakdown_blocked_panel(n):
+    """Breakdown inside a later panel of the blocked factorization (n = 100: the variant
+    factored in LDS, 16-column panels; n = 200: 32-column panels in place)."""
     W = np.eye(n)
     W[40, 40] = -1.0
-    W[150, 3] = 77.0  # lower garbage is ignored
+    W[n - 50, 3] = 77.0  # lower garbage is ignored
     R, info = tsqr.potrf(dev(np.asfortranarray(W)), stage=3)
     assert int(info.item()) == 3041
     Rh = host(R)
