@@ -50,6 +50,12 @@ def _load():
         "or_rxr_cholqr": (_c_int, [_c_int, _c_i64, _c_i64, _c_dp, _c_i64, _c_i64, _c_u64,
                                    _c_int, _c_dp, _c_i64, _c_dp, _c_i64, _c_dp, _c_dp,
                                    _c_dp]),
+        "or_rxr_cholqr_rows": (_c_int, [_c_int, _c_i64, _c_i64, _c_dp, _c_i64, _c_i64,
+                                        _c_u64, _c_int, _c_dp, _c_i64, _c_dp, _c_i64, _c_dp,
+                                        _c_dp, _c_dp]),
+        "or_sample_rows": (None, [_c_i64, _c_i64, _c_u64, ctypes.POINTER(ctypes.c_int64)]),
+        "or_sketch_rows": (None, [_c_i64, _c_i64, _c_dp, _c_i64, _c_i64, _c_u64, _c_dp,
+                                  _c_i64]),
         "or_cholqr_n": (_c_int, [_c_i64, _c_i64, _c_dp, _c_i64, _c_int, ctypes.c_double,
                                  _c_dp, _c_i64, _c_dp, _c_i64]),
         "or_orthogonality": (ctypes.c_double, [_c_i64, _c_i64, _c_dp, _c_i64]),
@@ -179,8 +185,10 @@ RQR = 0
 RLU = 1
 
 
-def rxr_cholqr(A: np.ndarray, s: int, seed: int, variant: int = RQR, extra_pass: bool = True):
-    """Randomized XR-preconditioned CholeskyQR.  Returns dict(Q, R, R0, R1, R2, info)."""
+def rxr_cholqr(A: np.ndarray, s: int, seed: int, variant: int = RQR, extra_pass: bool = True,
+               sketch: str = "gaussian"):
+    """Randomized XR-preconditioned CholeskyQR with the Gaussian (default) or the
+    row-extraction sketch.  Returns dict(Q, R, R0, R1, R2, info)."""
     A = _f64(A, "A")
     m, n = A.shape
     Q = np.zeros((m, n), dtype=np.float64, order="F")
@@ -188,14 +196,33 @@ def rxr_cholqr(A: np.ndarray, s: int, seed: int, variant: int = RQR, extra_pass:
     R0 = np.zeros((n, n), dtype=np.float64, order="F")
     R1 = np.zeros((n, n), dtype=np.float64, order="F")
     R2 = np.zeros((n, n), dtype=np.float64, order="F")
-    info = _load().or_rxr_cholqr(variant, m, n, _ptr(A), _ld(A), s, seed, int(extra_pass),
-                                 _ptr(Q), max(1, m), _ptr(R), max(1, n), _ptr(R0), _ptr(R1),
-                                 _ptr(R2))
+    if sketch not in ("gaussian", "rows"):
+        raise ValueError(f"unknown sketch {sketch!r}")
+    fn = _load().or_rxr_cholqr if sketch == "gaussian" else _load().or_rxr_cholqr_rows
+    info = fn(variant, m, n, _ptr(A), _ld(A), s, seed, int(extra_pass), _ptr(Q), max(1, m),
+              _ptr(R), max(1, n), _ptr(R0), _ptr(R1), _ptr(R2))
     return {"Q": Q, "R": R, "R0": R0, "R1": R1, "R2": R2, "info": info}
 
 
+def sample_rows(m: int, s: int, seed: int) -> np.ndarray:
+    """Row indices r_0..r_{s-1} of the row-extraction sketch (int64)."""
+    rows = np.zeros(s, dtype=np.int64)
+    _load().or_sample_rows(m, s, seed, rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return rows
+
+
+def sketch_rows(A: np.ndarray, s: int, seed: int) -> np.ndarray:
+    """B = A(rows, :) of the row-extraction sketch."""
+    A = _f64(A, "A")
+    m, n = A.shape
+    B = np.zeros((s, n), dtype=np.float64, order="F")
+    _load().or_sketch_rows(m, n, _ptr(A), _ld(A), s, seed, _ptr(B), max(1, s))
+    return B
+
+
 def cholqr_n(A: np.ndarray, npass: int, shift: float = 0.0):
-    """CholeskyQR (npass=1), CholeskyQR2 (npass=2), shifted CholeskyQR3 (npass=3, shift>0)."""
+    """CholeskyQR (npass=1), CholeskyQR2 (npass=2), shifted CholeskyQR3 (npass=3, shift != 0;
+    shift < 0 = the paper's suggested 11(mn + n(n+1)) u ||A||_2^2, bounded by ||A^T A||_F)."""
     A = _f64(A, "A")
     m, n = A.shape
     Q = np.zeros((m, n), dtype=np.float64, order="F")

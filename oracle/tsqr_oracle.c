@@ -36,6 +36,8 @@
 
 #define IDX(i, j, ld) ((size_t)(i) + (size_t)(j) * (size_t)(ld))
 
+static double or_fro(int64_t n, const double *X, int64_t ldx);
+
 /* ------------------------------------------------------------------------------------
  * Counter-based generator: Philox-4xW-10 (Salmon, Moraes, Dror, Shaw, "Parallel random
  * numbers: as easy as 1, 2, 3", SC'11).  One round maps the counter (c0,c1,c2,c3) with
@@ -138,6 +140,37 @@ void or_sketch_apply(int64_t m, int64_t n, const double *A, int64_t lda, int64_t
         }
         free(srow);
     }
+}
+
+/* ------------------------------------------------------------------------------------
+ * The row-extraction sketch (paper Section 2.3, "Row Extraction", the sketch of its
+ * experiments), with the sampling of Theorem "Equal Probability Case": s rows drawn
+ * independently, each uniformly from the m rows, so a row may repeat.  B(i, :) = A(r_i, :)
+ * (P selects rows, no scaling).
+ *
+ * Stream layout (a reading; the paper does not fix a generator): key as for the Gaussian
+ * sketch; for draw i, one Philox4x32-10 call with counter = (low 32 bits of i, high 32
+ * bits of i, 0, 1) (the last word is 0 for every Gaussian-sketch counter, so the streams
+ * never meet); w = w0 + 2^32 w1 and r_i = floor(w m / 2^64), exact 128-bit arithmetic.
+ * ------------------------------------------------------------------------------------ */
+void or_sample_rows(int64_t m, int64_t s, uint64_t seed, int64_t *rows) {
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int64_t i = 0; i < s; ++i) {
+        uint32_t ctr[4] = {(uint32_t)i, (uint32_t)((uint64_t)i >> 32), 0u, 1u};
+        uint32_t w[4];
+        or_philox4x32_10(ctr, key, w);
+        uint64_t w64 = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+        rows[i] = (int64_t)(((unsigned __int128)w64 * (unsigned __int128)(uint64_t)m) >> 64);
+    }
+}
+
+void or_sketch_rows(int64_t m, int64_t n, const double *A, int64_t lda, int64_t s,
+                    uint64_t seed, double *B, int64_t ldb) {
+    int64_t *rows = (int64_t *)malloc((size_t)s * sizeof(int64_t));
+    or_sample_rows(m, s, seed, rows);
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < s; ++i) B[IDX(i, j, ldb)] = A[IDX(rows[i], j, lda)];
+    free(rows);
 }
 
 /* ------------------------------------------------------------------------------------
@@ -357,9 +390,10 @@ static int cholqr_pass(int64_t m, int64_t n, const double *X, int64_t ldx, doubl
  *   extra pass: R2 = chol(Q1^T Q1), Q = Q1 R2^{-1}, R = R2 (R1 R0);  else Q = Q1, R = R1 R0
  * Q is m x n (ld ldq), R is n x n upper (ld ldr).  R0, R1, R2 (n x n, ld n) are written
  * when the pointers are non-NULL (R2 only with the extra pass). */
-int or_rxr_cholqr(int variant, int64_t m, int64_t n, const double *A, int64_t lda,
-                  int64_t s, uint64_t seed, int extra_pass, double *Q, int64_t ldq,
-                  double *R, int64_t ldr, double *R0o, double *R1o, double *R2o) {
+static int rxr_cholqr_k(int sketch, int variant, int64_t m, int64_t n, const double *A,
+                        int64_t lda, int64_t s, uint64_t seed, int extra_pass, double *Q,
+                        int64_t ldq, double *R, int64_t ldr, double *R0o, double *R1o,
+                        double *R2o) {
     size_t nn = (size_t)n * (size_t)n;
     double *B = (double *)malloc((size_t)s * (size_t)n * sizeof(double));
     double *R0 = (double *)calloc(nn, sizeof(double));
@@ -368,7 +402,8 @@ int or_rxr_cholqr(int variant, int64_t m, int64_t n, const double *A, int64_t ld
     double *R10 = (double *)calloc(nn, sizeof(double));
     int info = 0;
 
-    or_sketch_apply(m, n, A, lda, s, seed, B, s);
+    if (sketch == 1) or_sketch_rows(m, n, A, lda, s, seed, B, s);
+    else or_sketch_apply(m, n, A, lda, s, seed, B, s);
     info = (variant == 1) ? or_lu_r(s, n, B, s, R0, n, NULL) : or_householder_r(s, n, B, s, R0, n);
     if (!info) {
         or_trsm_ru(m, n, A, lda, R0, n, Q, ldq); /* Q holds A1 */
@@ -397,9 +432,26 @@ int or_rxr_cholqr(int variant, int64_t m, int64_t n, const double *A, int64_t ld
     return info;
 }
 
+int or_rxr_cholqr(int variant, int64_t m, int64_t n, const double *A, int64_t lda,
+                  int64_t s, uint64_t seed, int extra_pass, double *Q, int64_t ldq,
+                  double *R, int64_t ldr, double *R0o, double *R1o, double *R2o) {
+    return rxr_cholqr_k(0, variant, m, n, A, lda, s, seed, extra_pass, Q, ldq, R, ldr, R0o,
+                        R1o, R2o);
+}
+
+/* The same method with the row-extraction sketch in place of the Gaussian one. */
+int or_rxr_cholqr_rows(int variant, int64_t m, int64_t n, const double *A, int64_t lda,
+                       int64_t s, uint64_t seed, int extra_pass, double *Q, int64_t ldq,
+                       double *R, int64_t ldr, double *R0o, double *R1o, double *R2o) {
+    return rxr_cholqr_k(1, variant, m, n, A, lda, s, seed, extra_pass, Q, ldq, R, ldr, R0o,
+                        R1o, R2o);
+}
+
 /* CholeskyQR (npass = 1), CholeskyQR2 (npass = 2) and plain repeated passes, with an
- * optional diagonal shift on the first Gram matrix (paper Algorithm sCholeskyQR3 uses
- * shift > 0 with npass = 3).  R = R_npass ... R_1.  Returns 0 or 1000*(pass+1) + k. */
+ * optional diagonal shift on the first Gram matrix G (paper Algorithm sCholeskyQR3 uses a
+ * shift with npass = 3): shift > 0 is added as given; shift < 0 adds the paper's suggested
+ * 11 (m n + n (n + 1)) u ||A||_2^2 (Section 2.1) with ||A||_2^2 bounded above by ||G||_F
+ * and u = 2^-53.  R = R_npass ... R_1.  Returns 0 or 1000*(pass+1) + k. */
 int or_cholqr_n(int64_t m, int64_t n, const double *A, int64_t lda, int npass,
                 double shift, double *Q, int64_t ldq, double *R, int64_t ldr) {
     size_t nn = (size_t)n * (size_t)n;
@@ -413,8 +465,13 @@ int or_cholqr_n(int64_t m, int64_t n, const double *A, int64_t lda, int npass,
     for (int64_t k = 0; k < n; ++k) Racc[IDX(k, k, n)] = 1.0;
     for (int pass = 0; pass < npass && !info; ++pass) {
         or_gram(m, n, Q, ldq, W, n);
-        if (pass == 0 && shift != 0.0)
-            for (int64_t k = 0; k < n; ++k) W[IDX(k, k, n)] += shift;
+        if (pass == 0 && shift != 0.0) {
+            double sh = shift;
+            if (shift < 0.0)
+                sh = 11.0 * ((double)m * (double)n + (double)n * (double)(n + 1)) * 0x1p-53 *
+                     or_fro(n, W, n);
+            for (int64_t k = 0; k < n; ++k) W[IDX(k, k, n)] += sh;
+        }
         int c = or_cholesky_upper(n, W, n, Rk, n);
         if (c) { info = 1000 * (pass + 1) + c; break; }
         or_trsm_ru(m, n, Q, ldq, Rk, n, Q, ldq);
