@@ -101,6 +101,44 @@ int tsqr_rxr_cholqr_ws(int variant, int64_t m, int64_t n, const double* A, int64
                        int64_t ldq, double* R, int64_t ldr, void* work, size_t work_bytes,
                        int* d_info, void* stream);
 
+/* Row-extraction sketch (paper Section 2.3, "Row Extraction", the sketch of the paper's
+ * experiments): rQR/rLU-CholeskyQR with B = P A, P selecting s rows drawn independently,
+ * each uniformly from the m rows (the sampling of Theorem "Equal Probability Case"; a row
+ * may repeat).  Draw i: Philox4x32-10 with key (seed lo, seed hi) and counter (i lo, i hi,
+ * 0, 1); with w = word0 + 2^32 word1, row r_i = floor(w m / 2^64).  Arguments, codes,
+ * workspace (tsqr_workspace_bytes) and info as tsqr_rxr_cholqr_ws.  An A whose mass
+ * sits in few rows (the paper's [I; 0] example) can give a rank-deficient sample: a
+ * breakdown of the small factorization, info = 1000 + k. */
+int tsqr_rxr_cholqr_rows_ws(int variant, int64_t m, int64_t n, const double* A, int64_t lda,
+                            int64_t sketch_rows, uint64_t seed, int extra_pass, double* Q,
+                            int64_t ldq, double* R, int64_t ldr, void* work, size_t work_bytes,
+                            int* d_info, void* stream);
+
+/* ------------------------------------------------------------------------------------
+ * CholeskyQR family (paper Section 2.1: Algorithms CholeskyQR, CholeskyQR2 and
+ * sCholeskyQR3), the baselines the paper compares against, on the same kernels.
+ * ------------------------------------------------------------------------------------ */
+#define TSQR_ALGO_CHOLQR 1   /* one pass: W = A^T A, R = chol(W), Q = A R^{-1} */
+#define TSQR_ALGO_CHOLQR2 2  /* two passes, R = R2 R1 */
+#define TSQR_ALGO_SCHOLQR3 3 /* first Cholesky of W + shift I, then two passes, R = R3 R2 R1 */
+
+/* Bytes of workspace for tsqr_cholqr_ws (0 if the sizes are invalid). */
+size_t tsqr_cholqr_workspace_bytes(int64_t m, int64_t n);
+
+/*   algo (1): TSQR_ALGO_*;
+ *   m, n, A, lda (2-5): as tsqr_rxr_cholqr_ws;
+ *   shift (6): sCholeskyQR3 only: >= 0 is added to the first Gram matrix's diagonal as
+ *     given (the paper's experiments use 1e-15 for ||A||_2 = 1); < 0 adds the suggested
+ *     11 (m n + n (n + 1)) u ||A||_2^2, u = 2^-53, with ||A||_2^2 bounded above by
+ *     ||A^T A||_F (computed on the device, no host wait); NaN is an argument error;
+ *   Q, ldq (7, 8), R, ldr (9, 10): outputs as tsqr_rxr_cholqr_ws;
+ *   work, work_bytes (11, 12): at least tsqr_cholqr_workspace_bytes(m, n) bytes;
+ *   d_info (13): device int, 1000 * pass + k when pass `pass`'s Cholesky breaks down at
+ *     column k (Q and R then NaN), or NULL;  stream (14). */
+int tsqr_cholqr_ws(int algo, int64_t m, int64_t n, const double* A, int64_t lda, double shift,
+                   double* Q, int64_t ldq, double* R, int64_t ldr, void* work, size_t work_bytes,
+                   int* d_info, void* stream);
+
 /* ------------------------------------------------------------------------------------
  * Mixed precision
  * ------------------------------------------------------------------------------------ */
@@ -224,6 +262,13 @@ void tsqr_batched_destroy(tsqr_batch* plan);
 /* ------------------------------------------------------------------------------------
  * Steps of the method, one entry point per step (used for step-wise validation)
  * ------------------------------------------------------------------------------------ */
+
+/* Row-extraction sketch (paper Section 2.3): B(i, :) = A(r_i, :) with the draws of
+ * tsqr_rxr_cholqr_rows_ws; B is s x n (ldb >= s), an exact copy (no arithmetic).
+ * Codes: -1 m < 1, -2 n < 1, -3 A NULL, -4 lda < m, -5 s outside [1, 8192], -7 B NULL,
+ * -8 ldb < s. */
+int tsqr_sketch_rows(int64_t m, int64_t n, const double* A, int64_t lda, int64_t s,
+                     uint64_t seed, double* B, int64_t ldb, void* stream);
 
 /* Sketch (paper Section 2.3, Gaussian ensemble): B = S A, B is s x n (ldb >= s).  The
  * sum over the m rows is split into row blocks whose partial sums are added in a fixed

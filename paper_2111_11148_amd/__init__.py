@@ -35,6 +35,12 @@ _SIGS = {
     "tsqr_workspace_bytes": (_sz, [_i64, _i64, _i64]),
     "tsqr_rxr_cholqr_ws": (_int, [_int, _i64, _i64, _vp, _i64, _i64, _u64, _int, _vp, _i64, _vp,
                                   _i64, _vp, _sz, _vp, _vp]),
+    "tsqr_rxr_cholqr_rows_ws": (_int, [_int, _i64, _i64, _vp, _i64, _i64, _u64, _int, _vp, _i64,
+                                       _vp, _i64, _vp, _sz, _vp, _vp]),
+    "tsqr_sketch_rows": (_int, [_i64, _i64, _vp, _i64, _i64, _u64, _vp, _i64, _vp]),
+    "tsqr_cholqr_workspace_bytes": (_sz, [_i64, _i64]),
+    "tsqr_cholqr_ws": (_int, [_int, _i64, _i64, _vp, _i64, ctypes.c_double, _vp, _i64, _vp,
+                              _i64, _vp, _sz, _vp, _vp]),
     "tsqr_sketch_workspace_bytes": (_sz, [_i64, _i64, _i64]),
     "tsqr_sketch": (_int, [_i64, _i64, _vp, _i64, _i64, _u64, _vp, _i64, _vp, _sz, _vp]),
     "tsqr_sketch_factor_workspace_bytes": (_sz, [_i64, _i64]),
@@ -182,10 +188,13 @@ def rxr_cholqr(A: torch.Tensor, sketch_rows: int, seed: int, variant: int = RQR,
                extra_pass: bool = True, Q: torch.Tensor | None = None,
                R: torch.Tensor | None = None, want_r: bool = True,
                workspace: torch.Tensor | None = None, info: torch.Tensor | None = None,
-               stream=None):
-    """Randomized XR-preconditioned CholeskyQR (explicit-workspace entry point).
+               stream=None, sketch: str = "gaussian"):
+    """Randomized XR-preconditioned CholeskyQR (explicit-workspace entry point), with the
+    Gaussian sketch (default) or the row-extraction sketch (``sketch="rows"``).
 
     Returns (Q, R, info) with info a 1-element int32 device tensor (0 = success)."""
+    if sketch not in ("gaussian", "rows"):
+        raise ValueError(f"unknown sketch {sketch!r}")
     lda = _mat(A, "A")
     m, n = A.shape
     if Q is None:
@@ -198,12 +207,49 @@ def rxr_cholqr(A: torch.Tensor, sketch_rows: int, seed: int, variant: int = RQR,
         workspace = alloc_workspace(m, n, sketch_rows, device=A.device)
     if info is None:
         info = torch.zeros(1, dtype=torch.int32, device=A.device)
-    rc = load().tsqr_rxr_cholqr_ws(variant, m, n, A.data_ptr(), lda, sketch_rows, seed,
-                                   int(bool(extra_pass)), Q.data_ptr(), ldq,
-                                   R.data_ptr() if R is not None else None, ldr,
-                                   workspace.data_ptr(), workspace.numel(), info.data_ptr(),
-                                   _stream(stream))
-    _check(rc, "tsqr_rxr_cholqr_ws")
+    name = "tsqr_rxr_cholqr_ws" if sketch == "gaussian" else "tsqr_rxr_cholqr_rows_ws"
+    rc = getattr(load(), name)(variant, m, n, A.data_ptr(), lda, sketch_rows, seed,
+                               int(bool(extra_pass)), Q.data_ptr(), ldq,
+                               R.data_ptr() if R is not None else None, ldr,
+                               workspace.data_ptr(), workspace.numel(), info.data_ptr(),
+                               _stream(stream))
+    _check(rc, name)
+    return Q, R, info
+
+
+CHOLQR = 1
+CHOLQR2 = 2
+SCHOLQR3 = 3
+
+
+def cholqr_workspace_bytes(m: int, n: int) -> int:
+    return int(load().tsqr_cholqr_workspace_bytes(m, n))
+
+
+def cholqr(A: torch.Tensor, algo: int = CHOLQR2, shift: float = -1.0,
+           Q: torch.Tensor | None = None, R: torch.Tensor | None = None, want_r: bool = True,
+           workspace: torch.Tensor | None = None, info: torch.Tensor | None = None,
+           stream=None):
+    """CholeskyQR (algo=CHOLQR), CholeskyQR2 or shifted CholeskyQR3 (shift < 0: the
+    suggested 11(mn + n(n+1)) u ||A||_2^2 bound; >= 0: that shift).  Returns (Q, R, info)."""
+    lda = _mat(A, "A")
+    m, n = A.shape
+    if Q is None:
+        Q = colmajor(m, n, device=A.device)
+    ldq = _mat(Q, "Q", m, n)
+    if R is None and want_r:
+        R = colmajor(n, n, device=A.device)
+    ldr = _mat(R, "R", n, n) if R is not None else n
+    if workspace is None:
+        workspace = torch.empty(max(1, cholqr_workspace_bytes(m, n)), dtype=torch.uint8,
+                                device=A.device)
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    rc = load().tsqr_cholqr_ws(algo, m, n, A.data_ptr(), lda, float(shift), Q.data_ptr(), ldq,
+                               R.data_ptr() if R is not None else None, ldr,
+                               workspace.data_ptr(), workspace.numel(), info.data_ptr(),
+                               _stream(stream))
+    _check(rc, "tsqr_cholqr_ws")
     return Q, R, info
 
 
@@ -320,6 +366,16 @@ def sketch(A: torch.Tensor, s: int, seed: int, stream=None) -> torch.Tensor:
     work = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=A.device)
     _check(load().tsqr_sketch(m, n, A.data_ptr(), lda, s, seed, B.data_ptr(), s,
                               work.data_ptr(), nbytes, _stream(stream)), "tsqr_sketch")
+    return B
+
+
+def sketch_rows(A: torch.Tensor, s: int, seed: int, stream=None) -> torch.Tensor:
+    """B = A(rows, :), the row-extraction sketch (s x n)."""
+    lda = _mat(A, "A")
+    m, n = A.shape
+    B = colmajor(s, n, device=A.device)
+    _check(load().tsqr_sketch_rows(m, n, A.data_ptr(), lda, s, seed, B.data_ptr(), s,
+                                   _stream(stream)), "tsqr_sketch_rows")
     return B
 
 

@@ -254,6 +254,30 @@ hipError_t launch_sketch(const SketchPlan& p, int64_t m, int n, const double* A,
   return hipErrorInvalidValue;
 }
 
+// Row-extraction sketch (the sketch of the paper's experiments, Section 2.3), sampled as in
+// Theorem "Equal Probability Case": draw i picks row r_i = floor(w m / 2^64) for the 64-bit
+// word w = x + 2^32 y of Philox4x32-10 with counter (i lo, i hi, 0, 1) (the last counter
+// word is 0 in every Gaussian-sketch call, so the two streams never meet), independently
+// of the other draws; B(i, :) = A(r_i, :).  One workgroup per draw, columns over threads.
+__global__ __launch_bounds__(256) void k_sketch_rows(int64_t m, int n,
+                                                     const double* __restrict__ A, int64_t lda,
+                                                     uint32_t k0, uint32_t k1,
+                                                     double* __restrict__ B, int64_t ldb) {
+  const uint64_t i = blockIdx.x;
+  const U32x4 w = philox4x32_10(U32x4{(uint32_t)i, (uint32_t)(i >> 32), 0u, 1u}, k0, k1);
+  const uint64_t w64 = (uint64_t)w.x | ((uint64_t)w.y << 32);
+  const int64_t r = (int64_t)__umul64hi(w64, (uint64_t)m);  // in [0, m)
+  for (int j = threadIdx.x; j < n; j += blockDim.x)
+    B[(int64_t)j * ldb + (int64_t)i] = A[(int64_t)j * lda + r];
+}
+
+hipError_t launch_sketch_rows(int64_t m, int n, const double* A, int64_t lda, int s,
+                              uint64_t seed, double* B, int64_t ldb, hipStream_t st) {
+  hipLaunchKernelGGL(k_sketch_rows, dim3(s), dim3(256), 0, st, m, n, A, lda, (uint32_t)seed,
+                     (uint32_t)(seed >> 32), B, ldb);
+  return hipGetLastError();
+}
+
 hipError_t launch_sketch_reduce(const SketchPlan& p, int s, int n, const double* part,
                                 double scale, double* B, int64_t ldb, hipStream_t st) {
   const size_t E = (size_t)p.it_total * p.jt_total * 256;

@@ -1258,6 +1258,21 @@ hipError_t launch_trmm_or_copy(const int* flag, int n, const double* A, int64_t 
   return hipGetLastError();
 }
 
+// W(k, k) += coef * (*scale) (or coef when scale is null): the diagonal shift of the first
+// Gram matrix in shifted CholeskyQR, with the scale read on the device (no host wait).
+__global__ __launch_bounds__(256) void k_add_diag(int n, double* __restrict__ W, int64_t ldw,
+                                                  double coef, const double* __restrict__ scale) {
+  const double sh = scale ? coef * *scale : coef;
+  for (int k = threadIdx.x + blockIdx.x * blockDim.x; k < n; k += blockDim.x * gridDim.x)
+    W[(int64_t)k * ldw + k] += sh;
+}
+
+hipError_t launch_add_diag(int n, double* W, int64_t ldw, double coef, const double* scale,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_add_diag, dim3((n + 255) / 256), dim3(256), 0, st, n, W, ldw, coef, scale);
+  return hipGetLastError();
+}
+
 hipError_t launch_pass_decide(int n, const double* W, int64_t ldw, const int* lp_info,
                               const int* info, double thresh, int* need, double* dev_out,
                               hipStream_t st) {

@@ -130,9 +130,10 @@ void prof_push(const char* name, hipEvent_t a, hipEvent_t b) {
     if (err_ != hipSuccess) return TSQR_ERR_HIP;                             \
   } while (0)
 
+// sketch_kind 0: Gaussian B = S A; 1: row extraction B = A(rows, :).
 int run_chain(int variant, int64_t m, int64_t n, const double* A, int64_t lda, int64_t s,
               uint64_t seed, int extra_pass, double* Q, int64_t ldq, double* R, int64_t ldr,
-              void* work, int* d_info, hipStream_t st) {
+              void* work, int* d_info, hipStream_t st, int sketch_kind = 0) {
   const Layout L = make_layout(m, n, s);
   char* base = (char*)work;
   int* info = d_info ? d_info : (int*)(base + L.info);
@@ -148,10 +149,15 @@ int run_chain(int variant, int64_t m, int64_t n, const double* A, int64_t lda, i
   const int ni = (int)n, si = (int)s;
 
   TSQR_CHECK(launch_set_int(info, 0, st));
-  // B = S A  (paper Section 2.3)
-  TSQR_PHASE("sketch", launch_sketch(L.sp, m, ni, A, lda, si, seed, part, st));
-  TSQR_PHASE("sketch_reduce",
-             launch_sketch_reduce(L.sp, si, ni, part, 1.0 / sqrt((double)s), B, s, st));
+  if (sketch_kind == 1) {
+    // B = P A, s sampled rows  (paper Section 2.3, row extraction)
+    TSQR_PHASE("sketch_rows", launch_sketch_rows(m, ni, A, lda, si, seed, B, s, st));
+  } else {
+    // B = S A  (paper Section 2.3, Gaussian ensemble)
+    TSQR_PHASE("sketch", launch_sketch(L.sp, m, ni, A, lda, si, seed, part, st));
+    TSQR_PHASE("sketch_reduce",
+               launch_sketch_reduce(L.sp, si, ni, part, 1.0 / sqrt((double)s), B, s, st));
+  }
   // R0 = R factor of B
   TSQR_PHASE(variant == 1 ? "sketch_lu" : "sketch_qr",
              launch_sketch_factor(variant, si, ni, B, s, R0, n, info, fac, st));
@@ -224,6 +230,79 @@ int plain_form(int variant, int64_t m, int64_t n, const double* A, int64_t lda, 
   const int rc = run_chain(variant, m, n, A, lda, s, seed, 1, Q, m, R, n, work, nullptr, st);
   if (hipFreeAsync(work, st) != hipSuccess && rc == TSQR_OK) return TSQR_ERR_HIP;
   return rc;
+}
+
+// ---- CholeskyQR, CholeskyQR2, shifted CholeskyQR3 (paper Section 2.1) -----------------
+struct CholLayout {
+  size_t info, W, Rk, Racc, Rt, fac, Tt, part, dev, need, total;
+  GramPlan gp;
+};
+
+CholLayout make_chol_layout(int64_t m, int64_t n) {
+  CholLayout L{};
+  L.gp = plan_gram(m, (int)n);
+  const size_t nn = align256((size_t)n * n * sizeof(double));
+  size_t off = 0;
+  L.info = off; off += 256;
+  L.W = off; off += nn;
+  L.Rk = off; off += nn;
+  L.Racc = off; off += nn;
+  L.Rt = off; off += nn;
+  L.fac = off; off += nn;
+  L.Tt = off; off += align256(trsm_scratch_doubles((int)n) * sizeof(double));
+  L.part = off; off += align256(L.gp.part_doubles * sizeof(double));
+  L.dev = off; off += 256;
+  L.need = off; off += 256;
+  L.total = off;
+  return L;
+}
+
+// Passes k = 1..npass: W = X^T X (X = A, then Q), on the first pass plus the shift when
+// shifted, Rk = chol(W) (stage k), Q = X Rk^{-1}, R = Rk ... R1.  Shift: >= 0 absolute,
+// < 0 the suggested 11 (m n + n (n+1)) u ||A||_2^2 with ||A||_2^2 <= ||A^T A||_F taken on
+// the device.
+int run_cholqr(int npass, bool shifted, int64_t m, int64_t n, const double* A, int64_t lda,
+               double shift, double* Q, int64_t ldq, double* R, int64_t ldr, void* work,
+               int* d_info, hipStream_t st) {
+  const CholLayout L = make_chol_layout(m, n);
+  char* base = (char*)work;
+  int* info = d_info ? d_info : (int*)(base + L.info);
+  double* W = (double*)(base + L.W);
+  double* Rk = (double*)(base + L.Rk);
+  double* Racc = (double*)(base + L.Racc);
+  double* Rt = (double*)(base + L.Rt);
+  double* fac = (double*)(base + L.fac);
+  double* Tt = (double*)(base + L.Tt);
+  double* part = (double*)(base + L.part);
+  double* dev = (double*)(base + L.dev);
+  int* need = (int*)(base + L.need);
+  const int ni = (int)n;
+  TSQR_CHECK(launch_set_int(info, 0, st));
+  for (int pass = 0; pass < npass; ++pass) {
+    const double* X = pass == 0 ? A : Q;
+    const int64_t ldxx = pass == 0 ? lda : ldq;
+    TSQR_PHASE("gram", launch_gram(L.gp, m, ni, X, ldxx, part, st));
+    TSQR_PHASE("gram_reduce", launch_gram_reduce(L.gp, ni, part, W, n, st));
+    if (pass == 0 && shifted) {
+      if (shift < 0.0) {
+        const double c = 11.0 * ((double)m * (double)n + (double)n * (double)(n + 1)) * 0x1p-53;
+        TSQR_CHECK(launch_pass_decide(ni, W, n, nullptr, nullptr, 0.0, need, dev, st));
+        TSQR_PHASE("shift", launch_add_diag(ni, W, n, c, dev + 1, st));  // dev[1] = ||W||_F
+      } else {
+        TSQR_PHASE("shift", launch_add_diag(ni, W, n, shift, nullptr, st));
+      }
+    }
+    TSQR_PHASE("potrf", launch_potrf(ni, W, n, pass == 0 ? Racc : Rk, n, pass + 1, info, fac, st));
+    TSQR_PHASE("trsm", launch_trsm(m, ni, X, ldxx, pass == 0 ? Racc : Rk, n, Q, ldq, Tt, st));
+    if (pass > 0) {
+      TSQR_PHASE("trmm", launch_trmm_upper(ni, Rk, n, Racc, n, Rt, n, st));
+      std::swap(Racc, Rt);
+    }
+  }
+  if (R) TSQR_CHECK(hipMemcpy2DAsync(R, ldr * sizeof(double), Racc, n * sizeof(double),
+                                     n * sizeof(double), n, hipMemcpyDeviceToDevice, st));
+  TSQR_PHASE("poison", launch_poison(info, m, ni, Q, ldq, R, ldr, st));
+  return TSQR_OK;
 }
 
 // ---- mixed precision ---------------------------------------------------------------
@@ -465,6 +544,78 @@ int tsqr_rxr_cholqr_ws(int variant, int64_t m, int64_t n, const double* A, int64
   if (work_bytes < make_layout(m, n, sketch_rows).total) return TSQR_ERR_WORKSPACE;
   return run_chain(variant, m, n, A, lda, sketch_rows, seed, extra_pass != 0, Q, ldq, R, ldr, work,
                    d_info, (hipStream_t)stream);
+}
+
+int tsqr_rxr_cholqr_rows_ws(int variant, int64_t m, int64_t n, const double* A, int64_t lda,
+                            int64_t sketch_rows, uint64_t seed, int extra_pass, double* Q,
+                            int64_t ldq, double* R, int64_t ldr, void* work, size_t work_bytes,
+                            int* d_info, void* stream) {
+  if (variant != TSQR_VARIANT_RQR && variant != TSQR_VARIANT_RLU) return -1;
+  const ArgErr e = validate(m, n, A, lda, sketch_rows, Q, ldq, R, ldr);
+  switch (e) {
+    case E_OK: break;
+    case E_M: return -2;
+    case E_N: return -3;
+    case E_A: return -4;
+    case E_LDA: return -5;
+    case E_S: return -6;
+    case E_Q: return -9;
+    case E_LDQ: return -10;
+    case E_R: return -11;
+    case E_LDR: return -12;
+  }
+  if (!work) return -13;
+  if (n > kMaxN) return TSQR_ERR_UNSUPPORTED;
+  if (work_bytes < make_layout(m, n, sketch_rows).total) return TSQR_ERR_WORKSPACE;
+  return run_chain(variant, m, n, A, lda, sketch_rows, seed, extra_pass != 0, Q, ldq, R, ldr, work,
+                   d_info, (hipStream_t)stream, 1);
+}
+
+int tsqr_sketch_rows(int64_t m, int64_t n, const double* A, int64_t lda, int64_t s,
+                     uint64_t seed, double* B, int64_t ldb, void* stream) {
+  if (m < 1) return -1;
+  if (n < 1) return -2;
+  if (!A) return -3;
+  if (lda < m) return -4;
+  if (s < 1 || s > kMaxSketchRows) return -5;
+  if (!B) return -7;
+  if (ldb < s) return -8;
+  if (launch_sketch_rows(m, (int)n, A, lda, (int)s, seed, B, ldb, (hipStream_t)stream) !=
+      hipSuccess)
+    return TSQR_ERR_HIP;
+  return TSQR_OK;
+}
+
+size_t tsqr_cholqr_workspace_bytes(int64_t m, int64_t n) {
+  if (n < 1 || n > kMaxN || m < n) return 0;
+  return make_chol_layout(m, n).total;
+}
+
+int tsqr_cholqr_ws(int algo, int64_t m, int64_t n, const double* A, int64_t lda, double shift,
+                   double* Q, int64_t ldq, double* R, int64_t ldr, void* work, size_t work_bytes,
+                   int* d_info, void* stream) {
+  if (algo != TSQR_ALGO_CHOLQR && algo != TSQR_ALGO_CHOLQR2 && algo != TSQR_ALGO_SCHOLQR3)
+    return -1;
+  const ArgErr e = validate(m, n, A, lda, n, Q, ldq, R, ldr);
+  switch (e) {
+    case E_OK: break;
+    case E_M: return -2;
+    case E_N: return -3;
+    case E_A: return -4;
+    case E_LDA: return -5;
+    case E_S: return -3;
+    case E_Q: return -7;
+    case E_LDQ: return -8;
+    case E_R: return -9;
+    case E_LDR: return -10;
+  }
+  if (!(shift == shift)) return -6;
+  if (!work) return -11;
+  if (n > kMaxN) return TSQR_ERR_UNSUPPORTED;
+  if (work_bytes < make_chol_layout(m, n).total) return TSQR_ERR_WORKSPACE;
+  const int npass = algo;  // 1, 2 or 3 passes
+  return run_cholqr(npass, algo == TSQR_ALGO_SCHOLQR3, m, n, A, lda, shift, Q, ldq, R, ldr,
+                    work, d_info, (hipStream_t)stream);
 }
 
 size_t tsqr_mixed_workspace_bytes(int64_t m, int64_t n, int64_t sketch_rows, int lowp) {

@@ -64,6 +64,10 @@ hipError_t launch_trmm_upper(int n, const double* A, int64_t lda, const double* 
 // If *info != 0, fill Q (m x n) and R (n x n, optional) with NaN
 hipError_t launch_poison(const int* info, int64_t m, int n, double* Q, int64_t ldq, double* R,
                          int64_t ldr, hipStream_t st);
+hipError_t launch_sketch_rows(int64_t m, int n, const double* A, int64_t lda, int s,
+                              uint64_t seed, double* B, int64_t ldb, hipStream_t st);
+hipError_t launch_add_diag(int n, double* W, int64_t ldw, double coef, const double* scale,
+                           hipStream_t st);
 hipError_t launch_set_int(int* p, int v, hipStream_t st);
 hipError_t launch_identity(int n, double* Y, hipStream_t st);
 // C = *flag ? B : A B (upper n x n)

@@ -127,3 +127,37 @@ def test_mixed_width_limit(lib):
     assert lib.tsqr_mixed_workspace_bytes(4096, 256, 512, 1) > 0
     assert lib.tsqr_mixed_workspace_bytes(4096, 300, 600, 1) == 0
     assert lib.tsqr_workspace_bytes(4096, 1024, 2048) > 0
+
+
+def test_rows_and_cholqr_argument_codes(lib):
+    """Host-only argument checks of the row-extraction and CholeskyQR-family entries."""
+    A, Q, R, W = (ctypes.c_void_p(x) for x in (0x10000000, 0x20000000, 0x30000000, 0x40000000))
+    rows = lib.tsqr_rxr_cholqr_rows_ws
+    assert rows(2, 64, 8, A, 64, 16, 1, 1, Q, 64, R, 8, W, 1, None, None) == -1   # variant
+    assert rows(0, 64, 8, A, 64, 4, 1, 1, Q, 64, R, 8, W, 1, None, None) == -6    # s < n
+    assert rows(0, 64, 8, A, 64, 16, 1, 1, Q, 64, R, 8, None, 1, None, None) == -13
+    assert rows(0, 64, 8, A, 64, 16, 1, 1, Q, 64, R, 8, W, 1, None, None) == -101  # too small
+    sk = lib.tsqr_sketch_rows
+    assert sk(0, 8, A, 64, 16, 1, Q, 16, None) == -1
+    assert sk(64, 0, A, 64, 16, 1, Q, 16, None) == -2
+    assert sk(64, 8, None, 64, 16, 1, Q, 16, None) == -3
+    assert sk(64, 8, A, 63, 16, 1, Q, 16, None) == -4
+    assert sk(64, 8, A, 64, 0, 1, Q, 16, None) == -5
+    assert sk(64, 8, A, 64, 16, 1, None, 16, None) == -7
+    assert sk(64, 8, A, 64, 16, 1, Q, 15, None) == -8
+    lib.tsqr_cholqr_workspace_bytes.restype = ctypes.c_size_t
+    assert lib.tsqr_cholqr_workspace_bytes(64, 8) > 0
+    assert lib.tsqr_cholqr_workspace_bytes(4, 8) == 0
+    assert lib.tsqr_cholqr_workspace_bytes(4096, 2000) == 0
+    ch = lib.tsqr_cholqr_ws
+    ch.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                   ctypes.c_double, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                   ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                   ctypes.c_void_p]
+    assert ch(4, 64, 8, A, 64, -1.0, Q, 64, R, 8, W, 1, None, None) == -1        # algo
+    assert ch(2, 4, 8, A, 4, -1.0, Q, 4, R, 8, W, 1, None, None) == -2           # m < n
+    assert ch(2, 64, 8, A, 63, -1.0, Q, 64, R, 8, W, 1, None, None) == -5        # lda
+    assert ch(3, 64, 8, A, 64, float("nan"), Q, 64, R, 8, W, 1, None, None) == -6
+    assert ch(2, 64, 8, A, 64, -1.0, A, 64, R, 8, W, 1, None, None) == -7        # Q aliases A
+    assert ch(2, 64, 8, A, 64, -1.0, Q, 64, R, 8, None, 1, None, None) == -11
+    assert ch(2, 64, 8, A, 64, -1.0, Q, 64, R, 8, W, 1, None, None) == -101      # too small
