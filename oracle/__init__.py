@@ -54,6 +54,8 @@ def _load():
                                         _c_u64, _c_int, _c_dp, _c_i64, _c_dp, _c_i64, _c_dp,
                                         _c_dp, _c_dp]),
         "or_sample_rows": (None, [_c_i64, _c_i64, _c_u64, ctypes.POINTER(ctypes.c_int64)]),
+        "or_lstsq_rxr": (_c_int, [_c_int, _c_int, _c_i64, _c_i64, _c_dp, _c_i64, _c_dp, _c_i64,
+                                  _c_u64, _c_dp]),
         "or_sketch_rows": (None, [_c_i64, _c_i64, _c_dp, _c_i64, _c_i64, _c_u64, _c_dp,
                                   _c_i64]),
         "or_cholqr_n": (_c_int, [_c_i64, _c_i64, _c_dp, _c_i64, _c_int, ctypes.c_double,
@@ -202,6 +204,20 @@ def rxr_cholqr(A: np.ndarray, s: int, seed: int, variant: int = RQR, extra_pass:
     info = fn(variant, m, n, _ptr(A), _ld(A), s, seed, int(extra_pass), _ptr(Q), max(1, m),
               _ptr(R), max(1, n), _ptr(R0), _ptr(R1), _ptr(R2))
     return {"Q": Q, "R": R, "R0": R0, "R1": R1, "R2": R2, "info": info}
+
+
+def lstsq(A: np.ndarray, b: np.ndarray, s: int, seed: int, variant: int = RQR,
+          sketch: str = "gaussian"):
+    """Least squares preconditioned by the sketch's R factor (Section 5.2).
+    Returns (x, info)."""
+    A = _f64(A, "A")
+    m, n = A.shape
+    b = np.ascontiguousarray(b, dtype=np.float64).reshape(m)
+    x = np.zeros(n, dtype=np.float64)
+    info = _load().or_lstsq_rxr(variant, 0 if sketch == "gaussian" else 1, m, n, _ptr(A),
+                                _ld(A), b.ctypes.data_as(_c_dp), s, seed,
+                                x.ctypes.data_as(_c_dp))
+    return x, info
 
 
 def sample_rows(m: int, s: int, seed: int) -> np.ndarray:

@@ -447,6 +447,66 @@ int or_rxr_cholqr_rows(int variant, int64_t m, int64_t n, const double *A, int64
                         R1o, R2o);
 }
 
+/* ------------------------------------------------------------------------------------
+ * Least squares min ||A x - b||_2 preconditioned by the sketch's R factor (paper Section
+ * 5.2, Algorithm "LS solver preconditioned by randomized R factor"; the paper's R_1 is
+ * the R0 of the methods above):
+ *   R0 = R factor of the sketch (Gaussian: sketch = 0, row extraction: sketch = 1; QR or
+ *        LU by variant);
+ *   B = A R0^{-1};
+ *   y = (B^T B)^{-1} B^T b, by the normal equation: G = B^T B = U^T U (Cholesky),
+ *       c = B^T b, U^T z = c, U y = z;
+ *   x = R0^{-1} y  (R0 x = y).
+ * Returns 0, or 1000 + k (small factorization), 2000 + k (Cholesky of G); x NaN then.
+ * ------------------------------------------------------------------------------------ */
+int or_lstsq_rxr(int variant, int sketch, int64_t m, int64_t n, const double *A, int64_t lda,
+                 const double *b, int64_t s, uint64_t seed, double *x) {
+    size_t nn = (size_t)n * (size_t)n;
+    double *Bs = (double *)malloc((size_t)s * (size_t)n * sizeof(double));
+    double *R0 = (double *)calloc(nn, sizeof(double));
+    double *U = (double *)calloc(nn, sizeof(double));
+    double *G = (double *)calloc(nn, sizeof(double));
+    double *B = (double *)malloc((size_t)m * (size_t)n * sizeof(double));
+    double *c = (double *)calloc((size_t)n, sizeof(double));
+    double *z = (double *)calloc((size_t)n, sizeof(double));
+    int info = 0;
+    if (sketch == 1) or_sketch_rows(m, n, A, lda, s, seed, Bs, s);
+    else or_sketch_apply(m, n, A, lda, s, seed, Bs, s);
+    info = (variant == 1) ? or_lu_r(s, n, Bs, s, R0, n, NULL) : or_householder_r(s, n, Bs, s, R0, n);
+    if (!info) {
+        or_trsm_ru(m, n, A, lda, R0, n, B, m);
+        or_gram(m, n, B, m, G, n);
+        for (int64_t j = 0; j < n; ++j) {
+            double acc = 0.0;
+            for (int64_t i = 0; i < m; ++i) acc += B[IDX(i, j, m)] * b[i];
+            c[j] = acc;
+        }
+        int k = or_cholesky_upper(n, G, n, U, n);
+        if (k) info = 2000 + k;
+    }
+    if (!info) {
+        for (int64_t i = 0; i < n; ++i) {  /* U^T z = c */
+            double acc = c[i];
+            for (int64_t k = 0; k < i; ++k) acc -= U[IDX(k, i, n)] * z[k];
+            z[i] = acc / U[IDX(i, i, n)];
+        }
+        for (int64_t i = n - 1; i >= 0; --i) {  /* U y = z (y into c) */
+            double acc = z[i];
+            for (int64_t k = i + 1; k < n; ++k) acc -= U[IDX(i, k, n)] * c[k];
+            c[i] = acc / U[IDX(i, i, n)];
+        }
+        for (int64_t i = n - 1; i >= 0; --i) {  /* R0 x = y */
+            double acc = c[i];
+            for (int64_t k = i + 1; k < n; ++k) acc -= R0[IDX(i, k, n)] * x[k];
+            x[i] = acc / R0[IDX(i, i, n)];
+        }
+    } else {
+        for (int64_t i = 0; i < n; ++i) x[i] = NAN;
+    }
+    free(Bs); free(R0); free(U); free(G); free(B); free(c); free(z);
+    return info;
+}
+
 /* CholeskyQR (npass = 1), CholeskyQR2 (npass = 2) and plain repeated passes, with an
  * optional diagonal shift on the first Gram matrix G (paper Algorithm sCholeskyQR3 uses a
  * shift with npass = 3): shift > 0 is added as given; shift < 0 adds the paper's suggested

@@ -115,3 +115,37 @@ def test_scholqr3_with_suggested_shift_and_cholqr2_collapse():
     assert i3 == 0
     assert oracle.orthogonality(Q3) < 1e-13
     assert oracle.residual(A, Q3, R3) < 1e-14
+
+
+# ---------------------------------------------------------------- least squares ----
+@pytest.mark.parametrize("sketch", ["gaussian", "rows"])
+@pytest.mark.parametrize("variant", [oracle.RQR, oracle.RLU])
+@pytest.mark.parametrize("kappa", [1e3, 1e10])
+def test_lstsq_against_lapack(sketch, variant, kappa):
+    """Section 5.2's solver: a consistent system is solved to its forward-error level
+    kappa u (with constant 100), and an inconsistent one agrees with LAPACK's
+    QR-based least-squares solution to the same level."""
+    m, n = 4096, 32
+    A = gen_matrix(m, n, kappa, 3)
+    rng = np.random.default_rng(1)
+    xt = rng.standard_normal(n)
+    x, info = oracle.lstsq(A, A @ xt, 64, 5, variant=variant, sketch=sketch)
+    assert info == 0
+    assert np.linalg.norm(x - xt) / np.linalg.norm(xt) <= 100 * kappa * U64
+    b = A @ xt + 1e-3 * rng.standard_normal(m)
+    x2, info = oracle.lstsq(A, b, 64, 5, variant=variant, sketch=sketch)
+    xl = np.linalg.lstsq(A, b, rcond=None)[0]
+    assert info == 0
+    assert np.linalg.norm(x2 - xl) / np.linalg.norm(xl) <= 100 * kappa * U64
+
+
+def test_lstsq_closed_form():
+    """A = [D; 0] with D diagonal: x = b[:n] / diag(D) whatever the sketch and its R."""
+    m, n = 512, 8
+    A = np.zeros((m, n), order="F")
+    d = 2.0 ** np.arange(n)
+    A[:n, :n] = np.diag(d)
+    b = np.arange(1.0, m + 1.0)
+    x, info = oracle.lstsq(A, b, 16, 2)
+    assert info == 0
+    assert np.allclose(x, b[:n] / d, rtol=1e-14, atol=0)
