@@ -251,6 +251,20 @@ def baselines_comparison(args, kappas):
             code = int(info.item())
             o, r = gpu_metrics(A, Q, R) if code == 0 else (None, None)
             row[name] = {"ms": round(ms, 4), "info": code, "ortho": o, "residual": r}
+        # Section 5.2's least-squares solver on b = A x_true (forward error against x_true)
+        xt = torch.from_numpy(np.random.default_rng(3).standard_normal(n)).cuda()
+        bv = (A @ xt.unsqueeze(1)).squeeze(1).contiguous()
+        lwork = torch.empty(tsqr.load().tsqr_lstsq_workspace_bytes(m, n, s), dtype=torch.uint8,
+                            device="cuda")
+        xv = torch.empty(n, dtype=torch.float64, device="cuda")
+        for sk in ("rows", "gaussian"):
+            def ls(sk=sk):
+                tsqr.lstsq(A, bv, s, seed, sketch=sk, x=xv, workspace=lwork, info=info)
+            ms = timed(ls, args.baseline_steps, 2)
+            fe = float((torch.linalg.vector_norm(xv - xt) / torch.linalg.vector_norm(xt)).item())
+            row[f"lstsq_{sk}"] = {"ms": round(ms, 4), "info": int(info.item()),
+                                  "forward_error": fe}
+        del lwork
         base = row["rqr_rows"]["ms"]
         row["time_vs_rqr_rows"] = {k: round(row[k]["ms"] / base, 3)
                                    for k in methods if row[k]["info"] == 0}

@@ -115,6 +115,31 @@ int tsqr_rxr_cholqr_rows_ws(int variant, int64_t m, int64_t n, const double* A, 
                             int* d_info, void* stream);
 
 /* ------------------------------------------------------------------------------------
+ * Least squares min ||A x - b||_2 preconditioned by the sketch's R factor (paper Section
+ * 5.2, Algorithm "LS solver preconditioned by randomized R factor"; its R_1 is R0 here):
+ *   R0 = R factor of the sketch (QR or LU of the Gaussian or row-extraction sketch);
+ *   B = A R0^{-1} (right-side TRSM);  G = B^T B = U^T U (Cholesky);  c = B^T b;
+ *   y = U^{-1} U^{-T} c (the normal equation of B y = b);  x = R0^{-1} y.
+ * ------------------------------------------------------------------------------------ */
+#define TSQR_SKETCH_GAUSSIAN 0
+#define TSQR_SKETCH_ROWS 1
+
+/* Bytes of workspace for tsqr_lstsq_ws (0 if the sizes are invalid); it holds B (m x n). */
+size_t tsqr_lstsq_workspace_bytes(int64_t m, int64_t n, int64_t sketch_rows);
+
+/*   variant (1): TSQR_VARIANT_RQR or TSQR_VARIANT_RLU;  sketch (2): TSQR_SKETCH_*;
+ *   m, n, A, lda (3-6): as tsqr_rxr_cholqr_ws;  b (7): device vector of m doubles;
+ *   sketch_rows, seed (8, 9);  x (10): device output, n doubles;
+ *   work, work_bytes (11, 12): at least tsqr_lstsq_workspace_bytes() bytes;
+ *   d_info (13): device int: 1000 + k (small factorization), 2000 + k (Cholesky of G),
+ *     x then NaN; or NULL;  stream (14).
+ * Codes: -i for argument i (m < n is -3), TSQR_ERR_WORKSPACE, TSQR_ERR_UNSUPPORTED
+ * (n > 1024), TSQR_ERR_HIP. */
+int tsqr_lstsq_ws(int variant, int sketch, int64_t m, int64_t n, const double* A, int64_t lda,
+                  const double* b, int64_t sketch_rows, uint64_t seed, double* x, void* work,
+                  size_t work_bytes, int* d_info, void* stream);
+
+/* ------------------------------------------------------------------------------------
  * CholeskyQR family (paper Section 2.1: Algorithms CholeskyQR, CholeskyQR2 and
  * sCholeskyQR3), the baselines the paper compares against, on the same kernels.
  * ------------------------------------------------------------------------------------ */

@@ -39,6 +39,9 @@ _SIGS = {
                                        _vp, _i64, _vp, _sz, _vp, _vp]),
     "tsqr_sketch_rows": (_int, [_i64, _i64, _vp, _i64, _i64, _u64, _vp, _i64, _vp]),
     "tsqr_cholqr_workspace_bytes": (_sz, [_i64, _i64]),
+    "tsqr_lstsq_workspace_bytes": (_sz, [_i64, _i64, _i64]),
+    "tsqr_lstsq_ws": (_int, [_int, _int, _i64, _i64, _vp, _i64, _vp, _i64, _u64, _vp, _vp, _sz,
+                             _vp, _vp]),
     "tsqr_cholqr_ws": (_int, [_int, _i64, _i64, _vp, _i64, ctypes.c_double, _vp, _i64, _vp,
                               _i64, _vp, _sz, _vp, _vp]),
     "tsqr_sketch_workspace_bytes": (_sz, [_i64, _i64, _i64]),
@@ -220,6 +223,31 @@ def rxr_cholqr(A: torch.Tensor, sketch_rows: int, seed: int, variant: int = RQR,
 CHOLQR = 1
 CHOLQR2 = 2
 SCHOLQR3 = 3
+
+
+def lstsq(A: torch.Tensor, b: torch.Tensor, sketch_rows: int, seed: int, variant: int = RQR,
+          sketch: str = "gaussian", x: torch.Tensor | None = None,
+          workspace: torch.Tensor | None = None, info: torch.Tensor | None = None, stream=None):
+    """min ||A x - b||_2 preconditioned by the sketch's R factor.  Returns (x, info)."""
+    lda = _mat(A, "A")
+    m, n = A.shape
+    if b.dtype != torch.float64 or b.device != A.device or b.shape != (m,) or b.stride() != (1,):
+        raise ValueError("b must be a contiguous float64 vector of m entries on A's device")
+    if x is None:
+        x = torch.empty(n, dtype=torch.float64, device=A.device)
+    if x.dtype != torch.float64 or x.shape != (n,) or x.stride() != (1,):
+        raise ValueError("x must be a contiguous float64 vector of n entries")
+    if workspace is None:
+        workspace = torch.empty(max(1, int(load().tsqr_lstsq_workspace_bytes(m, n, sketch_rows))),
+                                dtype=torch.uint8, device=A.device)
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    kind = {"gaussian": 0, "rows": 1}[sketch]
+    rc = load().tsqr_lstsq_ws(variant, kind, m, n, A.data_ptr(), lda, b.data_ptr(), sketch_rows,
+                              seed, x.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                              info.data_ptr(), _stream(stream))
+    _check(rc, "tsqr_lstsq_ws")
+    return x, info
 
 
 def cholqr_workspace_bytes(m: int, n: int) -> int:

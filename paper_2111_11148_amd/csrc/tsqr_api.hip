@@ -305,6 +305,62 @@ int run_cholqr(int npass, bool shifted, int64_t m, int64_t n, const double* A, i
   return TSQR_OK;
 }
 
+// ---- least squares preconditioned by the sketch's R (paper Section 5.2) -----------------
+struct LsqLayout {
+  Layout base;
+  size_t Bm, cpart, c, total;
+};
+
+LsqLayout make_lsq_layout(int64_t m, int64_t n, int64_t s) {
+  LsqLayout L{};
+  L.base = make_layout(m, n, s);
+  size_t off = L.base.total;
+  L.Bm = off; off += align256((size_t)m * n * sizeof(double));
+  L.cpart = off; off += align256(gemv_part_doubles(m, (int)n) * sizeof(double));
+  L.c = off; off += align256((size_t)n * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+// R0 from the sketch; B = A R0^{-1}; G = B^T B = U^T U (stage 2); c = B^T b; then
+// U^T z = c, U y = z, R0 x = y.
+int run_lstsq(int variant, int sketch_kind, int64_t m, int64_t n, const double* A, int64_t lda,
+              const double* b, int64_t s, uint64_t seed, double* x, void* work, int* d_info,
+              hipStream_t st) {
+  const LsqLayout M = make_lsq_layout(m, n, s);
+  const Layout& L = M.base;
+  char* base = (char*)work;
+  int* info = d_info ? d_info : (int*)(base + L.info);
+  double* Bs = (double*)(base + L.B);
+  double* R0 = (double*)(base + L.R0);
+  double* U = (double*)(base + L.R1);
+  double* G = (double*)(base + L.W);
+  double* fac = (double*)(base + L.fac);
+  double* Tt = (double*)(base + L.Tt);
+  double* part = (double*)(base + L.part);
+  double* Bm = (double*)(base + M.Bm);
+  double* cpart = (double*)(base + M.cpart);
+  double* c = (double*)(base + M.c);
+  const int ni = (int)n, si = (int)s;
+  TSQR_CHECK(launch_set_int(info, 0, st));
+  if (sketch_kind == 1) {
+    TSQR_PHASE("sketch_rows", launch_sketch_rows(m, ni, A, lda, si, seed, Bs, s, st));
+  } else {
+    TSQR_PHASE("sketch", launch_sketch(L.sp, m, ni, A, lda, si, seed, part, st));
+    TSQR_PHASE("sketch_reduce",
+               launch_sketch_reduce(L.sp, si, ni, part, 1.0 / sqrt((double)s), Bs, s, st));
+  }
+  TSQR_PHASE(variant == 1 ? "sketch_lu" : "sketch_qr",
+             launch_sketch_factor(variant, si, ni, Bs, s, R0, n, info, fac, st));
+  TSQR_PHASE("trsm_r0", launch_trsm(m, ni, A, lda, R0, n, Bm, m, Tt, st));
+  TSQR_PHASE("gram", launch_gram(L.gp, m, ni, Bm, m, part, st));
+  TSQR_PHASE("gram_reduce", launch_gram_reduce(L.gp, ni, part, G, n, st));
+  TSQR_PHASE("gemv", launch_gemv_t(m, ni, Bm, m, b, cpart, c, st));
+  TSQR_PHASE("potrf", launch_potrf(ni, G, n, U, n, 2, info, fac, st));
+  TSQR_PHASE("solve", launch_lsq_solve(ni, U, n, R0, n, c, x, info, st));
+  return TSQR_OK;
+}
+
 // ---- mixed precision ---------------------------------------------------------------
 // Extra workspace after the FP64 layout: A1 in the input type, R0^{-1} (FP64 and rounded),
 // identity, R01 = R1 R0, two more n x n factors, the low-precision breakdown word, the
@@ -616,6 +672,30 @@ int tsqr_cholqr_ws(int algo, int64_t m, int64_t n, const double* A, int64_t lda,
   const int npass = algo;  // 1, 2 or 3 passes
   return run_cholqr(npass, algo == TSQR_ALGO_SCHOLQR3, m, n, A, lda, shift, Q, ldq, R, ldr,
                     work, d_info, (hipStream_t)stream);
+}
+
+size_t tsqr_lstsq_workspace_bytes(int64_t m, int64_t n, int64_t sketch_rows) {
+  if (n < 1 || n > kMaxN || m < n || sketch_rows < n || sketch_rows > kMaxSketchRows) return 0;
+  return make_lsq_layout(m, n, sketch_rows).total;
+}
+
+int tsqr_lstsq_ws(int variant, int sketch, int64_t m, int64_t n, const double* A, int64_t lda,
+                  const double* b, int64_t sketch_rows, uint64_t seed, double* x, void* work,
+                  size_t work_bytes, int* d_info, void* stream) {
+  if (variant != TSQR_VARIANT_RQR && variant != TSQR_VARIANT_RLU) return -1;
+  if (sketch != TSQR_SKETCH_GAUSSIAN && sketch != TSQR_SKETCH_ROWS) return -2;
+  if (n < 1) return -4;
+  if (m < 1 || m < n) return -3;
+  if (!A) return -5;
+  if (lda < m) return -6;
+  if (!b) return -7;
+  if (sketch_rows < n || sketch_rows > kMaxSketchRows) return -8;
+  if (!x) return -10;
+  if (!work) return -11;
+  if (n > kMaxN) return TSQR_ERR_UNSUPPORTED;
+  if (work_bytes < make_lsq_layout(m, n, sketch_rows).total) return TSQR_ERR_WORKSPACE;
+  return run_lstsq(variant, sketch, m, n, A, lda, b, sketch_rows, seed, x, work, d_info,
+                   (hipStream_t)stream);
 }
 
 size_t tsqr_mixed_workspace_bytes(int64_t m, int64_t n, int64_t sketch_rows, int lowp) {

@@ -68,6 +68,11 @@ hipError_t launch_sketch_rows(int64_t m, int n, const double* A, int64_t lda, in
                               uint64_t seed, double* B, int64_t ldb, hipStream_t st);
 hipError_t launch_add_diag(int n, double* W, int64_t ldw, double coef, const double* scale,
                            hipStream_t st);
+hipError_t launch_gemv_t(int64_t m, int n, const double* X, int64_t ldx, const double* b,
+                         double* part, double* c, hipStream_t st);
+size_t gemv_part_doubles(int64_t m, int n);
+hipError_t launch_lsq_solve(int n, const double* U, int64_t ldu, const double* R0, int64_t ldr,
+                            const double* c, double* x, const int* info, hipStream_t st);
 hipError_t launch_set_int(int* p, int v, hipStream_t st);
 hipError_t launch_identity(int n, double* Y, hipStream_t st);
 // C = *flag ? B : A B (upper n x n)

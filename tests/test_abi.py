@@ -161,3 +161,22 @@ def test_rows_and_cholqr_argument_codes(lib):
     assert ch(2, 64, 8, A, 64, -1.0, A, 64, R, 8, W, 1, None, None) == -7        # Q aliases A
     assert ch(2, 64, 8, A, 64, -1.0, Q, 64, R, 8, None, 1, None, None) == -11
     assert ch(2, 64, 8, A, 64, -1.0, Q, 64, R, 8, W, 1, None, None) == -101      # too small
+
+
+def test_lstsq_argument_codes(lib):
+    A, b, x, W = (ctypes.c_void_p(v) for v in (0x10000000, 0x20000000, 0x30000000, 0x40000000))
+    f = lib.tsqr_lstsq_ws
+    lib.tsqr_lstsq_workspace_bytes.restype = ctypes.c_size_t
+    assert lib.tsqr_lstsq_workspace_bytes(64, 8, 16) > 0
+    assert lib.tsqr_lstsq_workspace_bytes(64, 8, 4) == 0
+    assert f(2, 0, 64, 8, A, 64, b, 16, 1, x, W, 1, None, None) == -1    # variant
+    assert f(0, 2, 64, 8, A, 64, b, 16, 1, x, W, 1, None, None) == -2    # sketch kind
+    assert f(0, 0, 4, 8, A, 4, b, 16, 1, x, W, 1, None, None) == -3     # m < n
+    assert f(0, 0, 64, 0, A, 64, b, 16, 1, x, W, 1, None, None) == -4   # n < 1
+    assert f(0, 0, 64, 8, None, 64, b, 16, 1, x, W, 1, None, None) == -5
+    assert f(0, 0, 64, 8, A, 63, b, 16, 1, x, W, 1, None, None) == -6
+    assert f(0, 0, 64, 8, A, 64, None, 16, 1, x, W, 1, None, None) == -7
+    assert f(0, 0, 64, 8, A, 64, b, 4, 1, x, W, 1, None, None) == -8
+    assert f(0, 0, 64, 8, A, 64, b, 16, 1, None, W, 1, None, None) == -10
+    assert f(0, 0, 64, 8, A, 64, b, 16, 1, x, None, 1, None, None) == -11
+    assert f(0, 1, 64, 8, A, 64, b, 16, 1, x, W, 1, None, None) == -101  # workspace too small
