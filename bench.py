@@ -337,6 +337,22 @@ def batched_comparison(args):
     print(f"# batched: {ms:.3f} ms per batch ({len(descs) / ms * 1e3:.0f} problems/s), loop "
           f"{ms_loop:.3f} ms", file=sys.stderr, flush=True)
     del works
+
+    # the FP32 variant: the sketch from FP32-rounded inputs, every later step FP64
+    del g
+    b32 = tsqr.Batch(As, ss, seeds, precision=tsqr.FP32)
+    tuning32, tuned32 = b32.autotune()
+    g32 = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(st):
+        b32.run(stream=st)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g32, stream=st):
+        b32.run(stream=st)
+    ms32 = timed(g32.replay, args.batch_steps, 2)
+    info32 = bool(torch.all(b32.info == 0).item())
+    worst32 = max(gpu_metrics(As[i], b32.Q[i], b32.R[i])[0] for i in range(len(descs)))
+    print(f"# batched fp32 sketch: {ms32:.3f} ms per batch ({len(descs) / ms32 * 1e3:.0f} "
+          f"problems/s)", file=sys.stderr, flush=True)
     return {"workload": f"{len(descs)} uneven problems, m in [4096, 65536], n in {{16,32,64,128}}, "
                         "kappa 1e2..1e10, s = 2n, rqr + 1 pass, fp64",
             "problems_per_s": round(len(descs) / ms * 1e3, 1), "ms_per_batch": round(ms, 4),
@@ -345,7 +361,11 @@ def batched_comparison(args):
             "loop_ms_per_batch": round(ms_loop, 4), "speedup_vs_loop": round(ms_loop / ms, 3),
             "launches_per_run": b.launches, "tuning": tuning.as_dict(),
             "autotune_ms": round(tuned_ms, 4), "graph": True, "all_info_zero": info_ok,
-            "worst_ortho": worst}
+            "worst_ortho": worst,
+            "fp32": {"problems_per_s": round(len(descs) / ms32 * 1e3, 1),
+                     "ms_per_batch": round(ms32, 4), "tuning": tuning32.as_dict(),
+                     "all_info_zero": info32, "worst_ortho": worst32,
+                     "speedup_vs_fp64_batch": round(ms / ms32, 3)}}
 
 
 def main() -> int:

@@ -228,7 +228,12 @@ int tsqr_gram_lowp(int lowp, int64_t m, int64_t n, const void* X, int64_t ldx, d
  * Section 2.3 and one more CholeskyQR pass); the split-K blockings differ from the
  * single-problem calls, so results agree with them to rounding, not bitwise.
  * Limits: 1 <= n <= 128, n <= s <= 512 (s <= 256 when n > 64), m >= n; any other problem
- * makes the create call return -3. */
+ * makes the create call return -4.
+ * Precision: TSQR_BATCH_FP64 runs every step in FP64; TSQR_LOWP_FP32 or TSQR_LOWP_BF16
+ * computes the sketch S A from inputs rounded to that type with FP32 accumulation flushed
+ * into FP64 every 64 rows (as tsqr_sketch_lowp) and every later step in FP64, the mixed
+ * variant with the low precision in the sketch alone. */
+#define TSQR_BATCH_FP64 0
 typedef struct {
   int64_t m, n;        /* rows and columns of A */
   int64_t lda;         /* leading dimension of A (>= m) */
@@ -257,23 +262,24 @@ size_t tsqr_batched_workspace_bytes(int64_t count, const tsqr_problem* problems)
 
 /* Plan a batch: groups the problems by width, sizes their blockings, lays out `work` and
  * uploads the problem descriptors and work lists into it (synchronously).  Arguments:
- * variant (1), count (2), problems (3, host array, not kept), work / work_bytes (4, 5),
- * d_info (6: device int[count], one breakdown code per problem as for tsqr_rxr_cholqr_ws),
- * tuning (7: NULL for the defaults 2048 / 2048 / 64), out (8: receives the plan).  The plan
- * refers to `work`, `d_info` and the problems' device buffers: they must stay valid and
- * unmoved while the plan is used. */
-int tsqr_batched_create(int variant, int64_t count, const tsqr_problem* problems, void* work,
-                        size_t work_bytes, int* d_info, const tsqr_batch_tuning* tuning,
-                        tsqr_batch** out);
+ * variant (1), precision (2: TSQR_BATCH_FP64, TSQR_LOWP_FP32 or TSQR_LOWP_BF16), count (3),
+ * problems (4, host array, not kept), work / work_bytes (5, 6), d_info (7: device
+ * int[count], one breakdown code per problem as for tsqr_rxr_cholqr_ws), tuning (8: NULL
+ * for the defaults 2048 / 2048 / 64), out (9: receives the plan).  The plan refers to
+ * `work`, `d_info` and the problems' device buffers: they must stay valid and unmoved
+ * while the plan is used. */
+int tsqr_batched_create(int variant, int precision, int64_t count, const tsqr_problem* problems,
+                        void* work, size_t work_bytes, int* d_info,
+                        const tsqr_batch_tuning* tuning, tsqr_batch** out);
 
 /* Autotuner: plans and runs the batch with candidate blockings (coordinate search over
  * the sketch rows, the Gram rows and the solve tiles, each from four values) and returns
  * the fastest in *best and its time per run in *best_ms (may be NULL).  Runs the batch
  * (writes Q, R and d_info) and waits for the stream: call it outside any capture.
- * Arguments as tsqr_batched_create, then stream (7), best (8), best_ms (9). */
-int tsqr_batched_autotune(int variant, int64_t count, const tsqr_problem* problems, void* work,
-                          size_t work_bytes, int* d_info, void* stream, tsqr_batch_tuning* best,
-                          double* best_ms);
+ * Arguments as tsqr_batched_create up to d_info, then stream (8), best (9), best_ms (10). */
+int tsqr_batched_autotune(int variant, int precision, int64_t count,
+                          const tsqr_problem* problems, void* work, size_t work_bytes, int* d_info,
+                          void* stream, tsqr_batch_tuning* best, double* best_ms);
 
 /* Enqueue the whole batch on `stream`.  Kernel launches only (no allocation, copy or host
  * synchronisation), so a stream capture of this call records the batch as one graph. */

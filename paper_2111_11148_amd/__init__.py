@@ -67,8 +67,9 @@ _SIGS = {
                                     _vp]),
     "tsqr_gram_lowp": (_int, [_int, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp]),
     "tsqr_batched_workspace_bytes": (_sz, [_i64, _vp]),
-    "tsqr_batched_create": (_int, [_int, _i64, _vp, _vp, _sz, _vp, _vp, ctypes.POINTER(_vp)]),
-    "tsqr_batched_autotune": (_int, [_int, _i64, _vp, _vp, _sz, _vp, _vp, _vp,
+    "tsqr_batched_create": (_int, [_int, _int, _i64, _vp, _vp, _sz, _vp, _vp,
+                                   ctypes.POINTER(_vp)]),
+    "tsqr_batched_autotune": (_int, [_int, _int, _i64, _vp, _vp, _sz, _vp, _vp, _vp,
                                      ctypes.POINTER(ctypes.c_double)]),
     "tsqr_batched_run": (_int, [_vp, _vp]),
     "tsqr_batched_launches": (_int, [_vp]),
@@ -510,7 +511,9 @@ class Batch:
     may be captured into a HIP graph); info is a (count,) int32 device tensor."""
 
     def __init__(self, As, sketch_rows, seeds, variant: int = RQR, want_r: bool = True,
-                 tuning: "BatchTuning | None" = None):
+                 tuning: "BatchTuning | None" = None, precision: int = 0):
+        """precision: 0 (FP64 throughout), FP32 or BF16 (the sketch's inputs rounded to that
+        type, every later step FP64)."""
         count = len(As)
         if count < 1:
             raise ValueError("empty batch")
@@ -534,8 +537,9 @@ class Batch:
         self.work = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self.info = torch.zeros(count, dtype=torch.int32, device=dev)
         self._probs, self._variant, self._nbytes = probs, variant, nbytes
+        self._precision = precision
         plan = _vp()
-        _check(load().tsqr_batched_create(variant, count, ctypes.cast(probs, _vp),
+        _check(load().tsqr_batched_create(variant, precision, count, ctypes.cast(probs, _vp),
                                           self.work.data_ptr(), nbytes, self.info.data_ptr(),
                                           ctypes.byref(tuning) if tuning is not None else None,
                                           ctypes.byref(plan)), "tsqr_batched_create")
@@ -546,13 +550,13 @@ class Batch:
         """Measure candidate blockings on this batch; returns (BatchTuning, ms per run).
         Re-plans this batch with the winner."""
         best, ms = BatchTuning(), ctypes.c_double(0.0)
-        _check(load().tsqr_batched_autotune(self._variant, self.count,
+        _check(load().tsqr_batched_autotune(self._variant, self._precision, self.count,
                                             ctypes.cast(self._probs, _vp), self.work.data_ptr(),
                                             self._nbytes, self.info.data_ptr(), _stream(stream),
                                             ctypes.byref(best), ctypes.byref(ms)),
                "tsqr_batched_autotune")
         plan = _vp()
-        _check(load().tsqr_batched_create(self._variant, self.count,
+        _check(load().tsqr_batched_create(self._variant, self._precision, self.count,
                                           ctypes.cast(self._probs, _vp), self.work.data_ptr(),
                                           self._nbytes, self.info.data_ptr(), ctypes.byref(best),
                                           ctypes.byref(plan)), "tsqr_batched_create")

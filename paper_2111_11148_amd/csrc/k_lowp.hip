@@ -56,10 +56,12 @@ __device__ __forceinline__ int lowp_to_f64_tile_index(int lane, int r) {
 // ===================================================================== sketch ====
 // One workgroup: a row block of A, i-tiles it0.. of B for each wavefront, JT column tiles.
 // A is staged in LDS column-major (rows contiguous) already rounded to the input type.
+// Body of workgroup (row block bx, i-group by, column group bz).
 template <int PREC, int IT, int JT, int NW>
-__global__ __launch_bounds__(NW * 64) void k_sketch_lowp(
+__device__ __forceinline__ void sketch_lowp_body(
     int64_t m, int n, const double* __restrict__ A, int64_t lda, uint32_t k0, uint32_t k1,
-    int64_t rows_per_block, int it_total, int jt_total, double* __restrict__ part) {
+    int64_t rows_per_block, int it_total, int jt_total, double* __restrict__ part, int bx,
+    int by, int bz) {
   typedef typename LowT<PREC>::E E;
   constexpr int KC = 64;                       // rows per chunk
   constexpr int NC = JT * 16;
@@ -69,10 +71,10 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_lowp(
 
   const int lane = lane_id(), wave = wave_id();
   const int q = lane >> 4, c16 = lane & 15;
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r0 = (int64_t)bx * rows_per_block;
   const int64_t r1 = min(m, r0 + rows_per_block);
-  const int it0 = (int)blockIdx.y * (NW * IT) + wave * IT;
-  const int c0 = (int)blockIdx.z * NC;
+  const int it0 = by * (NW * IT) + wave * IT;
+  const int c0 = bz * NC;
 
   v4f acc[IT][JT];
   v4d acc64[IT][JT];
@@ -153,20 +155,39 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_lowp(
   }
 
   const size_t Et = (size_t)it_total * jt_total * 256;
-  double* dst = part + (size_t)blockIdx.x * Et;
+  double* dst = part + (size_t)bx * Et;
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int itg = it0 + it;
     if (itg >= it_total) continue;
 #pragma unroll
     for (int jt = 0; jt < JT; ++jt) {
-      const int jtg = (int)blockIdx.z * JT + jt;
+      const int jtg = bz * JT + jt;
       if (jtg >= jt_total) continue;
       double* tp = dst + ((size_t)itg * jt_total + jtg) * 256;
 #pragma unroll
       for (int r = 0; r < 4; ++r) tp[lowp_to_f64_tile_index(lane, r)] = acc64[it][jt][r];
     }
   }
+}
+
+template <int PREC, int IT, int JT, int NW>
+__global__ __launch_bounds__(NW * 64) void k_sketch_lowp(
+    int64_t m, int n, const double* __restrict__ A, int64_t lda, uint32_t k0, uint32_t k1,
+    int64_t rows_per_block, int it_total, int jt_total, double* __restrict__ part) {
+  sketch_lowp_body<PREC, IT, JT, NW>(m, n, A, lda, k0, k1, rows_per_block, it_total, jt_total,
+                                     part, (int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z);
+}
+
+// Batched form: one work item (problem, row block, i-group, column group) per workgroup;
+// the partials have the FP64 sketch's layout, so the batched FP64 reduction sums them.
+template <int PREC, int IT, int JT, int NW>
+__global__ __launch_bounds__(NW * 64) void k_b_sketch_lowp(const BItem* __restrict__ items,
+                                                           const BProb* __restrict__ probs) {
+  const BItem it = items[blockIdx.x];
+  const BProb& p = probs[it.pid];
+  sketch_lowp_body<PREC, IT, JT, NW>(p.m, p.n, p.A, p.lda, p.k0, p.k1, p.sk_rpb, p.sk_it,
+                                     p.sk_jt, p.part, it.x, it.y, it.z);
 }
 
 // Wide sketch (129..256 columns): every normal is generated once. A workgroup owns NW*IT
@@ -757,6 +778,27 @@ hipError_t launch_apply_rinv_lowp(int prec, int64_t m, int n, const double* Y, i
   TSQR_APL(TSQR_LOWP_BF16, 1) TSQR_APL(TSQR_LOWP_BF16, 2) TSQR_APL(TSQR_LOWP_BF16, 4)
   TSQR_APL(TSQR_LOWP_BF16, 8) TSQR_APL(TSQR_LOWP_BF16, 16)
 #undef TSQR_APL
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_b_sketch_lowp(int prec, int IT, int JT, int NW, const BItem* items, int nitems,
+                                const BProb* probs, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+#define TSQR_BSKL(PR, IT_, JT_, NW_)                                                            \
+  if (prec == PR && IT == IT_ && JT == JT_ && NW == NW_) {                                     \
+    hipLaunchKernelGGL((k_b_sketch_lowp<PR, IT_, JT_, NW_>), dim3(nitems), dim3(NW_ * 64), 0,   \
+                       st, items, probs);                                                      \
+    return hipGetLastError();                                                                  \
+  }
+#define TSQR_BSKL_ALL(PR)                                                                      \
+  TSQR_BSKL(PR, 1, 1, 4) TSQR_BSKL(PR, 1, 2, 4) TSQR_BSKL(PR, 1, 4, 4) TSQR_BSKL(PR, 1, 8, 4) \
+  TSQR_BSKL(PR, 1, 1, 8) TSQR_BSKL(PR, 1, 2, 8) TSQR_BSKL(PR, 1, 4, 8) TSQR_BSKL(PR, 1, 8, 8) \
+  TSQR_BSKL(PR, 2, 8, 4) TSQR_BSKL(PR, 2, 8, 8) TSQR_BSKL(PR, 2, 4, 8) TSQR_BSKL(PR, 2, 4, 4) \
+  TSQR_BSKL(PR, 2, 2, 8) TSQR_BSKL(PR, 2, 1, 8) TSQR_BSKL(PR, 2, 2, 4) TSQR_BSKL(PR, 2, 1, 4)
+  TSQR_BSKL_ALL(TSQR_LOWP_FP32)
+  TSQR_BSKL_ALL(TSQR_LOWP_BF16)
+#undef TSQR_BSKL_ALL
+#undef TSQR_BSKL
   return hipErrorInvalidValue;
 }
 

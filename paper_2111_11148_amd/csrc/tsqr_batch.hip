@@ -58,6 +58,7 @@ struct Launch {
 
 struct tsqr_batch {
   int variant = 0;
+  int precision = 0;  // TSQR_BATCH_FP64, or TSQR_LOWP_FP32 / TSQR_LOWP_BF16 for the sketch
   int64_t count = 0;
   size_t probs_off = 0, items_off = 0;
   tsqr::BProb* probs_dev = nullptr;
@@ -104,17 +105,18 @@ size_t problem_doubles(int64_t m, int n, int s, const tsqr_batch_tuning& t) {
   return d;
 }
 
+// Codes in the numbering of tsqr_batched_create (count is argument 3, problems 4).
 int validate(int64_t count, const tsqr_problem* pr) {
-  if (count < 1) return -2;
-  if (!pr) return -3;
+  if (count < 1) return -3;
+  if (!pr) return -4;
   for (int64_t i = 0; i < count; ++i) {
     const tsqr_problem& q = pr[i];
     if (q.n < 1 || q.n > 128 || q.m < q.n || q.s < q.n || q.s > 512 || !q.A || q.lda < q.m ||
         !q.Q || q.ldq < q.m || (q.R && q.ldr < q.n))
-      return -3;
+      return -4;
     // the register-resident factorization of the sketch holds s x n in one workgroup:
     // 8 rows and 8 columns per lane do not fit, so s <= 256 when n > 64
-    if (q.n > 64 && q.s > 256) return -3;
+    if (q.n > 64 && q.s > 256) return -4;
   }
   return 0;
 }
@@ -158,19 +160,21 @@ size_t tsqr_batched_workspace_bytes(int64_t count, const tsqr_problem* problems)
   return header_bytes(count, items) + bufs;
 }
 
-int tsqr_batched_create(int variant, int64_t count, const tsqr_problem* problems, void* work,
-                        size_t work_bytes, int* d_info, const tsqr_batch_tuning* tuning,
-                        tsqr_batch** out) {
+int tsqr_batched_create(int variant, int precision, int64_t count, const tsqr_problem* problems,
+                        void* work, size_t work_bytes, int* d_info,
+                        const tsqr_batch_tuning* tuning, tsqr_batch** out) {
   if (variant != TSQR_VARIANT_RQR && variant != TSQR_VARIANT_RLU) return -1;
+  if (precision != TSQR_BATCH_FP64 && precision != TSQR_LOWP_FP32 && precision != TSQR_LOWP_BF16)
+    return -2;
   const int v = validate(count, problems);
   if (v) return v;
-  if (!work) return -4;
-  if (!d_info) return -6;
+  if (!work) return -5;
+  if (!d_info) return -7;
   const tsqr_batch_tuning t = tuning ? *tuning : kDefaultTuning;
   if (t.sketch_rows < kMinRows || t.sketch_rows % 64 || t.gram_rows < kMinRows ||
       t.gram_rows % 64 || t.trsm_tiles < kMinTiles)
-    return -7;
-  if (!out) return -8;
+    return -8;
+  if (!out) return -9;
   *out = nullptr;
   const size_t need = tsqr_batched_workspace_bytes(count, problems);
   if (work_bytes < need) return TSQR_ERR_WORKSPACE;
@@ -300,6 +304,7 @@ int tsqr_batched_create(int variant, int64_t count, const tsqr_problem* problems
   tsqr_batch* plan = new (std::nothrow) tsqr_batch;
   if (!plan) return TSQR_ERR_HIP;
   plan->variant = variant;
+  plan->precision = precision;
   plan->count = count;
   plan->probs_dev = (BProb*)base;
   plan->items_dev = (BItem*)(base + probs_bytes);
@@ -331,7 +336,12 @@ int tsqr_batched_run(tsqr_batch* plan, void* stream) {
     hipError_t e = hipSuccess;
     switch (L.phase) {
       case kSetInfo: e = launch_b_set_info(it, L.count, P, st); break;
-      case kSketch: e = launch_b_sketch(k.sk_it, k.sk_jt, k.sk_nw, it, L.count, P, st); break;
+      case kSketch:
+        e = plan->precision == TSQR_BATCH_FP64
+                ? launch_b_sketch(k.sk_it, k.sk_jt, k.sk_nw, it, L.count, P, st)
+                : launch_b_sketch_lowp(plan->precision, k.sk_it, k.sk_jt, k.sk_nw, it, L.count,
+                                       P, st);
+        break;
       case kSketchReduce: e = launch_b_sketch_reduce(it, L.count, P, st); break;
       case kFactor: e = launch_b_factor(plan->variant, k.qr_rpl, k.qr_cpw, it, L.count, P, st); break;
       case kPrep0: e = launch_b_trsm_prep(0, it, L.count, P, st); break;
@@ -356,10 +366,10 @@ int tsqr_batched_run(tsqr_batch* plan, void* stream) {
   return TSQR_OK;
 }
 
-int tsqr_batched_autotune(int variant, int64_t count, const tsqr_problem* problems, void* work,
-                          size_t work_bytes, int* d_info, void* stream, tsqr_batch_tuning* best,
-                          double* best_ms) {
-  if (!best) return -8;
+int tsqr_batched_autotune(int variant, int precision, int64_t count,
+                          const tsqr_problem* problems, void* work, size_t work_bytes, int* d_info,
+                          void* stream, tsqr_batch_tuning* best, double* best_ms) {
+  if (!best) return -9;
   hipStream_t st = (hipStream_t)stream;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return TSQR_ERR_HIP;
@@ -370,7 +380,8 @@ int tsqr_batched_autotune(int variant, int64_t count, const tsqr_problem* proble
   // time of one run of the batch planned with `t` (warm-up run, then the mean of two)
   auto measure = [&](const tsqr_batch_tuning& t, double* ms) -> int {
     tsqr_batch* plan = nullptr;
-    int rc = tsqr_batched_create(variant, count, problems, work, work_bytes, d_info, &t, &plan);
+    int rc = tsqr_batched_create(variant, precision, count, problems, work, work_bytes, d_info, &t,
+                                 &plan);
     if (rc) return rc;
     rc = tsqr_batched_run(plan, st);
     if (!rc && hipEventRecord(e0, st) != hipSuccess) rc = TSQR_ERR_HIP;

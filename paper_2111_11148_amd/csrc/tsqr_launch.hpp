@@ -129,6 +129,8 @@ struct BItem {
   int pid, x, y, z;
 };
 
+hipError_t launch_b_sketch_lowp(int prec, int IT, int JT, int NW, const BItem* items, int nitems,
+                                const BProb* probs, hipStream_t st);
 hipError_t launch_b_sketch(int IT, int JT, int NW, const BItem* items, int nitems,
                            const BProb* probs, hipStream_t st);
 hipError_t launch_b_sketch_reduce(const BItem* items, int nitems, const BProb* probs,

@@ -109,15 +109,17 @@ def test_batched_descriptor_validation(lib):
         arr = (P * 2)(good, bad)
         assert lib.tsqr_batched_workspace_bytes(2, ctypes.cast(arr, ctypes.c_void_p)) == 0
         plan = ctypes.c_void_p()
-        rc = lib.tsqr_batched_create(0, 2, ctypes.cast(arr, ctypes.c_void_p), 16, 1 << 30, 16,
-                                     None, ctypes.byref(plan))
-        assert rc == -3 and plan.value is None
+        rc = lib.tsqr_batched_create(0, 0, 2, ctypes.cast(arr, ctypes.c_void_p), 16, 1 << 30,
+                                     16, None, ctypes.byref(plan))
+        assert rc == -4 and plan.value is None
     assert lib.tsqr_batched_workspace_bytes(0, ctypes.cast(arr, ctypes.c_void_p)) == 0
     arr = (P * 2)(good, good)
     plan = ctypes.c_void_p()
     bad_t = tsqr.BatchTuning(1000, 2048, 64)  # rows not a multiple of 64
-    assert lib.tsqr_batched_create(0, 2, ctypes.cast(arr, ctypes.c_void_p), 16, 1 << 30, 16,
-                                   ctypes.byref(bad_t), ctypes.byref(plan)) == -7
+    assert lib.tsqr_batched_create(0, 0, 2, ctypes.cast(arr, ctypes.c_void_p), 16, 1 << 30, 16,
+                                   ctypes.byref(bad_t), ctypes.byref(plan)) == -8
+    assert lib.tsqr_batched_create(0, 3, 2, ctypes.cast(arr, ctypes.c_void_p), 16, 1 << 30, 16,
+                                   None, ctypes.byref(plan)) == -2  # precision
     assert lib.tsqr_batched_run(None, None) == -1
     assert lib.tsqr_batched_launches(None) == 0
 

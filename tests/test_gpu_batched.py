@@ -115,6 +115,32 @@ def test_batched_graph_replay_matches_eager():
         assert torch.all(b.info == 0)
 
 
+@pytest.mark.parametrize("prec", [tsqr.FP32, tsqr.BF16])
+def test_batched_lowp_sketch_meets_fp64_targets(prec):
+    """precision FP32/BF16: the sketch from rounded inputs, every later step FP64.  Every
+    problem still meets the FP64 targets and the unique R (oracle's, kappa bound), as long
+    as kappa u_p leaves A R0^-1 within CholeskyQR2's reach: all of the small batch for
+    FP32, the problems with kappa <= 1e4 for BF16."""
+    mats, ss, seeds = small_batch()
+    keep = [i for i in range(len(SMALL)) if prec == tsqr.FP32 or SMALL[i][3] <= 1e4]
+    As = [dev(mats[i]) for i in keep]
+    b = tsqr.Batch(As, [ss[i] for i in keep], [seeds[i] for i in keep], precision=prec)
+    b.run()
+    torch.cuda.synchronize()
+    assert torch.all(b.info == 0)
+    for j, i in enumerate(keep):
+        A = mats[i]
+        n, kappa = A.shape[1], SMALL[i][3]
+        Q, R = host(b.Q[j]), host(b.R[j])
+        ortho, res = oracle.orthogonality(Q), oracle.residual(A, Q, R)
+        ref = oracle.rxr_cholqr(A, ss[i], seeds[i])
+        rd = rel_fro(R, ref["R"])
+        print(f"prec={prec} problem {i} kappa={kappa:g}: ortho={ortho:.2e} res={res:.2e} "
+              f"relR={rd:.2e}")
+        assert ortho <= 1e-12 and res <= 1e-13
+        assert rd <= 100 * n * EPS * kappa + 1e-14
+
+
 def test_batched_breakdown_is_confined():
     mats, ss, seeds = small_batch()
     bad = 3
@@ -170,6 +196,17 @@ def test_batched_full_size_properties_and_samples():
         worst_o, worst_r = max(worst_o, o), max(worst_r, r)
     print(f"worst ortho {worst_o:.2e}, worst residual {worst_r:.2e}")
     assert worst_o <= 1e-12 and worst_r <= 1e-13
+    # the FP32 variant of the same batch (kappa <= 1e10: kappa u_32 <= 600)
+    b32 = tsqr.Batch(As, [d["s"] for d in descs], [d["sketch_seed"] for d in descs],
+                     precision=tsqr.FP32)
+    b32.run()
+    torch.cuda.synchronize()
+    assert torch.all(b32.info == 0)
+    w32 = max(gpu_orthogonality(b32.Q[i]) for i in range(len(descs)))
+    r32 = max(gpu_residual(As[i], b32.Q[i], b32.R[i]) for i in range(len(descs)))
+    print(f"fp32 variant: worst ortho {w32:.2e}, worst residual {r32:.2e}")
+    assert w32 <= 1e-12 and r32 <= 1e-13
+    del b32
     for n, i in sorted(samples.items()):
         d = descs[i]
         ref = oracle.rxr_cholqr(mats_kept[i], d["s"], d["sketch_seed"])
