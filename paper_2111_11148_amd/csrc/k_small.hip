@@ -1155,6 +1155,176 @@ static hipError_t launch_qr_blocked(int s, int n, const double* B, int64_t ldb, 
   return hipErrorInvalidValue;
 }
 
+// ------------------------------------------------------------------------------------
+// Blocked partial-pivot LU of the s x n sketch (s <= 2048), in place in Wk (ld s):
+//  (a) k_lu_panel: one workgroup factors columns j0 .. j0+nb-1 over rows j0 .. s-1 in LDS
+//      (pivot = first largest |w_ik|, as the unblocked kernels), records the pivots;
+//  (b) k_lu_trail: one thread per trailing column applies the panel's row swaps and forms
+//      U12 = L11^{-1} A12 by forward substitution with the unit lower L11;
+//  (c) k_lu_update: A22 -= L21 U12 (K = nb) over 16 x 16 output tiles staged in LDS.
+// Only U is needed (R0 = diag(sign u_kk) U), so the swaps are not applied to L's columns.
+// ------------------------------------------------------------------------------------
+template <int NB>
+__global__ __launch_bounds__(kSmallThreads) void k_lu_panel(int s, int n, int j0, double* Wk,
+                                                            int* __restrict__ piv) {
+  extern __shared__ double P[];  // (s - j0) x NB, ld = s - j0
+  __shared__ double cand_v[kSmallWaves];
+  __shared__ int cand_i[kSmallWaves];
+  __shared__ int p_sh;
+  const int nb = min(NB, n - j0), rows = s - j0, ldp = rows;
+  const int lane = lane_id(), wave = wave_id();
+  for (int e = threadIdx.x; e < rows * nb; e += kSmallThreads) {
+    const int c = e / rows, r = e - c * rows;
+    P[c * ldp + r] = Wk[(int64_t)(j0 + c) * s + j0 + r];
+  }
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    // pivot over local rows k .. rows-1 of column k
+    double bv = -1.0;
+    int bi = 0x7fffffff;
+    for (int r = k + threadIdx.x; r < rows; r += kSmallThreads) {
+      const double a = fabs(P[k * ldp + r]);
+      if (piv_better(a, r, bv, bi)) {
+        bv = a;
+        bi = r;
+      }
+    }
+    wave_argmax(bv, bi);
+    if (lane == 0) {
+      cand_v[wave] = bv;
+      cand_i[wave] = bi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double v = cand_v[0];
+      int i = cand_i[0];
+      for (int w = 1; w < kSmallWaves; ++w)
+        if (piv_better(cand_v[w], cand_i[w], v, i)) {
+          v = cand_v[w];
+          i = cand_i[w];
+        }
+      p_sh = i;
+      piv[j0 + k] = j0 + i;
+    }
+    __syncthreads();
+    const int p = p_sh;
+    // swap local rows k and p across the panel
+    if (p != k)
+      for (int c = threadIdx.x; c < nb; c += kSmallThreads) {
+        const double t = P[c * ldp + k];
+        P[c * ldp + k] = P[c * ldp + p];
+        P[c * ldp + p] = t;
+      }
+    __syncthreads();
+    const double pivot = P[k * ldp + k];
+    for (int r = k + 1 + threadIdx.x; r < rows; r += kSmallThreads) P[k * ldp + r] /= pivot;
+    __syncthreads();
+    // rank-1 update of the panel columns right of k
+    for (int c = k + 1; c < nb; ++c) {
+      const double ukc = P[c * ldp + k];
+      for (int r = k + 1 + threadIdx.x; r < rows; r += kSmallThreads)
+        P[c * ldp + r] -= P[k * ldp + r] * ukc;
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < rows * nb; e += kSmallThreads) {
+    const int c = e / rows, r = e - c * rows;
+    Wk[(int64_t)(j0 + c) * s + j0 + r] = P[c * ldp + r];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_lu_trail(int s, int n, int j0, int nb, double* Wk,
+                                                  const int* __restrict__ piv) {
+  const int c = j0 + nb + blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  double* col = Wk + (int64_t)c * s;
+  for (int j = j0; j < j0 + nb; ++j) {
+    const int p = piv[j];
+    if (p != j) {
+      const double t = col[j];
+      col[j] = col[p];
+      col[p] = t;
+    }
+  }
+  // forward substitution with the unit lower L11 (rows and columns j0 .. j0+nb-1)
+  for (int i = j0 + 1; i < j0 + nb; ++i) {
+    double acc = col[i];
+    for (int k = j0; k < i; ++k) acc -= Wk[(int64_t)k * s + i] * col[k];
+    col[i] = acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_lu_update(int s, int n, int j0, int nb, double* Wk) {
+  __shared__ double Ls[16][33], Us[32][17];
+  const int i0 = j0 + nb + 16 * blockIdx.y, c0 = j0 + nb + 16 * blockIdx.x;
+  const int ti = threadIdx.x % 16, tc = threadIdx.x / 16;
+  for (int e = threadIdx.x; e < 16 * nb; e += 256) {
+    const int r = e % 16, k = e / 16;
+    Ls[r][k] = (i0 + r < s) ? Wk[(int64_t)(j0 + k) * s + i0 + r] : 0.0;
+    const int kk = e % nb, cc = e / nb;
+    Us[kk][cc] = (c0 + cc < n) ? Wk[(int64_t)(c0 + cc) * s + j0 + kk] : 0.0;
+  }
+  __syncthreads();
+  const int i = i0 + ti, c = c0 + tc;
+  if (i < s && c < n) {
+    double acc = 0.0;
+    for (int k = 0; k < nb; ++k) acc += Ls[ti][k] * Us[k][tc];
+    Wk[(int64_t)c * s + i] -= acc;
+  }
+}
+
+// R = diag(sign u_kk) U from the factored Wk; a zero or NaN u_kk at the first such k sets
+// *info = 1000 + k + 1 (if it was 0) and R(k, k) = NaN.
+__global__ __launch_bounds__(256) void k_lu_finish(int s, int n, const double* __restrict__ Wk,
+                                                   double* __restrict__ R, int64_t ldr,
+                                                   int* __restrict__ info) {
+  const int c = blockIdx.x;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double v = 0.0;
+    if (i <= c) {
+      const double ui = Wk[(int64_t)i * s + i];
+      const double sg = (ui < 0.0) ? -1.0 : 1.0;
+      v = (i == c) ? fabs(ui) : sg * Wk[(int64_t)c * s + i];
+      if (i == c && !(ui != 0.0)) v = NAN;
+    }
+    R[(int64_t)c * ldr + i] = v;
+  }
+  if (c == 0 && threadIdx.x == 0 && info) {
+    int bad = 0;
+    for (int k = 0; k < n && !bad; ++k)
+      if (!(Wk[(int64_t)k * s + k] != 0.0)) bad = k + 1;
+    if (bad && *info == 0) *info = 1000 + bad;
+  }
+}
+
+template <int NB>
+static hipError_t lu_blocked_t(int s, int n, const double* B, int64_t ldb, double* R,
+                               int64_t ldr, int* info, double* scratch, hipStream_t st) {
+  double* Wk = scratch;
+  int* piv = reinterpret_cast<int*>(scratch + (size_t)s * n);
+  hipLaunchKernelGGL(k_copy_cols, dim3(n), dim3(256), 0, st, s, n, B, ldb, Wk);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  for (int j0 = 0; j0 < n; j0 += NB) {
+    const int nb = NB < n - j0 ? NB : n - j0;
+    hipLaunchKernelGGL(k_lu_panel<NB>, dim3(1), dim3(kSmallThreads),
+                       (size_t)(s - j0) * NB * sizeof(double), st, s, n, j0, Wk, piv);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int t = n - j0 - nb;
+    if (t > 0) {
+      hipLaunchKernelGGL(k_lu_trail, dim3((t + 255) / 256), dim3(256), 0, st, s, n, j0, nb, Wk,
+                         piv);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      const int rows = s - j0 - nb;
+      hipLaunchKernelGGL(k_lu_update, dim3((t + 15) / 16, (rows + 15) / 16), dim3(256), 0, st, s,
+                         n, j0, nb, Wk);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  hipLaunchKernelGGL(k_lu_finish, dim3(n), dim3(256), 0, st, s, n, Wk, R, ldr, info);
+  return hipGetLastError();
+}
+
 hipError_t launch_sketch_factor(int variant, int s, int n, const double* B, int64_t ldb,
                                 double* R, int64_t ldr, int* info, double* scratch,
                                 hipStream_t st) {
@@ -1177,6 +1347,9 @@ hipError_t launch_sketch_factor(int variant, int s, int n, const double* B, int6
 #undef TSQR_FAC
   if (s > kMaxS) return hipErrorInvalidValue;
   if (variant == 0 && s <= 2048) return launch_qr_blocked(s, n, B, ldb, R, ldr, info, scratch, st);
+  if (variant == 1 && s <= 512) return lu_blocked_t<32>(s, n, B, ldb, R, ldr, info, scratch, st);
+  if (variant == 1 && s <= 1024) return lu_blocked_t<16>(s, n, B, ldb, R, ldr, info, scratch, st);
+  if (variant == 1 && s <= 2048) return lu_blocked_t<8>(s, n, B, ldb, R, ldr, info, scratch, st);
   if (variant == 1) {
     const size_t sh = (size_t)(2 * s + n) * sizeof(double) + 2 * sizeof(int);
     hipLaunchKernelGGL(k_getrf_glb, grid, block, sh, st, s, n, B, ldb, R, ldr, info, scratch);
