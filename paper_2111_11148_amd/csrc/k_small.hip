@@ -82,15 +82,14 @@ __device__ __forceinline__ void geqrf_reg_body(int s, int n,
     if (wave == k % kSmallWaves) {
       double x[RPL];
       col_select(col, k / kSmallWaves, x);
-      double part = 0.0, xk = 0.0;
+      double part = 0.0;
 #pragma unroll
       for (int r = 0; r < RPL; ++r) {
         const int i = lane + 64 * r;
-        if (i > k && i < s) part += x[r] * x[r];
-        if (i == k) xk = x[r];
+        part += (i > k && i < s) ? x[r] * x[r] : 0.0;
       }
       const double xnorm2 = wave_sum(part);
-      const double alpha = wave_sum(xk);
+      const double alpha = col_elem(x, k);
       double beta, tau, scal;
       house(alpha, xnorm2, beta, tau, scal);
 #pragma unroll
@@ -280,6 +279,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_qr_panel(int s, int n, int j0
   const int lane = lane_id(), wave = wave_id();
   copy_to_lds(Wk + (int64_t)j0 * s + j0, s, p, w, P, ldp);
   __syncthreads();
+  // Row loops are branch-free so that a lane's eight LDS loads are in flight together: a
+  // row past the panel reads and writes the padding entry (row p) of its column, which
+  // never enters a sum.
   // reflector of column k from rows k.. of its (updated) column: v = (1, x2 scal)
   auto reflector = [&](int k) {
     double* x = P + k * ldp;
@@ -288,7 +290,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_qr_panel(int s, int n, int j0
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         const int i = k + 1 + lane + kWave * (r0 + r);
-        if (i < p) part += x[i] * x[i];
+        const double v = x[i < p ? i : p];
+        part += (i < p) ? v * v : 0.0;
       }
     }
     const double xnorm2 = wave_sum(part);
@@ -296,10 +299,16 @@ __global__ __launch_bounds__(kSmallThreads) void k_qr_panel(int s, int n, int j0
     double beta, tk, scal;
     house(alpha, xnorm2, beta, tk, scal);
     for (int r0 = 0; r0 < PR; r0 += 8) {
+      double v[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         const int i = k + 1 + lane + kWave * (r0 + r);
-        if (i < p) x[i] *= scal;
+        v[r] = x[i < p ? i : p];
+      }
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int i = k + 1 + lane + kWave * (r0 + r);
+        x[i < p ? i : p] = v[r] * scal;
       }
     }
     if (lane == 0) {
@@ -322,15 +331,25 @@ __global__ __launch_bounds__(kSmallThreads) void k_qr_panel(int s, int n, int j0
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
           const int i = k + lane + kWave * (r0 + r);
-          if (i < p) d += x[i] * y[i];
+          const int ii = i < p ? i : p;
+          const double xv = x[ii], yv = y[ii];
+          d += (i < p) ? xv * yv : 0.0;
         }
       }
       const double wv = wave_sum(d) * tk;
       for (int r0 = 0; r0 < PR; r0 += 8) {
+        double xv[8], yv[8];
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
           const int i = k + lane + kWave * (r0 + r);
-          if (i < p) y[i] -= x[i] * wv;
+          const int ii = i < p ? i : p;
+          xv[r] = x[ii];
+          yv[r] = y[ii];
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const int i = k + lane + kWave * (r0 + r);
+          y[i < p ? i : p] = yv[r] - xv[r] * wv;
         }
       }
     };
@@ -353,7 +372,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_qr_panel(int s, int n, int j0
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         const int i = k + lane + kWave * (r0 + r);
-        if (i < p) d += P[j * ldp + i] * P[k * ldp + i];
+        const int ii = i < p ? i : p;
+        const double a = P[j * ldp + ii], b = P[k * ldp + ii];
+        d += (i < p) ? a * b : 0.0;
       }
     }
     d = wave_sum(d);
@@ -402,46 +423,59 @@ __global__ __launch_bounds__(512) void k_qr_update(int s, int n, int j0, int w, 
   const int lane = lane_id(), wave = wave_id();
   const int c0 = j0 + w + (int)blockIdx.x * cpb;
   const int c1 = min(n, c0 + cpb);
-  for (int c = c0 + wave; c < c1; c += (int)blockDim.x / kWave) {
-    double* y = Wk + (int64_t)c * s + j0;
-    double yl[RPL];
+  // The update runs only for a full panel (w == NB; a narrower panel is the last one).
+  // Branch-free row loops (a lane's loads are all in flight together): a row past the
+  // panel reads row 0, a valid address, and enters no sum; only its store is skipped.
+  // One column per wavefront (cpb is the number of wavefronts), its RPL rows per lane in
+  // registers; rolled loops over the panel's reflectors keep one row of V per lane in
+  // flight.  Row loops are branch-free: a row past the panel reads row 0, a valid
+  // address, and enters no sum; only its store is skipped.
+  __shared__ double ds_[8][NB];  // d = V^T y, then e = T^T d, per wavefront
+  const int c = c0 + wave;
+  if (c >= c1) return;
+  double* y = Wk + (int64_t)c * s + j0;
+  double yv[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int i = lane + kWave * r;
+    const double v = y[i < p ? i : 0];
+    yv[r] = (i < p) ? v : 0.0;
+  }
+  double* dw = ds_[wave];
+#pragma unroll 1
+  for (int k = 0; k < NB; ++k) {
+    const lds_f64* vk = (const lds_f64*)Vs + k * p;
+    double part = 0.0;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
       const int i = lane + kWave * r;
-      yl[r] = (i < p) ? y[i] : 0.0;
+      part += (i < p) ? vk[i < p ? i : 0] * yv[r] : 0.0;
     }
-    double d[NB];
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      double part = 0.0;
-      if (k < w)
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-          const int i = lane + kWave * r;
-          if (i < p) part += Vs[k * p + i] * yl[r];
-        }
-      d[k] = wave_sum(part);
-    }
-    // e = T^T d  (T upper: e_k = sum_{j <= k} T_jk d_j)
-    double e[NB];
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      double acc = 0.0;
-#pragma unroll
-      for (int j = 0; j <= k; ++j) acc += Ts[j * NB + k] * d[j];
-      e[k] = acc;
-    }
+    part = wave_sum(part);
+    if (lane == 0) dw[k] = part;
+  }
+  __builtin_amdgcn_wave_barrier();
+  // e = T^T d (T upper: e_k = sum_{j <= k} T_jk d_j), entry k computed by lane k
+  double el = 0.0;
+  if (lane < NB)
+    for (int j = 0; j <= lane; ++j) el += Ts[j * NB + lane] * dw[j];
+  __builtin_amdgcn_wave_barrier();
+  if (lane < NB) dw[lane] = el;
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
+  for (int k = 0; k < NB; ++k) {
+    const lds_f64* vk = (const lds_f64*)Vs + k * p;
+    const double ek = dw[k];
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
       const int i = lane + kWave * r;
-      if (i < p) {
-        double v = yl[r];
-#pragma unroll
-        for (int k = 0; k < NB; ++k)
-          if (k < w) v -= Vs[k * p + i] * e[k];
-        y[i] = v;
-      }
+      yv[r] -= vk[i < p ? i : 0] * ek;
     }
+  }
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int i = lane + kWave * r;
+    if (i < p) y[i] = yv[r];
   }
 }
 
@@ -486,16 +520,38 @@ __device__ __forceinline__ bool piv_better(double a, int ia, double b, int ib) {
   return ia < ib;
 }
 
+// The preferred (value, index) pair of the wavefront, in every lane.  piv_better is a total
+// order on pairs with distinct indices, so the result does not depend on the order of the
+// combinations: DPP within rows of 16 lanes (as in wave_sum), then the four row winners
+// read into scalars.  All lanes must be active.
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp_step(double& v, int& idx) {
+  const double ov = dpp_f64<CTRL>(v);
+  const int oi = __builtin_amdgcn_update_dpp(0, idx, CTRL, 0xF, 0xF, false);
+  if (piv_better(ov, oi, v, idx)) {
+    v = ov;
+    idx = oi;
+  }
+}
+
 __device__ __forceinline__ void wave_argmax(double& v, int& idx) {
+  argmax_dpp_step<0xB1>(v, idx);   // quad_perm [1,0,3,2]
+  argmax_dpp_step<0x4E>(v, idx);   // quad_perm [2,3,0,1]
+  argmax_dpp_step<0x124>(v, idx);  // row_ror:4
+  argmax_dpp_step<0x128>(v, idx);  // row_ror:8
+  double bv = readlane_f64(v, 0);
+  int bi = __builtin_amdgcn_readlane(idx, 0);
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const double ov = __shfl_xor(v, off, kWave);
-    const int oi = __shfl_xor(idx, off, kWave);
-    if (piv_better(ov, oi, v, idx)) {
-      v = ov;
-      idx = oi;
+  for (int row = 1; row < 4; ++row) {
+    const double rv = readlane_f64(v, 16 * row);
+    const int ri = __builtin_amdgcn_readlane(idx, 16 * row);
+    if (piv_better(rv, ri, bv, bi)) {
+      bv = rv;
+      bi = ri;
     }
   }
+  v = bv;
+  idx = bi;
 }
 
 template <int RPL, int CPW>
@@ -767,217 +823,142 @@ __global__ __launch_bounds__(kSmallThreads) void k_potrf_reg(int n, const double
   potrf_reg_body<RPL, CPW>(n, W, ldw, R, ldr, stage, info, shift);
 }
 
-__global__ __launch_bounds__(kSmallThreads) void k_potrf_glb(int n, const double* __restrict__ W,
-                                                             int64_t ldw, double* __restrict__ R,
-                                                             int64_t ldr, int stage,
-                                                             int* __restrict__ info,
-                                                             double* __restrict__ Wk,
-                                                             double shift) {
-  extern __shared__ double sm[];
-  double* rk0 = sm;
-  double* rk1 = sm + n;
-  __shared__ int fail_sh;
-  const int lane = lane_id(), wave = wave_id();
-  for (int c = wave; c < n; c += kSmallWaves)
-    for (int i = lane; i < n; i += 64)
-      Wk[(int64_t)c * n + i] =
-          ((i <= c) ? W[(int64_t)c * ldw + i] : W[(int64_t)i * ldw + c]) + (i == c ? shift : 0.0);
-  if (threadIdx.x == 0) fail_sh = -1;
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    double* rk = (k & 1) ? rk1 : rk0;
-    if (wave == k % kSmallWaves) {
-      const double* x = Wk + (int64_t)k * n;
-      const double d = x[k];
-      double rkk;
-      if (!(d > 0.0)) {
-        rkk = NAN;
-        if (lane == 0 && fail_sh < 0) fail_sh = k;
-      } else {
-        rkk = sqrt(d);
-      }
-      for (int i = lane; i < n; i += 64) {
-        const double v = (i > k) ? x[i] / rkk : (i == k ? rkk : 0.0);
-        rk[i] = v;
-        R[(int64_t)i * ldr + k] = v;
-      }
-    }
-    __syncthreads();
-    for (int c = wave; c < n; c += kSmallWaves) {
-      if (c <= k) continue;
-      double* y = Wk + (int64_t)c * n;
-      const double rkc = rk[c];
-      for (int i = k + 1 + lane; i < n; i += 64) y[i] -= rk[i] * rkc;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0 && info && fail_sh >= 0 && *info == 0) *info = 1000 * stage + fail_sh + 1;
-}
-
-// Blocked Cholesky in one workgroup, in place in R (ld ldr): the upper triangle of W (plus
-// `shift` on the diagonal) is copied to R, then for each panel of NB columns
+// ------------------------------------------------------------------------------------
+// Blocked Cholesky (n > 64), in place in R: k_chol_init copies the upper triangle of W
+// (plus `shift` on the diagonal) to R with zeros below; then for each panel of NB columns
 //  (a) one wavefront factors the NB x NB diagonal block: lane c keeps column c in
 //      registers, and row k of the factor is published in LDS (one wavefront: no barrier);
-//  (b) the panel row R12 = R11^{-T} W12 by forward substitution, one thread per column;
-//  (c) the trailing update W22 -= R12^T R12 on FP64 MFMA (upper 16x16 tiles, round-robin
-//      over the wavefronts; operand layout as in the Gram kernel), read-modify-write in R.
-// Three barriers per panel instead of one per column.  LDS: potrf_blk_lds_doubles(n).
-// LDSM: the whole matrix is factored in LDS (ld n + 1) and copied to R at the end, so the
-// three phases never wait on global memory (for n up to 128 with NB = 16).
-template <int NB, bool LDSM = false>
-__host__ __device__ constexpr size_t potrf_blk_lds_doubles(int n) {
-  return (size_t)NB * (NB + 1) + (size_t)NB * (n + 1) + (LDSM ? (size_t)n * (n + 1) : 0);
+//  (b) the panel row R12 = R11^{-T} W12 by forward substitution, one thread per column
+//      ((a) and (b) are one workgroup, k_chol_panel);
+//  (c) the trailing update W22 -= R12^T R12 on FP64 MFMA over the trailing upper 16 x 16
+//      tiles, one wavefront per tile (k_chol_trail).
+// The panels are ordered on the stream.  A pivot that is not positive (or NaN) becomes a
+// NaN diagonal entry, which then fills the rest of the factor.
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_chol_init(int n, const double* __restrict__ W,
+                                                   int64_t ldw, double* __restrict__ R,
+                                                   int64_t ldr, double shift) {
+  const int c = blockIdx.x;
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    R[(int64_t)c * ldr + i] = (i <= c) ? W[(int64_t)c * ldw + i] + (i == c ? shift : 0.0) : 0.0;
 }
 
-constexpr int kTiles = 4;  // trailing tiles a wavefront updates together
+constexpr int kCholPanelThreads = 256;
 
-template <int NB, bool LDSM>
-__global__ __launch_bounds__(kSmallThreads) void k_potrf_blk(int n, const double* __restrict__ W,
-                                                             int64_t ldw, double* Rg, int64_t ldrg,
-                                                             int stage, int* __restrict__ info,
-                                                             double shift) {
-  extern __shared__ double sm[];
+template <int NB>
+__global__ __launch_bounds__(kCholPanelThreads) void k_chol_panel(int n, double* R, int64_t ldr,
+                                                              int j0, int stage,
+                                                              int* __restrict__ info) {
   constexpr int LDD = NB + 1;
-  double* D = sm;                  // D[k * LDD + c] = R11(k, c)
-  double* Pn = sm + NB * LDD;      // Pn[k * ldpn + c] = R12(k, c), zero-padded rows/cols
-  const int ldpn = n + 1;
-  // the matrix being factored: LDS (ld n + 1) or R itself
-  double* const R = LDSM ? sm + NB * LDD + NB * ldpn : Rg;
-  const int64_t ldr = LDSM ? (int64_t)(n + 1) : ldrg;
+  __shared__ double D[NB * LDD];  // D[k * LDD + c] = R11(k, c)
   __shared__ int fail_sh;
   const int lane = lane_id(), wave = wave_id();
-  const int q = lane >> 4, c16 = lane & 15;
-  {
-    // upper triangle of W (+ shift) into R, zeros below; eight loads in flight per thread
-    const int total = n * n;
-    for (int e0 = threadIdx.x; e0 < total; e0 += 8 * kSmallThreads) {
-      double v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * kSmallThreads;
-        const int c = e / n, i = e - c * n;
-        v[u] = (e < total && i <= c) ? W[(int64_t)c * ldw + i] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * kSmallThreads;
-        const int c = e / n, i = e - c * n;
-        if (e < total) R[(int64_t)c * ldr + i] = v[u] + (i == c ? shift : 0.0);
-      }
-    }
-  }
+  const int b = min(NB, n - j0), t = n - j0 - b;
   if (threadIdx.x == 0) fail_sh = -1;
   __syncthreads();
-
-  for (int j0 = 0; j0 < n; j0 += NB) {
-    const int b = min(NB, n - j0), t = n - j0 - b;
-    // (a) diagonal block
-    if (wave == 0) {
-      const int c = lane;
-      const bool cok = c < b;
-      double col[NB];
+  if (wave == 0) {
+    const int c = lane;
+    const bool cok = c < b;
+    double col[NB];
 #pragma unroll
-      for (int i = 0; i < NB; ++i)
-        col[i] = (cok && i <= c) ? R[(int64_t)(j0 + c) * ldr + j0 + i] : 0.0;
+    for (int i = 0; i < NB; ++i) col[i] = (cok && i <= c) ? R[(int64_t)(j0 + c) * ldr + j0 + i] : 0.0;
 #pragma unroll
-      for (int k = 0; k < NB; ++k) {
-        if (k < b) {
-          const double dkk = readlane_f64(col[k], k);
-          const bool ok = dkk > 0.0;
-          const double rkk = ok ? sqrt(dkk) : NAN;
-          if (!ok && lane == 0 && fail_sh < 0) fail_sh = j0 + k;
-          double rkc = 0.0;
-          if (c == k) rkc = rkk;
-          else if (c > k && cok) rkc = col[k] / rkk;
-          col[k] = rkc;
-          if (c < NB) D[k * LDD + c] = rkc;
-          __builtin_amdgcn_wave_barrier();  // row k is read below by every lane
+    for (int k = 0; k < NB; ++k) {
+      if (k < b) {
+        const double dkk = readlane_f64(col[k], k);
+        const bool ok = dkk > 0.0;
+        const double rkk = ok ? sqrt(dkk) : NAN;
+        if (!ok && lane == 0 && fail_sh < 0) fail_sh = j0 + k;
+        double rkc = 0.0;
+        if (c == k) rkc = rkk;
+        else if (c > k && cok) rkc = col[k] / rkk;
+        col[k] = rkc;
+        if (c < NB) D[k * LDD + c] = rkc;
+        __builtin_amdgcn_wave_barrier();  // row k is read below by every lane
 #pragma unroll
-          for (int i = k + 1; i < NB; ++i)
-            if (i <= c && cok) col[i] -= D[k * LDD + i] * rkc;
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < NB; ++i)
-        if (cok && i <= c) R[(int64_t)(j0 + c) * ldr + j0 + i] = col[i];
-    }
-    __syncthreads();
-    // (b) panel row R12 (rows j0 .. j0+b-1 of the trailing columns)
-    const int t16 = (t + 15) & ~15;
-    for (int tc = threadIdx.x; tc < t16; tc += kSmallThreads) {
-      if (tc < t) {
-        const int cg = j0 + b + tc;
-        double x[NB];
-#pragma unroll
-        for (int i = 0; i < NB; ++i) x[i] = (i < b) ? R[(int64_t)cg * ldr + j0 + i] : 0.0;
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-          if (i < b) {
-            double acc = x[i];
-#pragma unroll
-            for (int k = 0; k < i; ++k) acc -= D[k * LDD + i] * x[k];
-            x[i] = acc / D[i * LDD + i];
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-          if (i < b) R[(int64_t)cg * ldr + j0 + i] = x[i];
-          Pn[i * ldpn + tc] = (i < b) ? x[i] : 0.0;
-        }
-      } else {
-#pragma unroll
-        for (int i = 0; i < NB; ++i) Pn[i * ldpn + tc] = 0.0;
+        for (int i = k + 1; i < NB; ++i)
+          if (i <= c && cok) col[i] -= D[k * LDD + i] * rkc;
       }
     }
-    __syncthreads();
-    // (c) trailing update of the upper tiles: a wavefront's tiles (at most kTiles) are
-    // read first, updated on the matrix cores, then written, so their memory latencies
-    // overlap instead of adding up
-    const int tt = t16 / 16;
-    const int ntile = tt * (tt + 1) / 2;
-    for (int base = wave; base < ntile; base += kTiles * kSmallWaves) {
-      int ta[kTiles], tb[kTiles];
-      double old[kTiles][4];
 #pragma unroll
-      for (int u = 0; u < kTiles; ++u) {
-        const int tile = base + u * kSmallWaves;
-        int b2 = 0;
-        while ((b2 + 1) * (b2 + 2) / 2 <= tile) ++b2;
-        tb[u] = b2;
-        ta[u] = tile - b2 * (b2 + 1) / 2;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 16 * ta[u] + 4 * r + q, col = 16 * tb[u] + c16;
-          const bool ok = tile < ntile && row < t && col < t && row <= col;
-          old[u][r] = ok ? R[(int64_t)(j0 + b + col) * ldr + j0 + b + row] : 0.0;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kTiles; ++u) {
-        const int tile = base + u * kSmallWaves;
-        if (tile >= ntile) continue;
-        v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int kk = 0; kk < NB / 4; ++kk)
-          acc = mfma_f64(Pn[(4 * kk + q) * ldpn + 16 * ta[u] + c16],
-                         Pn[(4 * kk + q) * ldpn + 16 * tb[u] + c16], acc);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 16 * ta[u] + 4 * r + q, col = 16 * tb[u] + c16;
-          if (row < t && col < t && row <= col)
-            R[(int64_t)(j0 + b + col) * ldr + j0 + b + row] = old[u][r] - acc[r];
-        }
-      }
-    }
-    __syncthreads();
+    for (int i = 0; i < NB; ++i)
+      if (cok && i <= c) R[(int64_t)(j0 + c) * ldr + j0 + i] = col[i];
   }
-  if constexpr (LDSM) {
-    for (int e = threadIdx.x; e < n * n; e += kSmallThreads) {
-      const int c = e / n, i = e - c * n;
-      Rg[(int64_t)c * ldrg + i] = R[(int64_t)c * ldr + i];
+  __syncthreads();
+  for (int tc = threadIdx.x; tc < t; tc += kCholPanelThreads) {
+    const int cg = j0 + b + tc;  // b == NB whenever t > 0
+    // opaque per-column base: R11 would otherwise be hoisted out of the loop into registers
+    const lds_f64* Dp = (const lds_f64*)D;
+    asm volatile("" : "+v"(Dp));
+    double x[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) x[i] = R[(int64_t)cg * ldr + j0 + i];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      double acc = x[i];
+#pragma unroll
+      for (int k = 0; k < i; ++k) acc -= Dp[k * LDD + i] * x[k];
+      x[i] = acc / Dp[i * LDD + i];
     }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) R[(int64_t)cg * ldr + j0 + i] = x[i];
   }
   if (threadIdx.x == 0 && info && fail_sh >= 0 && *info == 0) *info = 1000 * stage + fail_sh + 1;
+}
+
+// W22 -= R12^T R12 on the upper 16 x 16 tiles of the trailing matrix: wavefront w of
+// workgroup (x, y) updates tile (ta, tb) = (4y + w, x) when ta <= tb.  Operands: lane
+// (q, c16) feeds R12(4kk + q, 16ta + c16) and R12(4kk + q, 16tb + c16); accumulator
+// register r is tile entry (4r + q, c16).
+template <int NB>
+__global__ __launch_bounds__(256) void k_chol_trail(int n, double* R, int64_t ldr, int j0) {
+  const int lane = lane_id(), wave = wave_id();
+  const int q = lane >> 4, c16 = lane & 15;
+  const int ta = 4 * blockIdx.y + wave, tb = blockIdx.x;
+  const int o = j0 + NB, t = n - o;
+  if (ta > tb || 16 * ta >= t) return;
+  const int ca = 16 * ta + c16, cb = 16 * tb + c16;
+  const double* pa = R + (int64_t)(o + (ca < t ? ca : 0)) * ldr + j0 + q;
+  const double* pb = R + (int64_t)(o + (cb < t ? cb : 0)) * ldr + j0 + q;
+  double av[NB / 4], bv[NB / 4], old[4];
+#pragma unroll
+  for (int kk = 0; kk < NB / 4; ++kk) {
+    av[kk] = ca < t ? pa[4 * kk] : 0.0;
+    bv[kk] = cb < t ? pb[4 * kk] : 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * ta + 4 * r + q;
+    old[r] = (row < t && cb < t && row <= cb) ? R[(int64_t)(o + cb) * ldr + o + row] : 0.0;
+  }
+  v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < NB / 4; ++kk) acc = mfma_f64(av[kk], bv[kk], acc);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * ta + 4 * r + q;
+    if (row < t && cb < t && row <= cb) R[(int64_t)(o + cb) * ldr + o + row] = old[r] - acc[r];
+  }
+}
+
+template <int NB>
+static hipError_t potrf_multi_t(int n, const double* W, int64_t ldw, double* R, int64_t ldr,
+                                int stage, int* info, hipStream_t st, double shift) {
+  hipLaunchKernelGGL(k_chol_init, dim3(n), dim3(256), 0, st, n, W, ldw, R, ldr, shift);
+  hipError_t e = hipGetLastError();
+  for (int j0 = 0; j0 < n && e == hipSuccess; j0 += NB) {
+    hipLaunchKernelGGL(k_chol_panel<NB>, dim3(1), dim3(kCholPanelThreads), 0, st, n, R, ldr, j0,
+                       stage, info);
+    e = hipGetLastError();
+    const int t = n - j0 - NB;
+    if (t > 0 && e == hipSuccess) {
+      const int tt = (t + 15) / 16;
+      hipLaunchKernelGGL(k_chol_trail<NB>, dim3(tt, (tt + 3) / 4), dim3(256), 0, st, n, R, ldr,
+                         j0);
+      e = hipGetLastError();
+    }
+  }
+  return e;
 }
 
 // ============================================================ small products =========
@@ -1157,36 +1138,50 @@ static hipError_t launch_qr_blocked(int s, int n, const double* B, int64_t ldb, 
 
 // ------------------------------------------------------------------------------------
 // Blocked partial-pivot LU of the s x n sketch (s <= 2048), in place in Wk (ld s):
-//  (a) k_lu_panel: one workgroup factors columns j0 .. j0+nb-1 over rows j0 .. s-1 in LDS
-//      (pivot = first largest |w_ik|, as the unblocked kernels), records the pivots;
-//  (b) k_lu_trail: one thread per trailing column applies the panel's row swaps and forms
-//      U12 = L11^{-1} A12 by forward substitution with the unit lower L11;
+//  (a) k_lu_panel: one workgroup factors columns j0 .. j0+nb-1 over rows j0 .. s-1, each
+//      thread holding PR rows of the panel in registers (pivot = first largest |w_ik|, as
+//      the unblocked kernels; two barriers per column), and records the pivots;
+//  (b) k_lu_trail: one wavefront per trailing column applies the panel's row swaps in
+//      order (lane j holds row j0 + j, and tracks the row its swap reaches below the
+//      panel) and forms U12 = L11^{-1} A12 with the unit lower L11;
 //  (c) k_lu_update: A22 -= L21 U12 (K = nb) over 16 x 16 output tiles staged in LDS.
 // Only U is needed (R0 = diag(sign u_kk) U), so the swaps are not applied to L's columns.
 // ------------------------------------------------------------------------------------
-template <int NB>
-__global__ __launch_bounds__(kSmallThreads) void k_lu_panel(int s, int n, int j0, double* Wk,
-                                                            int* __restrict__ piv) {
-  extern __shared__ double P[];  // (s - j0) x NB, ld = s - j0
-  __shared__ double cand_v[kSmallWaves];
-  __shared__ int cand_i[kSmallWaves];
-  __shared__ int p_sh;
-  const int nb = min(NB, n - j0), rows = s - j0, ldp = rows;
-  const int lane = lane_id(), wave = wave_id();
-  for (int e = threadIdx.x; e < rows * nb; e += kSmallThreads) {
-    const int c = e / rows, r = e - c * rows;
-    P[c * ldp + r] = Wk[(int64_t)(j0 + c) * s + j0 + r];
+constexpr int kLuPanelThreads = 512;
+constexpr int kLuPanelWaves = kLuPanelThreads / kWave;
+
+template <int NB, int PR>  // panel rows s - j0 <= PR * kLuPanelThreads
+__global__ __launch_bounds__(kLuPanelThreads) void k_lu_panel(int s, int n, int j0, double* Wk,
+                                                              int* __restrict__ piv) {
+  __shared__ double cand_v[kLuPanelWaves];
+  __shared__ int cand_i[kLuPanelWaves];
+  __shared__ double rowp[NB], rowk[NB];
+  const int nb = min(NB, n - j0), rows = s - j0;
+  const int t = (int)threadIdx.x, lane = lane_id(), wave = wave_id();
+  double a[PR][NB];
+#pragma unroll
+  for (int u = 0; u < PR; ++u) {
+    const int row = t + kLuPanelThreads * u;
+    const bool rok = row < rows;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const bool ok = rok && c < nb;
+      const double v = Wk[(int64_t)(j0 + (c < nb ? c : 0)) * s + j0 + (rok ? row : 0)];
+      a[u][c] = ok ? v : 0.0;
+    }
   }
-  __syncthreads();
-  for (int k = 0; k < nb; ++k) {
-    // pivot over local rows k .. rows-1 of column k
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    if (k < nb) {  // uniform (a guard, not a break: the panel stays in registers)
     double bv = -1.0;
     int bi = 0x7fffffff;
-    for (int r = k + threadIdx.x; r < rows; r += kSmallThreads) {
-      const double a = fabs(P[k * ldp + r]);
-      if (piv_better(a, r, bv, bi)) {
-        bv = a;
-        bi = r;
+#pragma unroll
+    for (int u = 0; u < PR; ++u) {
+      const int row = t + kLuPanelThreads * u;
+      const double av = fabs(a[u][k]);
+      if (row >= k && row < rows && piv_better(av, row, bv, bi)) {
+        bv = av;
+        bi = row;
       }
     }
     wave_argmax(bv, bi);
@@ -1195,63 +1190,98 @@ __global__ __launch_bounds__(kSmallThreads) void k_lu_panel(int s, int n, int j0
       cand_i[wave] = bi;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      double v = cand_v[0];
-      int i = cand_i[0];
-      for (int w = 1; w < kSmallWaves; ++w)
-        if (piv_better(cand_v[w], cand_i[w], v, i)) {
-          v = cand_v[w];
-          i = cand_i[w];
-        }
-      p_sh = i;
-      piv[j0 + k] = j0 + i;
-    }
-    __syncthreads();
-    const int p = p_sh;
-    // swap local rows k and p across the panel
-    if (p != k)
-      for (int c = threadIdx.x; c < nb; c += kSmallThreads) {
-        const double t = P[c * ldp + k];
-        P[c * ldp + k] = P[c * ldp + p];
-        P[c * ldp + p] = t;
+    // every thread combines the candidates (a total order: the same p everywhere)
+    double pv = cand_v[0];
+    int p = cand_i[0];
+#pragma unroll
+    for (int w = 1; w < kLuPanelWaves; ++w) {
+      const double cv = cand_v[w];
+      const int ci = cand_i[w];
+      if (piv_better(cv, ci, pv, p)) {
+        pv = cv;
+        p = ci;
       }
-    __syncthreads();
-    const double pivot = P[k * ldp + k];
-    for (int r = k + 1 + threadIdx.x; r < rows; r += kSmallThreads) P[k * ldp + r] /= pivot;
-    __syncthreads();
-    // rank-1 update of the panel columns right of k
-    for (int c = k + 1; c < nb; ++c) {
-      const double ukc = P[c * ldp + k];
-      for (int r = k + 1 + threadIdx.x; r < rows; r += kSmallThreads)
-        P[c * ldp + r] -= P[k * ldp + r] * ukc;
+    }
+    // publish rows p and k (before the swap)
+#pragma unroll
+    for (int u = 0; u < PR; ++u) {
+      const int row = t + kLuPanelThreads * u;
+      if (row == p)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) rowp[c] = a[u][c];
+      if (row == k)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) rowk[c] = a[u][c];
     }
     __syncthreads();
+    const double pivot = rowp[k];
+#pragma unroll
+    for (int u = 0; u < PR; ++u) {
+      const int row = t + kLuPanelThreads * u;
+      const bool isk = row == k, isp = row == p && p != k, below = row > k && row < rows;
+      double x[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) x[c] = isk ? rowp[c] : (isp ? rowk[c] : a[u][c]);
+      const double l = x[k] / pivot;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        if (c == k) a[u][c] = below ? l : x[c];
+        else if (c > k) a[u][c] = below ? x[c] - l * rowp[c] : x[c];
+        else a[u][c] = x[c];
+      }
+    }
+    if (t == 0) piv[j0 + k] = j0 + p;
+    }
   }
-  for (int e = threadIdx.x; e < rows * nb; e += kSmallThreads) {
-    const int c = e / rows, r = e - c * rows;
-    Wk[(int64_t)(j0 + c) * s + j0 + r] = P[c * ldp + r];
+#pragma unroll
+  for (int u = 0; u < PR; ++u) {
+    const int row = t + kLuPanelThreads * u;
+    if (row < rows)
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c < nb) Wk[(int64_t)(j0 + c) * s + j0 + row] = a[u][c];
   }
 }
 
+template <int NB>
 __global__ __launch_bounds__(256) void k_lu_trail(int s, int n, int j0, int nb, double* Wk,
                                                   const int* __restrict__ piv) {
-  const int c = j0 + nb + blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = lane_id(), wave = wave_id();
+  const int c = j0 + nb + 4 * (int)blockIdx.x + wave;
   if (c >= n) return;
   double* col = Wk + (int64_t)c * s;
-  for (int j = j0; j < j0 + nb; ++j) {
-    const int p = piv[j];
-    if (p != j) {
-      const double t = col[j];
-      col[j] = col[p];
-      col[p] = t;
+  const bool in = lane < nb;
+  const int pj = in ? piv[j0 + lane] : j0;  // lane j: the row swapped with row j0 + j
+  const bool below = in && pj >= j0 + nb;
+  double x = col[j0 + (in ? lane : 0)];
+  double xb = col[below ? pj : j0];          // lane j: the current value of row pj
+  // L11 row of this lane (columns l < lane), loaded while the swaps run
+  double lrow[NB];
+#pragma unroll
+  for (int l = 0; l < NB; ++l) lrow[l] = Wk[(int64_t)(j0 + (l < nb ? l : 0)) * s + j0 + (in ? lane : 0)];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int p = __builtin_amdgcn_readlane(pj, j);
+    if (j < nb && p != j0 + j) {
+      const double xj = readlane_f64(x, j);
+      if (p < j0 + nb) {
+        const double xp = readlane_f64(x, p - j0);
+        x = (lane == j) ? xp : ((lane == p - j0) ? xj : x);
+      } else {
+        const double xp = readlane_f64(xb, j);  // lane j tracks row p
+        x = (lane == j) ? xp : x;
+        xb = (below && pj == p) ? xj : xb;
+      }
     }
   }
-  // forward substitution with the unit lower L11 (rows and columns j0 .. j0+nb-1)
-  for (int i = j0 + 1; i < j0 + nb; ++i) {
-    double acc = col[i];
-    for (int k = j0; k < i; ++k) acc -= Wk[(int64_t)k * s + i] * col[k];
-    col[i] = acc;
+  // forward substitution with the unit lower L11
+#pragma unroll
+  for (int l = 0; l < NB; ++l) {
+    const double xl = readlane_f64(x, l);
+    x -= (in && lane > l && l < nb) ? lrow[l] * xl : 0.0;
   }
+  if (in) col[j0 + lane] = x;
+  if (below) col[pj] = xb;
 }
 
 __global__ __launch_bounds__(256) void k_lu_update(int s, int n, int j0, int nb, double* Wk) {
@@ -1297,7 +1327,7 @@ __global__ __launch_bounds__(256) void k_lu_finish(int s, int n, const double* _
   }
 }
 
-template <int NB>
+template <int NB, int PR>
 static hipError_t lu_blocked_t(int s, int n, const double* B, int64_t ldb, double* R,
                                int64_t ldr, int* info, double* scratch, hipStream_t st) {
   double* Wk = scratch;
@@ -1307,12 +1337,12 @@ static hipError_t lu_blocked_t(int s, int n, const double* B, int64_t ldb, doubl
   if (e != hipSuccess) return e;
   for (int j0 = 0; j0 < n; j0 += NB) {
     const int nb = NB < n - j0 ? NB : n - j0;
-    hipLaunchKernelGGL(k_lu_panel<NB>, dim3(1), dim3(kSmallThreads),
-                       (size_t)(s - j0) * NB * sizeof(double), st, s, n, j0, Wk, piv);
+    hipLaunchKernelGGL((k_lu_panel<NB, PR>), dim3(1), dim3(kLuPanelThreads), 0, st, s, n, j0, Wk,
+                       piv);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int t = n - j0 - nb;
     if (t > 0) {
-      hipLaunchKernelGGL(k_lu_trail, dim3((t + 255) / 256), dim3(256), 0, st, s, n, j0, nb, Wk,
+      hipLaunchKernelGGL(k_lu_trail<NB>, dim3((t + 3) / 4), dim3(256), 0, st, s, n, j0, nb, Wk,
                          piv);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       const int rows = s - j0 - nb;
@@ -1347,9 +1377,10 @@ hipError_t launch_sketch_factor(int variant, int s, int n, const double* B, int6
 #undef TSQR_FAC
   if (s > kMaxS) return hipErrorInvalidValue;
   if (variant == 0 && s <= 2048) return launch_qr_blocked(s, n, B, ldb, R, ldr, info, scratch, st);
-  if (variant == 1 && s <= 512) return lu_blocked_t<32>(s, n, B, ldb, R, ldr, info, scratch, st);
-  if (variant == 1 && s <= 1024) return lu_blocked_t<16>(s, n, B, ldb, R, ldr, info, scratch, st);
-  if (variant == 1 && s <= 2048) return lu_blocked_t<8>(s, n, B, ldb, R, ldr, info, scratch, st);
+  // panel registers per thread: NB x PR <= 32 doubles
+  if (variant == 1 && s <= 512) return lu_blocked_t<16, 1>(s, n, B, ldb, R, ldr, info, scratch, st);
+  if (variant == 1 && s <= 1024) return lu_blocked_t<16, 2>(s, n, B, ldb, R, ldr, info, scratch, st);
+  if (variant == 1 && s <= 2048) return lu_blocked_t<8, 4>(s, n, B, ldb, R, ldr, info, scratch, st);
   if (variant == 1) {
     const size_t sh = (size_t)(2 * s + n) * sizeof(double) + 2 * sizeof(int);
     hipLaunchKernelGGL(k_getrf_glb, grid, block, sh, st, s, n, B, ldb, R, ldr, info, scratch);
@@ -1360,41 +1391,30 @@ hipError_t launch_sketch_factor(int variant, int s, int n, const double* B, int6
   return hipGetLastError();
 }
 
+#ifndef TSQR_POTRF_MULTI_MIN
+#define TSQR_POTRF_MULTI_MIN 64
+#define TSQR_POTRF_MULTI_NB 32
+#endif
+constexpr int kPotrfMultiMin = TSQR_POTRF_MULTI_MIN;  // larger n: one launch per phase
+constexpr int kPotrfMultiNB = TSQR_POTRF_MULTI_NB;
+
 hipError_t launch_potrf(int n, const double* W, int64_t ldw, double* R, int64_t ldr, int stage,
                         int* info, double* scratch, hipStream_t st, double shift) {
-  const int rpl = pow2_at_least((n + 63) / 64), cpw = pow2_at_least((n + 15) / 16);
+  (void)scratch;
+  if (n < 1 || n > kMaxS) return hipErrorInvalidValue;
+  if (n > kPotrfMultiMin)
+    return potrf_multi_t<kPotrfMultiNB>(n, W, ldw, R, ldr, stage, info, st, shift);
+  const int cpw = pow2_at_least((n + 15) / 16);  // n <= 64: one row of 64 lanes
   dim3 grid(1), block(kSmallThreads);
-#define TSQR_POTRF(RPL_, CPW_)                                                                 \
-  if (rpl == RPL_ && cpw == CPW_) {                                                            \
-    hipLaunchKernelGGL((k_potrf_reg<RPL_, CPW_>), grid, block, 0, st, n, W, ldw, R, ldr, stage, \
-                       info, shift);                                                           \
-    return hipGetLastError();                                                                  \
+#define TSQR_POTRF(CPW_)                                                                      \
+  if (cpw == CPW_) {                                                                          \
+    hipLaunchKernelGGL((k_potrf_reg<1, CPW_>), grid, block, 0, st, n, W, ldw, R, ldr, stage, \
+                       info, shift);                                                          \
+    return hipGetLastError();                                                                 \
   }
-  if (n > 64 && n <= 128) {  // the whole matrix in LDS
-    hipLaunchKernelGGL((k_potrf_blk<16, true>), grid, block,
-                       (potrf_blk_lds_doubles<16, true>(n)) * sizeof(double), st, n, W, ldw, R, ldr,
-                       stage, info, shift);
-    return hipGetLastError();
-  }
-  if (n > 128 && n <= 512) {
-    hipLaunchKernelGGL((k_potrf_blk<32, false>), grid, block,
-                       potrf_blk_lds_doubles<32>(n) * sizeof(double), st, n, W, ldw, R, ldr, stage,
-                       info, shift);
-    return hipGetLastError();
-  }
-  if (n > 512 && n <= 1024) {  // narrower panels keep the panel row in LDS
-    hipLaunchKernelGGL((k_potrf_blk<16, false>), grid, block,
-                       potrf_blk_lds_doubles<16>(n) * sizeof(double), st, n, W, ldw, R, ldr, stage,
-                       info, shift);
-    return hipGetLastError();
-  }
-  TSQR_POTRF(1, 1) TSQR_POTRF(1, 2) TSQR_POTRF(1, 4) TSQR_POTRF(2, 8)
+  TSQR_POTRF(1) TSQR_POTRF(2) TSQR_POTRF(4)
 #undef TSQR_POTRF
-  if (n > kMaxS) return hipErrorInvalidValue;
-  const size_t sh = (size_t)(2 * n) * sizeof(double);
-  hipLaunchKernelGGL(k_potrf_glb, grid, block, sh, st, n, W, ldw, R, ldr, stage, info, scratch,
-                     shift);
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_trmm_upper(int n, const double* A, int64_t lda, const double* B, int64_t ldb,

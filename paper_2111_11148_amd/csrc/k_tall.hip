@@ -37,8 +37,6 @@ __host__ __device__ constexpr int tri_b(int t) {
 __host__ __device__ constexpr int sigma16(int x) { return 4 * (x & 3) + (x >> 2); }
 __host__ __device__ constexpr int off_index(int a, int b) { return b * (b - 1) / 2 + a; }
 
-typedef __attribute__((address_space(3))) double lds_f64;
-
 // Prepared operand buffer, tiles of 256 doubles stored as tile[i*16 + sigma16(j)]:
 //   [0, NOFF)          off-diagonal tiles (a < b): -T(16a+i, 16b+j)
 //   [NOFF, NOFF+JT)    diagonal tiles: -T(16b+i, 16b+j) for i <= j, else 0
