@@ -277,7 +277,11 @@ def baselines_comparison(args, kappas):
     return {"workload": f"tall128 shape (m={m}, n={n}, s={s})", "results": out,
             "paper": "Section 4.3, 32 processes, n=100, m=1e5: CholeskyQR2 +24% and "
                      "sCholeskyQR3 +82% time over rQR-CholeskyQR (row extraction); "
-                     "CholeskyQR2 collapses beyond kappa 1e8"}
+                     "CholeskyQR2 collapses beyond kappa 1e8",
+            "note": "with m=2^20 the sCholeskyQR3 shift 11(mn+n(n+1))u||A||^2 bounds the "
+                    "first pass's cond(Q1) by about sqrt(shift/||A||^2) kappa, which stays "
+                    "below u^-1/2 (what its CholeskyQR2 needs) only up to kappa ~ 1e11; "
+                    "beyond that it may break down"}
 
 
 def batched_comparison(args):
@@ -383,7 +387,7 @@ def main() -> int:
                     help="condition numbers of the mixed-precision comparison (mixed256 "
                          "workload, m=2^20, n=256, s=512); empty to skip it")
     ap.add_argument("--mixed-steps", type=int, default=5)
-    ap.add_argument("--baseline-kappas", default="1e5,1e12",
+    ap.add_argument("--baseline-kappas", default="1e5,1e10,1e12",
                     help="condition numbers of the comparison with CholeskyQR2 / sCholeskyQR3 "
                          "and the row-extraction sketch (m=2^20, n=128); empty to skip it")
     ap.add_argument("--baseline-steps", type=int, default=5)

@@ -39,21 +39,30 @@ __global__ __launch_bounds__(256) void k_gemv_t(int64_t m, int n, const double* 
   }
 }
 
-// c(j) = sum over kb of part[kb][j], kb in increasing order.
+// c(j) = sum over kb of part[kb][j]: workgroup j, thread t sums kb = t, t + 256, ... in
+// increasing order, then the 256 sums are added in a fixed order (wave_sum within each
+// wavefront, the four wavefront sums in order).  Each thread's loads are independent, so
+// they are in flight together.
 __global__ __launch_bounds__(256) void k_gemv_reduce(int kblocks, int n,
                                                      const double* __restrict__ part,
                                                      double* __restrict__ c) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+  __shared__ double ws[4];
+  const int j = blockIdx.x, t = threadIdx.x, lane = lane_id(), wave = wave_id();
   double acc = 0.0;
-  for (int kb = 0; kb < kblocks; ++kb) acc += part[(size_t)kb * n + j];
-  c[j] = acc;
+  for (int kb = t; kb < kblocks; kb += 256) acc += part[(size_t)kb * n + j];
+  acc = wave_sum(acc);
+  if (lane == 0) ws[wave] = acc;
+  __syncthreads();
+  if (t == 0) c[j] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
 }
 
-// One wavefront, vectors in LDS: U^T z = c (z_i = (c_i - sum_{k<i} U(k,i) z_k) / U(i,i),
-// column i of U read contiguously, wave_sum for the dot product), U y = z and R0 x = y
-// (column-oriented back substitution: y_i = z_i / U(i,i), then z_k -= U(k,i) y_i for
-// k < i).  Skipped (x = NaN) when *info is set.
+// One wavefront, the vector in LDS (a single wavefront's LDS accesses are in order, so no
+// barrier is needed), the triangular factor's next column loaded while the current step
+// runs: U^T z = c (z_i = (c_i - sum_{k<i} U(k,i) z_k) / U(i,i), column i of U read
+// contiguously, wave_sum for the dot product), U y = z and R0 x = y (column-oriented back
+// substitution: y_i = z_i / U(i,i), then z_k -= U(k,i) y_i for k < i).  RL: rows per lane
+// (n <= 64 RL).  Skipped (x = NaN) when *info is set.
+template <int RL>
 __global__ __launch_bounds__(64) void k_lsq_solve(int n, const double* __restrict__ U,
                                                   int64_t ldu, const double* __restrict__ R0,
                                                   int64_t ldr, const double* __restrict__ c,
@@ -66,25 +75,53 @@ __global__ __launch_bounds__(64) void k_lsq_solve(int n, const double* __restric
     return;
   }
   for (int i = lane; i < n; i += kWave) v[i] = c[i];
-  __syncthreads();
+  __builtin_amdgcn_wave_barrier();
+  // column j of T, rows lane + 64 r (row 0 stands in past n: a valid address)
+  auto load_col = [&](const double* T, int64_t ldt, int j, double (&col)[RL]) {
+    const int jc = j < n ? j : n - 1;
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const int k = lane + kWave * r;
+      col[r] = T[(int64_t)jc * ldt + (k < n ? k : 0)];
+    }
+  };
+  double cur[RL], nxt[RL];
   // forward: U^T z = c, z overwrites v
+  load_col(U, ldu, 0, cur);
   for (int i = 0; i < n; ++i) {
+    load_col(U, ldu, i + 1, nxt);
+    const double uii = U[(int64_t)i * ldu + i];
     double acc = 0.0;
-    for (int k = lane; k < i; k += kWave) acc += U[(int64_t)i * ldu + k] * v[k];
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const int k = lane + kWave * r;
+      acc += (k < i) ? cur[r] * v[k < n ? k : 0] : 0.0;
+    }
     acc = wave_sum(acc);
-    if (lane == 0) v[i] = (v[i] - acc) / U[(int64_t)i * ldu + i];
-    __syncthreads();
+    if (lane == 0) v[i] = (v[i] - acc) / uii;
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < RL; ++r) cur[r] = nxt[r];
   }
   // back: U y = z, then R0 x = y, y and x overwrite v
   for (int pass = 0; pass < 2; ++pass) {
     const double* T = pass == 0 ? U : R0;
     const int64_t ldt = pass == 0 ? ldu : ldr;
+    load_col(T, ldt, n - 1, cur);
     for (int i = n - 1; i >= 0; --i) {
-      if (lane == 0) v[i] = v[i] / T[(int64_t)i * ldt + i];
-      __syncthreads();
-      const double yi = v[i];
-      for (int k = lane; k < i; k += kWave) v[k] -= T[(int64_t)i * ldt + k] * yi;
-      __syncthreads();
+      load_col(T, ldt, i > 0 ? i - 1 : 0, nxt);
+      const double tii = T[(int64_t)i * ldt + i];
+      const double yi = v[i] / tii;  // every lane reads v[i] and divides alike
+      __builtin_amdgcn_wave_barrier();
+      if (lane == 0) v[i] = yi;
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int k = lane + kWave * r;
+        if (k < i) v[k] -= cur[r] * yi;
+      }
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int r = 0; r < RL; ++r) cur[r] = nxt[r];
     }
   }
   for (int i = lane; i < n; i += kWave) x[i] = v[i];
@@ -104,7 +141,7 @@ hipError_t launch_gemv_t(int64_t m, int n, const double* X, int64_t ldx, const d
   hipLaunchKernelGGL(k_gemv_t, dim3(kblocks), dim3(256), 0, st, m, n, X, ldx, b, rpb, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_gemv_reduce, dim3((n + 255) / 256), dim3(256), 0, st, kblocks, n, part, c);
+  hipLaunchKernelGGL(k_gemv_reduce, dim3(n), dim3(256), 0, st, kblocks, n, part, c);
   return hipGetLastError();
 }
 
@@ -115,9 +152,16 @@ size_t gemv_part_doubles(int64_t m, int n) {
 
 hipError_t launch_lsq_solve(int n, const double* U, int64_t ldu, const double* R0, int64_t ldr,
                             const double* c, double* x, const int* info, hipStream_t st) {
-  hipLaunchKernelGGL(k_lsq_solve, dim3(1), dim3(kWave), (size_t)n * sizeof(double), st, n, U, ldu,
-                     R0, ldr, c, x, info);
-  return hipGetLastError();
+  const size_t sh = (size_t)n * sizeof(double);
+#define TSQR_LSQ(RL_)                                                                          \
+  if (n <= 64 * RL_) {                                                                         \
+    hipLaunchKernelGGL(k_lsq_solve<RL_>, dim3(1), dim3(kWave), sh, st, n, U, ldu, R0, ldr, c, x, \
+                       info);                                                                  \
+    return hipGetLastError();                                                                  \
+  }
+  TSQR_LSQ(1) TSQR_LSQ(2) TSQR_LSQ(4) TSQR_LSQ(8) TSQR_LSQ(16)
+#undef TSQR_LSQ
+  return hipErrorInvalidValue;
 }
 
 }  // namespace tsqr

@@ -374,7 +374,7 @@ int tsqr_batched_autotune(int variant, int precision, int64_t count,
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return TSQR_ERR_HIP;
   if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);  // best effort on the error path
     return TSQR_ERR_HIP;
   }
   // time of one run of the batch planned with `t` (warm-up run, then the mean of two)
@@ -416,9 +416,9 @@ int tsqr_batched_autotune(int variant, int precision, int64_t count,
         cur_ms = ms;
       }
     }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  const hipError_t d0 = hipEventDestroy(e0), d1 = hipEventDestroy(e1);
   if (rc) return rc;
+  if (d0 != hipSuccess || d1 != hipSuccess) return TSQR_ERR_HIP;
   *best = cur;
   if (best_ms) *best_ms = cur_ms;
   return TSQR_OK;

@@ -193,6 +193,23 @@ def test_potrf_parity(n):
     assert rel_fro(Rg, Ro) <= 20 * n * EPS * 900.0
 
 
+@pytest.mark.parametrize("n", [65, 128, 200, 333])
+@pytest.mark.parametrize("kappa_w", [1e10, 1e13])
+def test_potrf_ill_conditioned(n, kappa_w):
+    """The blocked Cholesky is backward stable at any conditioning it completes:
+    ||R^T R - W|| <= c n u ||W||, and R within c n u cond(W) of the oracle's factor."""
+    X = gen_matrix(4 * n + 10, n, math.sqrt(kappa_w), 7 + n)
+    W = np.asfortranarray(X.T @ X)
+    Rg, info = tsqr.potrf(dev(W), stage=2)
+    assert int(info.item()) == 0
+    Rg = host(Rg)
+    Ro, io = oracle.cholesky_upper(W)
+    assert io == 0
+    assert np.all(np.tril(Rg, -1) == 0) and np.all(np.diag(Rg) > 0)
+    assert np.linalg.norm(Rg.T @ Rg - W) <= 20 * n * EPS * np.linalg.norm(W)
+    assert rel_fro(Rg, Ro) <= 20 * n * EPS * kappa_w
+
+
 def test_potrf_breakdown_and_upper_only():
     W = np.eye(6)
     W[3, 3] = -1.0
