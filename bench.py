@@ -391,6 +391,8 @@ def main() -> int:
                     help="condition numbers of the comparison with CholeskyQR2 / sCholeskyQR3 "
                          "and the row-extraction sketch (m=2^20, n=128); empty to skip it")
     ap.add_argument("--baseline-steps", type=int, default=5)
+    ap.add_argument("--graph", type=int, default=1,
+                    help="also time the step captured into one HIP graph (0 to skip)")
     ap.add_argument("--batch-count", type=int, default=512,
                     help="problems of the batched workload (0 to skip it)")
     ap.add_argument("--batch-steps", type=int, default=10)
@@ -453,6 +455,39 @@ def main() -> int:
 
     binfo = int(info.item())
     ortho, res = gpu_metrics(A, Q, R)
+
+    # the same step captured into one HIP graph on a side stream and replayed (no phase
+    # events); every replay must reproduce the eager Q and R bit for bit
+    graph = None
+    if args.graph:
+        Qe, Re = Q.clone(), R.clone()
+        st = torch.cuda.Stream()
+
+        def step_on(stream):
+            tsqr.rxr_cholqr(A, s, seed, variant=variant, extra_pass=extra_pass, Q=Q, R=R,
+                            workspace=work, info=info, stream=stream)
+
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            step_on(st)
+        torch.cuda.current_stream().wait_stream(st)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=st):
+            step_on(st)
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.replay()
+        torch.cuda.synchronize()
+        g_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        same = bool(torch.equal(Q, Qe) and torch.equal(R, Re)) and int(info.item()) == 0
+        graph = {"ms_per_step": round(g_ms, 4), "same_q_r_as_eager": same}
+        print(f"# graph replay: {g_ms:.3f} ms/step (bitwise equal to eager: {same})",
+              file=sys.stderr, flush=True)
+        del Qe, Re, g
 
     # per-phase average durations (ms per launch) from the events of the timed steps
     phase_tot, phase_cnt = {}, {}
@@ -551,6 +586,8 @@ def main() -> int:
         "residual": res,
         "info": binfo,
         "phases_ms": {k: round(v, 4) for k, v in per_step.items()},
+        "graph": None if graph is None else dict(
+            graph, gflops=round(F["total"] / (graph["ms_per_step"] * 1e-3) / 1e9, 3)),
         "mixed_vs_fp64": mixed,
         "baselines": baselines,
         "batched": batched,
