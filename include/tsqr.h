@@ -340,7 +340,8 @@ int tsqr_gram(int64_t m, int64_t n, const double* X, int64_t ldx, double* W, int
 /* Cholesky W = R^T R (paper Algorithm CholeskyQR, step 2): reads the upper triangle of
  * W, writes upper R (strict lower part zeroed).  A pivot that is not positive (or NaN)
  * at column k sets *d_info = 1000*stage + k (if *d_info was 0) and makes R NaN from
- * column k on.  Workspace: at least n*n doubles (scratch of the large-size variant). */
+ * column k on.  R may be W itself (ldr == ldw, in place); no other overlap.  n <= 8192.
+ * work, work_bytes: unused (the factorization runs in R); NULL and 0 are accepted. */
 int tsqr_potrf(int64_t n, const double* W, int64_t ldw, double* R, int64_t ldr, int stage,
                int* d_info, void* work, size_t work_bytes, void* stream);
 

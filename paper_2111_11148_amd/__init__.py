@@ -451,9 +451,8 @@ def potrf(W: torch.Tensor, stage: int = 2, stream=None):
     n = W.shape[0]
     R = colmajor(n, n, device=W.device)
     info = torch.zeros(1, dtype=torch.int32, device=W.device)
-    work = torch.empty(n * n, dtype=torch.float64, device=W.device)
     _check(load().tsqr_potrf(n, W.data_ptr(), ldw, R.data_ptr(), n, stage, info.data_ptr(),
-                             work.data_ptr(), work.numel() * 8, _stream(stream)), "tsqr_potrf")
+                             None, 0, _stream(stream)), "tsqr_potrf")
     return R, info
 
 

@@ -905,8 +905,9 @@ int tsqr_potrf(int64_t n, const double* W, int64_t ldw, double* R, int64_t ldr, 
   if (!R) return -4;
   if (ldr < n) return -5;
   if (stage < 1 || stage > 9) return -6;
-  if (!work || work_bytes < (size_t)n * n * sizeof(double)) return TSQR_ERR_WORKSPACE;
-  if (launch_potrf((int)n, W, ldw, R, ldr, stage, d_info, (double*)work, (hipStream_t)stream) !=
+  (void)work;  // the factorization runs in place in R: no scratch
+  (void)work_bytes;
+  if (launch_potrf((int)n, W, ldw, R, ldr, stage, d_info, nullptr, (hipStream_t)stream) !=
       hipSuccess)
     return TSQR_ERR_HIP;
   return TSQR_OK;

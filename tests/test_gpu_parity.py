@@ -210,6 +210,23 @@ def test_potrf_ill_conditioned(n, kappa_w):
     assert rel_fro(Rg, Ro) <= 20 * n * EPS * kappa_w
 
 
+@pytest.mark.parametrize("n", [40, 128, 300])
+def test_potrf_in_place_without_workspace(n):
+    """R may be W itself (same leading dimension); the call takes no workspace."""
+    X = gen_matrix(3 * n + 5, n, 10.0, 11 + n)
+    W = np.asfortranarray(X.T @ X)
+    Wd = dev(W)
+    ref, _ = tsqr.potrf(dev(W), stage=2)
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ld = Wd.stride(1)
+    rc = tsqr.load().tsqr_potrf(n, Wd.data_ptr(), ld, Wd.data_ptr(), ld, 2, info.data_ptr(),
+                                None, 0, None)
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    assert torch.equal(Wd, ref)
+
+
 def test_potrf_breakdown_and_upper_only():
     W = np.eye(6)
     W[3, 3] = -1.0
