@@ -64,7 +64,8 @@ def test_sketch_normals_match_oracle(i0, ni, j0, nj):
 
 
 # ---------------------------------------------------------------------------- sketch --
-@pytest.mark.parametrize("m,n,s", [(4096, 32, 64), (1000, 5, 7), (1027, 17, 40), (3000, 128, 256),
+@pytest.mark.parametrize("m,n,s", [(5000, 16, 8192), (3001, 40, 2500),
+                                   (4096, 32, 64), (1000, 5, 7), (1027, 17, 40), (3000, 128, 256),
                                    (777, 1, 1), (2050, 100, 100), (513, 64, 129), (4100, 200, 400),
                                    (2000, 600, 1200)])
 def test_sketch_parity(m, n, s):
@@ -92,7 +93,8 @@ def test_sketch_leading_dimension_and_determinism():
 @pytest.mark.parametrize("s,n,kappa", [(64, 32, 1e4), (256, 128, 1e8), (40, 40, 1e3), (9, 1, 1.0),
                                        (300, 150, 1e5), (512, 256, 1e6), (130, 65, 1e2),
                                        (1000, 100, 1e5), (1536, 700, 1e4), (512, 200, 1e12),
-                                       (2048, 1024, 1e8), (700, 333, 1e6)])
+                                       (2048, 1024, 1e8), (700, 333, 1e6),
+                                       (3000, 200, 1e6), (8192, 64, 1e4), (4100, 300, 1e8)])
 def test_sketch_factor_parity(variant, s, n, kappa):
     """R0 is the unique (sign-normalised) R or U factor: ||dR0||/||R0|| <= c n u kappa(B)."""
     B = gen_matrix(s, n, kappa, 17 + s)
@@ -279,7 +281,8 @@ def _check_qr(A, Qd, Rd, Q, R, info, ortho_tol=1e-12, res_tol=1e-13):
                                          (1000, 7, 14, 1e8), (1027, 17, 33, 1e12),
                                          (6000, 128, 256, 1e14), (2500, 100, 200, 1e6),
                                          (64, 64, 128, 1e4), (300, 1, 2, 1.0),
-                                         (3000, 256, 512, 1e12), (800, 20, 20, 1e3)])
+                                         (3000, 256, 512, 1e12), (800, 20, 20, 1e3),
+                                         (12000, 48, 4000, 1e10)])
 def test_end_to_end_parity(variant, m, n, s, kappa):
     """Q, R of the GPU path: orthogonality <= 1e-12 and residual <= 1e-13 (the targets),
     R upper with positive diagonal, and R within c kappa u of the oracle's R (both are
