@@ -308,7 +308,8 @@ size_t tsqr_sketch_workspace_bytes(int64_t m, int64_t n, int64_t s);
 int tsqr_sketch(int64_t m, int64_t n, const double* A, int64_t lda, int64_t s, uint64_t seed,
                 double* B, int64_t ldb, void* work, size_t work_bytes, void* stream);
 
-/* R factor of the s x n sketch (paper Algorithms rQR/rLU-CholeskyQR, step 2):
+/* R factor of the s x n sketch (paper Algorithms rQR/rLU-CholeskyQR, the sketch's
+ * factorization):
  * variant TSQR_VARIANT_RQR = Householder QR (LAPACK reflector convention), RLU = partial
  * pivot LU; the result is sign-normalised, R0 = diag(sign d_k) * (R or U), and written as
  * an n x n upper matrix (strict lower part zeroed, ldr >= n).  A zero or NaN diagonal at
@@ -320,8 +321,8 @@ int tsqr_sketch_factor(int variant, int64_t s, int64_t n, const double* B, int64
                        double* R0, int64_t ldr, int* d_info, void* work, size_t work_bytes,
                        void* stream);
 
-/* Right-side upper triangular solve X = Y T^{-1} by row-wise substitution (paper
- * Algorithm CholeskyQR, step 3; row-wise backward stable, no explicit inverse).
+/* Right-side upper triangular solve X = Y T^{-1} by row-wise substitution (the Q = A R^{-1}
+ * of paper Algorithm CholeskyQR; row-wise backward stable, no explicit inverse).
  * Y, X: m x n (ldy, ldx >= m); X may be the same buffer as Y with ldx == ldy (in place);
  * T: n x n upper, only its upper triangle is read.  n <= 1024 (above 128 columns the
  * solve runs by 128-column blocks with an MFMA update between them).
@@ -330,14 +331,14 @@ size_t tsqr_trsm_workspace_bytes(int64_t n);
 int tsqr_trsm(int64_t m, int64_t n, const double* Y, int64_t ldy, const double* T, int64_t ldt,
               double* X, int64_t ldx, void* work, size_t work_bytes, void* stream);
 
-/* Gram matrix W = X^T X (paper Algorithm CholeskyQR, step 1), both triangles written
+/* Gram matrix W = X^T X (paper Algorithm CholeskyQR), both triangles written
  * (ldw >= n).  Split over row blocks, fixed-order reduction.  n <= 1024.
  * Workspace: tsqr_gram_workspace_bytes(m, n). */
 size_t tsqr_gram_workspace_bytes(int64_t m, int64_t n);
 int tsqr_gram(int64_t m, int64_t n, const double* X, int64_t ldx, double* W, int64_t ldw,
               void* work, size_t work_bytes, void* stream);
 
-/* Cholesky W = R^T R (paper Algorithm CholeskyQR, step 2): reads the upper triangle of
+/* Cholesky W = R^T R (paper Algorithm CholeskyQR): reads the upper triangle of
  * W, writes upper R (strict lower part zeroed).  A pivot that is not positive (or NaN)
  * at column k sets *d_info = 1000*stage + k (if *d_info was 0) and makes R NaN from
  * column k on.  R may be W itself (ldr == ldw, in place); no other overlap.  n <= 8192.
@@ -345,8 +346,8 @@ int tsqr_gram(int64_t m, int64_t n, const double* X, int64_t ldx, double* W, int
 int tsqr_potrf(int64_t n, const double* W, int64_t ldw, double* R, int64_t ldr, int stage,
                int* d_info, void* work, size_t work_bytes, void* stream);
 
-/* C = A B for upper triangular n x n A and B (R-factor assembly, paper Algorithm
- * rQR-CholeskyQR step 5 and Algorithm CholeskyQR2 step 3).  C must not overlap A or B. */
+/* C = A B for upper triangular n x n A and B (the R-factor products of paper Algorithms
+ * rQR-CholeskyQR and CholeskyQR2).  C must not overlap A or B. */
 int tsqr_trmm_upper(int64_t n, const double* A, int64_t lda, const double* B, int64_t ldb,
                     double* C, int64_t ldc, void* stream);
 

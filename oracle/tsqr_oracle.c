@@ -174,8 +174,8 @@ void or_sketch_rows(int64_t m, int64_t n, const double *A, int64_t lda, int64_t 
 }
 
 /* ------------------------------------------------------------------------------------
- * Small dense factorizations of the l x n sketch (paper Algorithms rLU- and
- * rQR-CholeskyQR, step 2).
+ * Small dense factorizations of the l x n sketch (the R factor of the sketch in paper
+ * Algorithms rLU- and rQR-CholeskyQR).
  * ------------------------------------------------------------------------------------ */
 
 /* Householder QR (Golub & Van Loan, "Matrix Computations", Alg. 5.2.1 with the reflector
@@ -304,7 +304,7 @@ void or_trsm_ru(int64_t m, int64_t n, const double *Y, int64_t ldy, const double
     }
 }
 
-/* Gram matrix W = X^T X (paper Algorithm CholeskyQR, step 1).  Only the upper triangle
+/* Gram matrix W = X^T X (the Gram matrix of paper Algorithm CholeskyQR).  Only the upper triangle
  * (with the diagonal) is formed; the strict lower triangle of W is set equal to it. */
 void or_gram(int64_t m, int64_t n, const double *X, int64_t ldx, double *W, int64_t ldw) {
 #pragma omp parallel for schedule(dynamic, 1)

@@ -1,7 +1,7 @@
 // Small dense factorizations on the critical path of randomized XR-CholeskyQR:
-//   * R0 of the l x n sketch by Householder QR (paper Algorithm rQR-CholeskyQR, step 2)
-//     or by partial-pivot LU (Algorithm rLU-CholeskyQR, step 2), sign-normalised;
-//   * the n x n Cholesky factor of a Gram matrix (Algorithm CholeskyQR, step 2);
+//   * R0 of the l x n sketch by Householder QR (paper Algorithm rQR-CholeskyQR) or by
+//     partial-pivot LU (Algorithm rLU-CholeskyQR), sign-normalised;
+//   * the n x n Cholesky factor of a Gram matrix (Algorithm CholeskyQR);
 //   * products of upper-triangular factors (R = R2 R1 R0) and breakdown poisoning.
 //
 // Each factorization runs in one 1024-thread workgroup (16 wavefronts).  Wavefront w owns
