@@ -376,10 +376,13 @@ int tsqr_sketch_normals(uint64_t seed, int64_t i0, int64_t ni, int64_t j0, int64
  * clears the records and enables recording; tsqr_profile_stop() disables it, waits for
  * the recorded events and returns the number of records (or TSQR_ERR_HIP);
  * tsqr_profile_record(i) returns the i-th record's name (static storage) and duration in
- * milliseconds (-1 if i is out of range).  Process-wide; not meant for concurrent use. */
+ * milliseconds (-1 if i is out of range).  tsqr_profile_only(name) limits the recording
+ * to the phase of that name (NULL: every phase), so that a timed run carries only the
+ * events it needs.  Process-wide; not meant for concurrent use. */
 int tsqr_profile_start(void);
 int tsqr_profile_stop(void);
 int tsqr_profile_record(int i, const char** name, double* ms);
+int tsqr_profile_only(const char* name);
 
 /* Library identification string (static storage). */
 const char* tsqr_version(void);

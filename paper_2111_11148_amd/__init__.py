@@ -75,6 +75,7 @@ _SIGS = {
     "tsqr_batched_launches": (_int, [_vp]),
     "tsqr_batched_destroy": (None, [_vp]),
     "tsqr_profile_start": (_int, []),
+    "tsqr_profile_only": (_int, [ctypes.c_char_p]),
     "tsqr_profile_stop": (_int, []),
     "tsqr_profile_record": (_int, [_int, ctypes.POINTER(ctypes.c_char_p),
                                    ctypes.POINTER(ctypes.c_double)]),
@@ -156,7 +157,9 @@ def to_device_colmajor(A, ld: int | None = None, device="cuda") -> torch.Tensor:
 
 
 # ------------------------------------------------------------------ phase timing ----
-def profile_start() -> None:
+def profile_start(only: str | None = None) -> None:
+    """Start recording phase events; `only` limits them to the phase of that name."""
+    _check(load().tsqr_profile_only(only.encode() if only else None), "tsqr_profile_only")
     _check(load().tsqr_profile_start(), "tsqr_profile_start")
 
 

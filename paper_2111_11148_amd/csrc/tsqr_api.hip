@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -94,10 +95,16 @@ bool g_prof_on = false;
 std::vector<ProfRec> g_prof_live;
 std::vector<std::pair<const char*, double>> g_prof_done;
 std::vector<hipEvent_t> g_prof_pool;
+std::string g_prof_only;  // empty: every phase
 
-bool prof_on() {
+bool prof_on(const char* name) {
   std::lock_guard<std::mutex> g(g_prof_mu);
-  return g_prof_on;
+  return g_prof_on && (g_prof_only.empty() || g_prof_only == name);
+}
+
+void prof_release(hipEvent_t e) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof_pool.push_back(e);
 }
 
 hipEvent_t prof_event() {
@@ -120,12 +127,16 @@ void prof_push(const char* name, hipEvent_t a, hipEvent_t b) {
 #define TSQR_PHASE(name, expr)                                               \
   do {                                                                       \
     hipEvent_t ev_a_ = nullptr, ev_b_ = nullptr;                             \
-    const bool on_ = prof_on();                                              \
+    const bool on_ = prof_on(name);                                          \
     if (on_ && (ev_a_ = prof_event())) (void)hipEventRecord(ev_a_, st);      \
     const hipError_t err_ = (expr);                                          \
-    if (on_ && ev_a_ && (ev_b_ = prof_event())) {                            \
-      (void)hipEventRecord(ev_b_, st);                                       \
-      prof_push(name, ev_a_, ev_b_);                                         \
+    if (on_ && ev_a_) {                                                      \
+      if ((ev_b_ = prof_event())) {                                          \
+        (void)hipEventRecord(ev_b_, st);                                     \
+        prof_push(name, ev_a_, ev_b_);                                       \
+      } else {                                                               \
+        prof_release(ev_a_);                                                 \
+      }                                                                      \
     }                                                                        \
     if (err_ != hipSuccess) return TSQR_ERR_HIP;                             \
   } while (0)
@@ -552,6 +563,12 @@ int tsqr_profile_stop(void) {
   }
   g_prof_live.clear();
   return rc == TSQR_OK ? (int)g_prof_done.size() : rc;
+}
+
+int tsqr_profile_only(const char* name) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof_only = name ? name : "";
+  return TSQR_OK;
 }
 
 int tsqr_profile_record(int i, const char** name, double* ms) {
