@@ -717,9 +717,16 @@ hipError_t launch_sketch_lowp(int prec, const SketchPlan& p, int64_t m, int n, c
                          p.kblocks, part);
     return hipGetLastError();
   }
+  // the FP64 sketch's 16-wavefront shape (one row tile each) runs here as 8 wavefronts of
+  // two row tiles: the same 16 row tiles per workgroup, row blocks and partial layout
+  SketchPlan q = p;
+  if (q.NW == 16 && q.IT == 1) {
+    q.NW = 8;
+    q.IT = 2;
+  }
 #define TSQR_SKL(PR, IT_, JT_, NW_)                                                           \
-  if (prec == PR && p.IT == IT_ && p.JT == JT_ && p.NW == NW_)                                \
-    return sketch_lowp_t<PR, IT_, JT_, NW_>(p, m, n, A, lda, seed, part, st);
+  if (prec == PR && q.IT == IT_ && q.JT == JT_ && q.NW == NW_)                                \
+    return sketch_lowp_t<PR, IT_, JT_, NW_>(q, m, n, A, lda, seed, part, st);
 #define TSQR_SKL_ALL(PR)                                                                      \
   TSQR_SKL(PR, 1, 1, 4) TSQR_SKL(PR, 1, 2, 4) TSQR_SKL(PR, 1, 4, 4) TSQR_SKL(PR, 1, 8, 4)     \
   TSQR_SKL(PR, 1, 1, 8) TSQR_SKL(PR, 1, 2, 8) TSQR_SKL(PR, 1, 4, 8) TSQR_SKL(PR, 1, 8, 8)     \

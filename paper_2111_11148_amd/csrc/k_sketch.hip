@@ -214,10 +214,18 @@ SketchPlan plan_sketch(int64_t m, int n, int s) {
   p.IT = p.it_total >= 16 ? 2 : 1;
   const int waves_needed = (p.it_total + p.IT - 1) / p.IT;
   p.NW = waves_needed >= 8 ? 8 : 4;
+  // at least 16 row tiles and 8 column tiles: sixteen wavefronts of one row tile each (four
+  // per SIMD, within 128 registers) hide latency better than eight with two (measured:
+  // 2^20 x 128, s = 256: 1.268 -> 1.259 ms; 2^20 x 256, s = 512: 4.74 -> 4.61 ms); every
+  // tile is still summed by one wavefront over the same rows, so B does not change
+  if (p.it_total >= 16 && p.JT == 8) {
+    p.IT = 1;
+    p.NW = 16;
+  }
   p.igroups = (p.it_total + p.NW * p.IT - 1) / (p.NW * p.IT);
   const int cus = device_cu_count();
-  // one 8-wave workgroup (or two 4-wave ones) per compute unit
-  int64_t target = (int64_t)cus * (p.NW == 8 ? 1 : 2) / (p.igroups * p.jgroups);
+  // one workgroup of 8 or 16 wavefronts (or two 4-wave ones) per compute unit
+  int64_t target = (int64_t)cus * (p.NW >= 8 ? 1 : 2) / (p.igroups * p.jgroups);
   if (target < 1) target = 1;
   int64_t rpb = (m + target - 1) / target;
   rpb = ((rpb + 31) / 32) * 32;
@@ -249,7 +257,7 @@ hipError_t launch_sketch(const SketchPlan& p, int64_t m, int n, const double* A,
   TSQR_SK(1, 1, 4) TSQR_SK(1, 2, 4) TSQR_SK(1, 4, 4) TSQR_SK(1, 8, 4)
   TSQR_SK(1, 1, 8) TSQR_SK(1, 2, 8) TSQR_SK(1, 4, 8) TSQR_SK(1, 8, 8)
   TSQR_SK(2, 8, 4) TSQR_SK(2, 8, 8) TSQR_SK(2, 4, 8) TSQR_SK(2, 4, 4)
-  TSQR_SK(2, 2, 8) TSQR_SK(2, 1, 8) TSQR_SK(2, 2, 4) TSQR_SK(2, 1, 4)
+  TSQR_SK(2, 2, 8) TSQR_SK(2, 1, 8) TSQR_SK(2, 2, 4) TSQR_SK(2, 1, 4) TSQR_SK(1, 8, 16)
 #undef TSQR_SK
   return hipErrorInvalidValue;
 }
