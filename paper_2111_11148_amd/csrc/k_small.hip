@@ -1360,6 +1360,10 @@ hipError_t launch_sketch_factor(int variant, int s, int n, const double* B, int6
                                 hipStream_t st) {
   const int rpl = pow2_at_least((s + 63) / 64), cpw = pow2_at_least((n + 15) / 16);
   dim3 grid(1), block(kSmallThreads);
+  // LU of 64+ columns: the blocked form is faster than the register kernel from n = 64
+  // (measured: 256 x 128, 0.40 -> 0.38 ms)
+  if (variant == 1 && n >= 64 && s <= 512)
+    return lu_blocked_t<16, 1>(s, n, B, ldb, R, ldr, info, scratch, st);
 #define TSQR_FAC(RPL_, CPW_)                                                                  \
   if (rpl == RPL_ && cpw == CPW_) {                                                           \
     if (variant == 1)                                                                         \
