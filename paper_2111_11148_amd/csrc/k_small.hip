@@ -58,6 +58,25 @@ __device__ __forceinline__ void house(double alpha, double xnorm2, double& beta,
   }
 }
 
+// 1 + the smallest k < n with !(d(k) != 0.0) (a zero or NaN diagonal), 0 if there is none;
+// the same value in every thread.  Every thread of the workgroup must call it (it has
+// barriers); each thread scans a strided share, so no thread walks the whole diagonal.
+template <class F>
+__device__ __forceinline__ int block_first_bad(int n, F d) {
+  __shared__ int best;
+  if (threadIdx.x == 0) best = 0x7fffffff;
+  __syncthreads();
+  int mine = 0x7fffffff;
+  for (int k = (int)threadIdx.x; k < n; k += (int)blockDim.x)
+    if (!(d(k) != 0.0)) {
+      mine = k;  // strided scan: a thread's first hit is its smallest
+      break;
+    }
+  if (mine != 0x7fffffff) atomicMin(&best, mine);
+  __syncthreads();
+  return best == 0x7fffffff ? 0 : best + 1;
+}
+
 // ================================================================ Householder QR ====
 template <int RPL, int CPW>
 __device__ __forceinline__ void geqrf_reg_body(int s, int n,
@@ -142,11 +161,9 @@ __device__ __forceinline__ void geqrf_reg_body(int s, int n,
       R[(int64_t)c * ldr + i] = v;
     }
   }
-  if (threadIdx.x == 0 && info) {
-    int bad = 0;
-    for (int k = 0; k < n && !bad; ++k)
-      if (!(betas[k] != 0.0)) bad = k + 1;
-    if (bad && *info == 0) *info = 1000 + bad;
+  if (info) {
+    const int bad = block_first_bad(n, [&](int k) { return betas[k]; });
+    if (threadIdx.x == 0 && bad && *info == 0) *info = 1000 + bad;
   }
 }
 
@@ -216,11 +233,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_geqrf_glb(int s, int n,
       }
       R[(int64_t)c * ldr + i] = v;
     }
-  if (threadIdx.x == 0 && info) {
-    int bad = 0;
-    for (int k = 0; k < n && !bad; ++k)
-      if (!(betas[k] != 0.0)) bad = k + 1;
-    if (bad && *info == 0) *info = 1000 + bad;
+  if (info) {
+    const int bad = block_first_bad(n, [&](int k) { return betas[k]; });
+    if (threadIdx.x == 0 && bad && *info == 0) *info = 1000 + bad;
   }
 }
 
@@ -496,11 +511,9 @@ __global__ __launch_bounds__(256) void k_qr_finish(int s, int n, const double* _
     }
     R[(int64_t)c * ldr + i] = v;
   }
-  if (c == 0 && threadIdx.x == 0 && info) {
-    int bad = 0;
-    for (int k = 0; k < n && !bad; ++k)
-      if (!(betas[k] != 0.0)) bad = k + 1;
-    if (bad && *info == 0) *info = 1000 + bad;
+  if (c == 0 && info) {
+    const int bad = block_first_bad(n, [&](int k) { return betas[k]; });
+    if (threadIdx.x == 0 && bad && *info == 0) *info = 1000 + bad;
   }
 }
 
@@ -648,11 +661,9 @@ __device__ __forceinline__ void getrf_reg_body(int s, int n,
       R[(int64_t)c * ldr + i] = v;
     }
   }
-  if (threadIdx.x == 0 && info) {
-    int bad = 0;
-    for (int k = 0; k < n && !bad; ++k)
-      if (!(ukk[k] != 0.0)) bad = k + 1;
-    if (bad && *info == 0) *info = 1000 + bad;
+  if (info) {
+    const int bad = block_first_bad(n, [&](int k) { return ukk[k]; });
+    if (threadIdx.x == 0 && bad && *info == 0) *info = 1000 + bad;
   }
 }
 
@@ -739,11 +750,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_getrf_glb(int s, int n,
       }
       R[(int64_t)c * ldr + i] = v;
     }
-  if (threadIdx.x == 0 && info) {
-    int bad = 0;
-    for (int k = 0; k < n && !bad; ++k)
-      if (!(ukk[k] != 0.0)) bad = k + 1;
-    if (bad && *info == 0) *info = 1000 + bad;
+  if (info) {
+    const int bad = block_first_bad(n, [&](int k) { return ukk[k]; });
+    if (threadIdx.x == 0 && bad && *info == 0) *info = 1000 + bad;
   }
 }
 
@@ -1319,11 +1328,9 @@ __global__ __launch_bounds__(256) void k_lu_finish(int s, int n, const double* _
     }
     R[(int64_t)c * ldr + i] = v;
   }
-  if (c == 0 && threadIdx.x == 0 && info) {
-    int bad = 0;
-    for (int k = 0; k < n && !bad; ++k)
-      if (!(Wk[(int64_t)k * s + k] != 0.0)) bad = k + 1;
-    if (bad && *info == 0) *info = 1000 + bad;
+  if (c == 0 && info) {
+    const int bad = block_first_bad(n, [&](int k) { return Wk[(int64_t)k * s + k]; });
+    if (threadIdx.x == 0 && bad && *info == 0) *info = 1000 + bad;
   }
 }
 
