@@ -55,10 +55,17 @@ __device__ __forceinline__ void trsm_prep_body(int n, int jt, const double* __re
   auto Tg = [&](int i, int j) -> double {
     return (i < n && j < n) ? T[(int64_t)j * ldt + i] : (i == j ? 1.0 : 0.0);
   };
-  for (int a = 0; a < b; ++a)
+  // off-diagonal tiles of block column b: one element per thread per tile, eight tiles'
+  // loads in flight together
+  for (int a0 = 0; a0 < b; a0 += 8)
     for (int e = threadIdx.x; e < 256; e += blockDim.x) {
       const int i = e / 16, j = e % 16;
-      P[(size_t)off_index(a, b) * 256 + i * 16 + sigma16(j)] = -Tg(16 * a + i, 16 * b + j);
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = (a0 + u < b) ? Tg(16 * (a0 + u) + i, 16 * b + j) : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (a0 + u < b) P[(size_t)off_index(a0 + u, b) * 256 + i * 16 + sigma16(j)] = -v[u];
     }
   __shared__ double tb[16][17];
   __shared__ double ti[16][17];
@@ -82,20 +89,29 @@ __device__ __forceinline__ void trsm_prep_body(int n, int jt, const double* __re
     const int i = e / 16, j = e % 16;
     P[(size_t)(noff + jt + b) * 256 + i * 16 + sigma16(j)] = ti[i][j];
   }
-  if (threadIdx.x == 0) {  // infinity-norm condition estimate of the block
-    double nt = 0.0, ni = 0.0;
-    for (int i = 0; i < 16; ++i) {
-      double st = 0.0, si = 0.0;
+  if (threadIdx.x < 64) {  // infinity-norm condition estimate of the block, one wavefront
+    // lane i < 16 sums row i of the block and of its inverse; the maxima over the rows by
+    // DPP within the first row of 16 lanes (max is order-independent)
+    const int i = threadIdx.x;
+    double st = 0.0, si = 0.0;
+    if (i < 16)
       for (int j = 0; j < 16; ++j) {
         st += fabs(tb[i][j]);
         si += fabs(ti[i][j]);
       }
-      nt = fmax(nt, st);
-      ni = fmax(ni, si);
+    st = fmax(st, dpp_f64<0xB1>(st));
+    st = fmax(st, dpp_f64<0x4E>(st));
+    st = fmax(st, dpp_f64<0x124>(st));
+    st = fmax(st, dpp_f64<0x128>(st));
+    si = fmax(si, dpp_f64<0xB1>(si));
+    si = fmax(si, dpp_f64<0x4E>(si));
+    si = fmax(si, dpp_f64<0x124>(si));
+    si = fmax(si, dpp_f64<0x128>(si));
+    if (i == 0) {
+      const double c = st * si;
+      int* flags = reinterpret_cast<int*>(P + (size_t)(noff + 2 * jt) * 256);
+      flags[b] = (c > kTrsmRefineCond || !(c == c)) ? 1 : 0;
     }
-    const double c = nt * ni;
-    int* flags = reinterpret_cast<int*>(P + (size_t)(noff + 2 * jt) * 256);
-    flags[b] = (c > kTrsmRefineCond || !(c == c)) ? 1 : 0;
   }
 }
 
