@@ -953,6 +953,7 @@ __global__ __launch_bounds__(256) void k_chol_trail(int n, double* R, int64_t ld
 template <int NB>
 static hipError_t potrf_multi_t(int n, const double* W, int64_t ldw, double* R, int64_t ldr,
                                 int stage, int* info, hipStream_t st, double shift) {
+  static_assert(NB <= kWave && NB % 4 == 0, "one wavefront factors the diagonal block");
   hipLaunchKernelGGL(k_chol_init, dim3(n), dim3(256), 0, st, n, W, ldw, R, ldr, shift);
   hipError_t e = hipGetLastError();
   for (int j0 = 0; j0 < n && e == hipSuccess; j0 += NB) {
@@ -1337,6 +1338,8 @@ __global__ __launch_bounds__(256) void k_lu_finish(int s, int n, const double* _
 template <int NB, int PR>
 static hipError_t lu_blocked_t(int s, int n, const double* B, int64_t ldb, double* R,
                                int64_t ldr, int* info, double* scratch, hipStream_t st) {
+  static_assert(NB <= kWave, "k_lu_trail holds the panel's rows in one wavefront's lanes");
+  if (s > PR * kLuPanelThreads || n > s) return hipErrorInvalidValue;  // panel rows per thread
   double* Wk = scratch;
   int* piv = reinterpret_cast<int*>(scratch + (size_t)s * n);
   hipLaunchKernelGGL(k_copy_cols, dim3(n), dim3(256), 0, st, s, n, B, ldb, Wk);
