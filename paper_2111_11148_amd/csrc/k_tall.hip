@@ -339,6 +339,87 @@ __global__ __launch_bounds__(512) void k_trsm_update(int64_t m, int nb,
   }
 }
 
+// The same update against all earlier blocks at once, C = Y - X T for X of K = k0 columns
+// (the solved blocks) and the k0 x nb block column T(0:k0, block): one read of X instead of
+// one pass over C per earlier block.  A workgroup of 16 wavefronts holds 256 rows of C in
+// registers (one 16-row tile per wavefront) while T streams through LDS in 128-row
+// chunks; Y is read at the end.  K is a multiple of kBlk.
+__global__ __launch_bounds__(1024) void k_trsm_update_k(int64_t m, int nb, int K,
+                                                        const double* __restrict__ X,
+                                                        int64_t ldx, const double* __restrict__ T,
+                                                        int64_t ldt, const double* Y, int64_t ldy,
+                                                        double* C, int64_t ldc) {
+  constexpr int NB = kBlk / 16;  // column tiles of C
+  constexpr int KS = kBlk / 4;   // MFMA K-steps per chunk
+  constexpr int LDT = kBlk + 1;
+  constexpr int KC = 8;
+  extern __shared__ double ts[];  // kBlk x LDT
+  const int lane = lane_id();
+  const int q = lane >> 4, c16 = lane & 15;
+  const int64_t tile = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+  const int64_t ntiles = (m + 15) / 16;
+  const bool tok = tile < ntiles;
+  const int64_t row = (tok ? tile : 0) * 16 + c16;
+  const bool rok = tok && row < m;
+  const int64_t rowc = rok ? row : 0;  // clamped, always a valid address
+  auto load_x = [&](int kc, int c, double (&xb)[KC]) {
+    const double* xp = X + (int64_t)(kc + 4 * c * KC + q) * ldx + rowc;
+    int64_t xs = ldx;
+    asm volatile("" : "+v"(xp), "+s"(xs));
+#pragma unroll
+    for (int j = 0; j < KC; ++j) xb[j] = xp[(4 * j) * xs];
+  };
+  v4d acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = v4d{0.0, 0.0, 0.0, 0.0};
+  double xa[KC], xn[KC];
+  load_x(0, 0, xa);
+  for (int kc = 0; kc < K; kc += kBlk) {
+    __syncthreads();  // every wavefront is done with the previous chunk of T
+    for (int e = threadIdx.x; e < kBlk * kBlk; e += blockDim.x) {
+      const int k = e % kBlk, c = e / kBlk;
+      ts[k * LDT + c] = (c < nb) ? T[(int64_t)c * ldt + kc + k] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < KS / KC; ++c) {
+      // next X chunk: the rest of this block of K, then the next block's first (the last
+      // chunk re-reads itself: always a valid address)
+      if (c + 1 < KS / KC) load_x(kc, c + 1, xn);
+      else load_x(kc + kBlk < K ? kc + kBlk : kc, 0, xn);
+#pragma unroll
+      for (int j = 0; j < KC; ++j) {
+        const lds_f64* tp = (const lds_f64*)ts + (4 * (c * KC + j) + q) * LDT + c16;
+        asm volatile("" : "+v"(tp));
+        const double xv = rok ? xa[j] : 0.0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[b] = mfma_f64(tp[16 * b], xv, acc[b]);
+      }
+#pragma unroll
+      for (int j = 0; j < KC; ++j) xa[j] = xn[j];
+    }
+  }
+  if (rok) {
+    // Y(row, 16b + 4r + q); a column past nb is neither read nor stored
+    const double* yp = Y + (int64_t)q * ldy + row;
+    double* cp = C + (int64_t)q * ldc + row;
+    int64_t ys = ldy, cs = ldc;
+    asm volatile("" : "+v"(yp), "+v"(cp), "+s"(ys), "+s"(cs));
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      double yv[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const bool ok = 16 * b + 4 * r + q < nb;
+        yv[r] = yp[ok ? (16 * b + 4 * r) * ys : 0];
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (16 * b + 4 * r + q < nb) cp[(16 * b + 4 * r) * cs] = yv[r] - acc[b][r];
+    }
+  }
+}
+
 size_t trsm_scratch_doubles(int n) {
   // wider matrices are solved in column blocks of kBlk that reuse one prepared block
   const int nn = n > kBlk ? kBlk : n;
@@ -354,6 +435,11 @@ static hipError_t launch_trsm_block(int64_t m, int n, const double* Y, int64_t l
 // X = Y T^{-1}.  Up to kBlk columns: one substitution kernel.  Wider: by column blocks,
 // X_k = (Y_k - sum_{j<k} X_j T_jk) T_kk^{-1} (the update kernel, then the substitution of
 // the diagonal block in place).
+#ifndef TSQR_TRSM_UPDATE_K
+#define TSQR_TRSM_UPDATE_K 1
+#endif
+constexpr bool kTrsmUpdateK = TSQR_TRSM_UPDATE_K;
+
 hipError_t launch_trsm(int64_t m, int n, const double* Y, int64_t ldy, const double* T,
                        int64_t ldt, double* X, int64_t ldx, double* scratch, hipStream_t st) {
   if (m <= 0 || n <= 0) return hipSuccess;
@@ -365,6 +451,15 @@ hipError_t launch_trsm(int64_t m, int n, const double* Y, int64_t ldy, const dou
   const size_t ush = (size_t)kBlk * (kBlk + 1) * sizeof(double);
   for (int k0 = 0; k0 < n; k0 += kBlk) {
     const int nbk = (n - k0) < kBlk ? (n - k0) : kBlk;
+    if (k0 >= 2 * kBlk && kTrsmUpdateK) {
+      // all earlier blocks in one pass: X(:, 0:k0) read once
+      const int64_t wgs = (ntiles + 15) / 16;
+      hipLaunchKernelGGL(k_trsm_update_k, dim3((unsigned)wgs), dim3(1024), ush, st, m, nbk, k0,
+                         X, ldx, T + (int64_t)k0 * ldt, ldt, Y + (int64_t)k0 * ldy, ldy,
+                         X + (int64_t)k0 * ldx, ldx);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    } else
     for (int j0 = 0; j0 < k0; j0 += kBlk) {
       const double* src = (j0 == 0) ? Y + (int64_t)k0 * ldy : X + (int64_t)k0 * ldx;
       const int64_t lds_ = (j0 == 0) ? ldy : ldx;
