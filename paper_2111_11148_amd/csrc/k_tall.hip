@@ -420,6 +420,126 @@ __global__ __launch_bounds__(1024) void k_trsm_update_k(int64_t m, int nb, int K
   }
 }
 
+// A later column block of the blocked solve in one pass: C = Y - X0 T(0:K, block) against
+// all solved blocks, then the block's own substitution, without writing C.  Persistent
+// workgroups of 16 wavefronts take 256 rows per round (one 16-row tile per wavefront);
+// the block's prepared diagonal tiles (k_trsm_prep) sit in LDS for the whole launch, and
+// T(0:K, block) streams through LDS in 32-row chunks with its columns in sigma16 order,
+// so that the update's accumulators come out in the substitution's register layout
+// (lane (q, c16), register r of tile b = column 16b + 4q + r of row c16).  Y may be the
+// output block itself (each element is read and written by the same lane).
+template <int JT>
+__global__ __launch_bounds__(1024, 1) void k_trsm_fused(int64_t m, int n, int K,
+                                                       const double* __restrict__ X0,
+                                                       int64_t ldx0,
+                                                       const double* __restrict__ Tk,
+                                                       int64_t ldt, const double* Y, int64_t ldy,
+                                                       const double* __restrict__ P, double* Xk,
+                                                       int64_t ldxk) {
+  constexpr int NOFF = JT * (JT - 1) / 2;
+  constexpr int NTILE = NOFF + 2 * JT;
+  constexpr int KCH = 32;          // rows of T per staged chunk (8 K-steps)
+  constexpr int NC = 16 * JT;      // columns of the block (padded)
+  constexpr int LDU = NC + 1;
+  extern __shared__ double sm[];
+  double* tl = sm;                 // prepared diagonal tiles
+  double* tu = sm + NTILE * 256;   // KCH x LDU chunk of T(0:K, block)
+  __shared__ int flags[JT];
+  const int* flags_g = reinterpret_cast<const int*>(P + (size_t)NTILE * 256);
+  for (int e = threadIdx.x; e < NTILE * 256; e += blockDim.x) tl[e] = P[e];
+  for (int e = threadIdx.x; e < JT; e += blockDim.x) flags[e] = flags_g[e];
+
+  const int lane = lane_id(), wave = wave_id();
+  const int q = lane >> 4, c16 = lane & 15;
+  const int64_t ntiles = (m + 15) / 16;
+  const int64_t ngroups = (ntiles + 15) / 16;
+  for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    const int64_t tile = g * 16 + wave;
+    const int64_t row = tile * 16 + c16;
+    const bool rok = tile < ntiles && row < m;
+    const int64_t rowc = rok ? row : 0;  // clamped, always a valid address
+    v4d xr[JT];
+#pragma unroll
+    for (int b = 0; b < JT; ++b) xr[b] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int kc = 0; kc < K; kc += KCH) {
+      // this chunk's X0(row, kc + 4j + q), issued before the barriers
+      double xa[KCH / 4];
+      {
+        const double* xp = X0 + (int64_t)(kc + q) * ldx0 + rowc;
+        int64_t xs = ldx0;
+        asm volatile("" : "+v"(xp), "+s"(xs));
+#pragma unroll
+        for (int j = 0; j < KCH / 4; ++j) xa[j] = xp[(4 * j) * xs];
+      }
+      __syncthreads();  // the previous chunk (or round) is done with tu
+      for (int e = threadIdx.x; e < KCH * NC; e += blockDim.x) {
+        const int k = e % KCH, pcol = e / KCH;  // consecutive threads: consecutive rows
+        const int col = 16 * (pcol / 16) + sigma16(pcol % 16);
+        tu[k * LDU + pcol] = (col < n) ? Tk[(int64_t)col * ldt + kc + k] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < KCH / 4; ++j) {
+        const lds_f64* tp = (const lds_f64*)tu + (4 * j + q) * LDU + c16;
+        asm volatile("" : "+v"(tp));
+        const double xv = rok ? xa[j] : 0.0;
+#pragma unroll
+        for (int b = 0; b < JT; ++b) xr[b] = mfma_f64(tp[16 * b], xv, xr[b]);
+      }
+    }
+    __syncthreads();  // tl and flags are staged (first round)
+    // C = Y - X0 T, in place in xr
+    {
+      const double* yb = Y + rowc + (int64_t)(4 * q) * ldy;
+      int64_t ys = ldy;
+      int lim = n - 4 * q;  // column 16b + 4q + r exists iff 16b + r < lim
+      asm volatile("" : "+v"(yb), "+s"(ys), "+v"(lim));
+#pragma unroll
+      for (int b = 0; b < JT; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const bool ok = 16 * b + r < lim;
+          const double y = yb[ok ? (16 * b + r) * ys : 0];
+          xr[b][r] = (rok && ok) ? y - xr[b][r] : 0.0;
+        }
+    }
+    // the block's substitution (as in trsm_mfma_body)
+    lds_f64* tlp = (lds_f64*)tl;
+    asm volatile("" : "+v"(tlp));
+    auto Aop = [&](int t, int kk) -> double { return tlp[t * 256 + (4 * q + kk) * 16 + c16]; };
+#pragma unroll
+    for (int b = 0; b < JT; ++b) {
+      const v4d C = xr[b];
+      v4d x0 = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) x0 = mfma_f64(Aop(NOFF + JT + b, kk), C[kk], x0);
+      if (flags[b]) {
+        v4d e = C;
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) e = mfma_f64(Aop(NOFF + b, kk), x0[kk], e);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) x0 = mfma_f64(Aop(NOFF + JT + b, kk), e[kk], x0);
+      }
+      xr[b] = x0;
+#pragma unroll
+      for (int bb = b + 1; bb < JT; ++bb)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+          xr[bb] = mfma_f64(Aop(off_index(b, bb), kk), xr[b][kk], xr[bb]);
+    }
+    if (rok) {
+      double* xb = Xk + row + (int64_t)(4 * q) * ldxk;
+      int64_t xs = ldxk;
+      asm volatile("" : "+v"(xb), "+s"(xs));
+#pragma unroll
+      for (int b = 0; b < JT; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (16 * b + 4 * q + r < n) xb[(16 * b + r) * xs] = xr[b][r];
+    }
+  }
+}
+
 size_t trsm_scratch_doubles(int n) {
   // wider matrices are solved in column blocks of kBlk that reuse one prepared block
   const int nn = n > kBlk ? kBlk : n;
@@ -439,6 +559,10 @@ static hipError_t launch_trsm_block(int64_t m, int n, const double* Y, int64_t l
 #define TSQR_TRSM_UPDATE_K 1
 #endif
 constexpr bool kTrsmUpdateK = TSQR_TRSM_UPDATE_K;
+#ifndef TSQR_TRSM_FUSED
+#define TSQR_TRSM_FUSED 1
+#endif
+constexpr bool kTrsmFused = TSQR_TRSM_FUSED;
 
 hipError_t launch_trsm(int64_t m, int n, const double* Y, int64_t ldy, const double* T,
                        int64_t ldt, double* X, int64_t ldx, double* scratch, hipStream_t st) {
@@ -451,6 +575,30 @@ hipError_t launch_trsm(int64_t m, int n, const double* Y, int64_t ldy, const dou
   const size_t ush = (size_t)kBlk * (kBlk + 1) * sizeof(double);
   for (int k0 = 0; k0 < n; k0 += kBlk) {
     const int nbk = (n - k0) < kBlk ? (n - k0) : kBlk;
+    if (k0 >= kBlk && kTrsmFused) {
+      // update against all solved blocks and this block's substitution in one pass
+      int jt = 1;
+      while (jt < (nbk + 15) / 16) jt <<= 1;
+      hipLaunchKernelGGL(k_trsm_prep, dim3(jt), dim3(256), 0, st, nbk, jt,
+                         T + (int64_t)k0 * ldt + k0, ldt, scratch);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      const int64_t ngroups = (ntiles + 15) / 16;
+      const int64_t grid = ngroups < cap ? ngroups : cap;
+      const double* yk = Y + (int64_t)k0 * ldy;
+      double* xk = X + (int64_t)k0 * ldx;
+#define TSQR_TF(J)                                                                             \
+  if (jt == J) {                                                                               \
+    const size_t sh = ((size_t)(J * (J - 1) / 2 + 2 * J) * 256 + 32 * (16 * J + 1)) * sizeof(double); \
+    hipLaunchKernelGGL(k_trsm_fused<J>, dim3((unsigned)grid), dim3(1024), sh, st, m, nbk, k0, X,  \
+                       ldx, T + (int64_t)k0 * ldt, ldt, yk, ldy, scratch, xk, ldx);             \
+  }
+      TSQR_TF(1) TSQR_TF(2) TSQR_TF(4) TSQR_TF(8)
+#undef TSQR_TF
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      continue;
+    }
     if (k0 >= 2 * kBlk && kTrsmUpdateK) {
       // all earlier blocks in one pass: X(:, 0:k0) read once
       const int64_t wgs = (ntiles + 15) / 16;
