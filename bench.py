@@ -403,7 +403,7 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; multi-GPU runs are not part of it "
+        print("bench.py: measures one GPU; runs over several GPUs are not supported "
               "(use --gpus 1)", file=sys.stderr)
         return 2
 

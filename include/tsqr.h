@@ -16,7 +16,7 @@
  *     enqueued on it in order and the host does not wait for it;
  *   - return value: 0 on success; -i if the i-th argument (1-based) is invalid, detected
  *     before any work is enqueued; TSQR_ERR_HIP if a HIP call fails; TSQR_ERR_WORKSPACE if
- *     the workspace is too small; TSQR_ERR_UNSUPPORTED for sizes this build does not
+ *     the workspace is too small; TSQR_ERR_UNSUPPORTED for sizes the library does not
  *     implement;
  *   - numerical breakdown is reported asynchronously through `d_info` (device int):
  *     0 = success; 1000*stage + k = zero, non-positive or NaN pivot at column k (1-based)
