@@ -28,7 +28,7 @@ __device__ __forceinline__ void sketch_f64_body(int64_t m, int n, const double* 
   constexpr int T = NW * 64;      // threads
   constexpr int CPP = T / (KC / 2);                 // columns loaded per pass
   constexpr int PASSES = (NC + CPP - 1) / CPP;
-  __shared__ double lds[KC * LDN];
+  __shared__ double ldsb[2][KC * LDN];  // double buffer: one barrier per chunk
 
   const int lane = lane_id(), wave = wave_id();
   const int q = lane >> 4, c16 = lane & 15;
@@ -58,7 +58,7 @@ __device__ __forceinline__ void sketch_f64_body(int64_t m, int n, const double* 
       pre[ps][1] = (okc && row + 1 < r1) ? src[1] : 0.0;
     }
   };
-  auto store_chunk = [&]() {
+  auto store_chunk = [&](double* lds) {
 #pragma unroll
     for (int ps = 0; ps < PASSES; ++ps) {
       const int cc = cb + ps * CPP;
@@ -69,12 +69,15 @@ __device__ __forceinline__ void sketch_f64_body(int64_t m, int n, const double* 
     }
   };
 
-  if (r0 < r1) load_chunk(r0);
-  for (int64_t rb = r0; rb < r1; rb += KC) {
-    __syncthreads();
-    store_chunk();
-    __syncthreads();
-    if (rb + KC < r1) load_chunk(rb + KC);
+  if (r0 < r1) {
+    load_chunk(r0);
+    store_chunk(ldsb[0]);
+    if (r0 + KC < r1) load_chunk(r0 + KC);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int64_t rb = r0; rb < r1; rb += KC, cur ^= 1) {
+    const double* lds = ldsb[cur];
 #pragma unroll
     for (int g = 0; g < KC / 16; ++g) {
       const int64_t jbase = rb + 16 * g;
@@ -99,6 +102,9 @@ __device__ __forceinline__ void sketch_f64_body(int64_t m, int n, const double* 
         }
       }
     }
+    if (rb + KC < r1) store_chunk(ldsb[cur ^ 1]);
+    __syncthreads();
+    if (rb + 2 * KC < r1) load_chunk(rb + 2 * KC);
   }
 
   const size_t E = (size_t)it_total * (size_t)jt_total * 256;
