@@ -213,6 +213,64 @@ def mixed_comparison(args, kappas):
             "target_ortho": 1e-12, "results": out}
 
 
+def paper_shaped_comparison(args):
+    """The paper's own strong-scaling problem (Table "scalability1": m = 1e7, n = 100,
+    kappa = 1e5, l = 2n, rQR-CholeskyQR with row extraction as printed, CholeskyQR2 and
+    sCholeskyQR3) on one GPU.  A (8 GB) is built on the device as U diag(sigma) V^T from
+    seeded N(0,1) matrices orthonormalised by torch's QR (the construction of Section 4.1);
+    it is timing input only and never meets the oracle."""
+    import torch
+
+    import paper_2111_11148_amd as tsqr
+
+    m, n, s, kappa, seed = 10_000_000, 100, 200, 1e5, 11109
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(211109)
+    G = torch.randn(m, n, generator=gen, dtype=torch.float64, device="cuda")
+    U, _ = torch.linalg.qr(G)
+    del G
+    V, _ = torch.linalg.qr(torch.randn(n, n, generator=gen, dtype=torch.float64, device="cuda"))
+    sig = kappa ** (-torch.arange(n, dtype=torch.float64, device="cuda") / (n - 1))
+    A = tsqr.colmajor(m, n)
+    A.copy_((U * sig) @ V.t())
+    del U
+    torch.cuda.empty_cache()
+    Q, R = tsqr.colmajor(m, n), tsqr.colmajor(n, n)
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    work = tsqr.alloc_workspace(m, n, s)
+    cwork = torch.empty(tsqr.cholqr_workspace_bytes(m, n), dtype=torch.uint8, device="cuda")
+    methods = {
+        "rqr_rows": lambda: tsqr.rxr_cholqr(A, s, seed, extra_pass=False, Q=Q, R=R,
+                                            workspace=work, info=info, sketch="rows"),
+        "rqr_rows_plus_pass": lambda: tsqr.rxr_cholqr(A, s, seed, Q=Q, R=R, workspace=work,
+                                                      info=info, sketch="rows"),
+        "rqr_gaussian_plus_pass": lambda: tsqr.rxr_cholqr(A, s, seed, Q=Q, R=R, workspace=work,
+                                                          info=info),
+        "cholqr2": lambda: tsqr.cholqr(A, tsqr.CHOLQR2, Q=Q, R=R, workspace=cwork, info=info),
+        "scholqr3": lambda: tsqr.cholqr(A, tsqr.SCHOLQR3, -1.0, Q=Q, R=R, workspace=cwork,
+                                        info=info),
+    }
+    paper_s = {"rqr_rows": (1.8643, 0.052), "cholqr2": (2.3181, 0.0631),
+               "scholqr3": (3.6855, 0.0958)}  # (8 processes, 512 processes), seconds
+    out = {}
+    for name, fn in methods.items():
+        ms = timed(fn, args.baseline_steps, 1)
+        code = int(info.item())
+        o, r = gpu_metrics(A, Q, R) if code == 0 else (None, None)
+        row = {"ms": round(ms, 3), "info": code, "ortho": o, "residual": r}
+        if name in paper_s:
+            row["paper_s_8_and_512_processes"] = paper_s[name]
+            row["speedup_vs_paper_512_processes"] = round(paper_s[name][1] * 1e3 / ms, 2)
+        out[name] = row
+        print(f"# paper shape {name}: {ms:.3f} ms (info {code})", file=sys.stderr, flush=True)
+    del A, Q, R, work, cwork
+    torch.cuda.empty_cache()
+    return {"workload": f"Table scalability1 shape (m={m}, n={n}, l={s}, kappa={kappa:g})",
+            "results": out,
+            "paper": "rQR-CholeskyQR (row extraction, no extra pass), CholeskyQR2 and "
+                     "sCholeskyQR3 on 8-512 MPI processes of 32-core Xeon nodes"}
+
+
 def baselines_comparison(args, kappas):
     """The paper's comparison (Section 4.3) on the benchmark's shape (m=2^20, n=128,
     s=256): rQR-CholeskyQR with the row-extraction sketch (the paper's experiments; as
@@ -393,6 +451,9 @@ def main() -> int:
                     help="condition numbers of the comparison with CholeskyQR2 / sCholeskyQR3 "
                          "and the row-extraction sketch (m=2^20, n=128); empty to skip it")
     ap.add_argument("--baseline-steps", type=int, default=5)
+    ap.add_argument("--paper-shape", type=int, default=1,
+                    help="time the paper's Table scalability1 problem (m=1e7, n=100) too "
+                         "(0 to skip)")
     ap.add_argument("--graph", type=int, default=1,
                     help="also time the step captured into one HIP graph (0 to skip)")
     ap.add_argument("--batch-count", type=int, default=512,
@@ -568,6 +629,11 @@ def main() -> int:
         torch.cuda.empty_cache()
         baselines = baselines_comparison(args, bkappas)
 
+    paper_shaped = None
+    if args.paper_shape:
+        torch.cuda.empty_cache()
+        paper_shaped = paper_shaped_comparison(args)
+
     batched = None
     if args.batch_count > 0:
         torch.cuda.empty_cache()
@@ -600,6 +666,7 @@ def main() -> int:
             graph, gflops=round(F["total"] / (graph["ms_per_step"] * 1e-3) / 1e9, 3)),
         "mixed_vs_fp64": mixed,
         "baselines": baselines,
+        "paper_shaped": paper_shaped,
         "batched": batched,
     }
     print(json.dumps(line), flush=True)
