@@ -89,6 +89,10 @@ __device__ __forceinline__ void sketch_f64_body(int64_t m, int n, const double* 
         const uint64_t p = (uint64_t)(jbase >> 2) + (uint64_t)q;
         sketch_normals4(p, i, k0, k1, z[it]);
       }
+      // raised issue priority while this wave feeds the matrix core, so that the arbiter
+      // prefers MFMA issue over other waves' normal generation (measured: 2^20 x 128,
+      // 1.173 -> 1.162 ms; 2^20 x 64, 0.389 -> 0.374 ms)
+      __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         double bop[JT];
@@ -101,6 +105,7 @@ __device__ __forceinline__ void sketch_f64_body(int64_t m, int n, const double* 
           for (int jt = 0; jt < JT; ++jt) acc[it][jt] = mfma_f64(a, bop[jt], acc[it][jt]);
         }
       }
+      __builtin_amdgcn_s_setprio(0);
     }
     if (rb + KC < r1) store_chunk(ldsb[cur ^ 1]);
     __syncthreads();
