@@ -190,6 +190,9 @@ __device__ __forceinline__ void trsm_mfma_body(int64_t m, int n, const double* _
     };
     const int64_t row = tile * 16 + c16;
     const bool rok = row < m;
+    // raised issue priority during the solve, so that the arbiter prefers this wave's MFMA
+    // chain over other waves' loads and stores (measured: 2^20 x 128, 0.494 -> 0.482 ms)
+    __builtin_amdgcn_s_setprio(1);
 
 #pragma unroll
     for (int b = 0; b < JT; ++b) {
@@ -214,6 +217,7 @@ __device__ __forceinline__ void trsm_mfma_body(int64_t m, int n, const double* _
           xr[bb] = mfma_f64(Aop(off_index(b, bb), kk), xr[b][kk], xr[bb]);
     }
 
+    __builtin_amdgcn_s_setprio(0);
     if (rok) {
       // opaque base and uniform column offsets (per-lane column products would be hoisted)
       double* xb = X + row + (int64_t)(4 * q) * ldx;
