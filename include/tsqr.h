@@ -154,8 +154,9 @@ size_t tsqr_cholqr_workspace_bytes(int64_t m, int64_t n);
  *   m, n, A, lda (2-5): as tsqr_rxr_cholqr_ws;
  *   shift (6): sCholeskyQR3 only: >= 0 is added to the first Gram matrix's diagonal as
  *     given (the paper's experiments use 1e-15 for ||A||_2 = 1); < 0 adds the suggested
- *     11 (m n + n (n + 1)) u ||A||_2^2, u = 2^-53, with ||A||_2^2 bounded above by
- *     ||A^T A||_F (computed on the device, no host wait); NaN is an argument error;
+ *     11 (m n + n (n + 1)) u ||A||_2^2 with u = 2^-52 (the machine precision of Section
+ *     4.1) and ||A||_2^2 bounded above by ||A^T A||_F (computed on the device, no host
+ *     wait); NaN is an argument error;
  *   Q, ldq (7, 8), R, ldr (9, 10): outputs as tsqr_rxr_cholqr_ws;
  *   work, work_bytes (11, 12): at least tsqr_cholqr_workspace_bytes(m, n) bytes;
  *   d_info (13): device int, 1000 * pass + k when pass `pass`'s Cholesky breaks down at

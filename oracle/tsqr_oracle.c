@@ -511,7 +511,8 @@ int or_lstsq_rxr(int variant, int sketch, int64_t m, int64_t n, const double *A,
  * optional diagonal shift on the first Gram matrix G (paper Algorithm sCholeskyQR3 uses a
  * shift with npass = 3): shift > 0 is added as given; shift < 0 adds the paper's suggested
  * 11 (m n + n (n + 1)) u ||A||_2^2 (Section 2.1) with ||A||_2^2 bounded above by ||G||_F
- * and u = 2^-53.  R = R_npass ... R_1.  Returns 0 or 1000*(pass+1) + k. */
+ * and u = 2^-52, the machine precision the paper defines in Section 4.1.
+ * R = R_npass ... R_1.  Returns 0 or 1000*(pass+1) + k. */
 int or_cholqr_n(int64_t m, int64_t n, const double *A, int64_t lda, int npass,
                 double shift, double *Q, int64_t ldq, double *R, int64_t ldr) {
     size_t nn = (size_t)n * (size_t)n;
@@ -528,7 +529,7 @@ int or_cholqr_n(int64_t m, int64_t n, const double *A, int64_t lda, int npass,
         if (pass == 0 && shift != 0.0) {
             double sh = shift;
             if (shift < 0.0)
-                sh = 11.0 * ((double)m * (double)n + (double)n * (double)(n + 1)) * 0x1p-53 *
+                sh = 11.0 * ((double)m * (double)n + (double)n * (double)(n + 1)) * 0x1p-52 *
                      or_fro(n, W, n);
             for (int64_t k = 0; k < n; ++k) W[IDX(k, k, n)] += sh;
         }
@@ -803,7 +804,7 @@ int or_rxr_cholqr_mixed(int variant, int prec, int64_t m, int64_t n, const doubl
             int c = or_cholesky_upper(n, W, n, Rk, n), shifted = 0;
             if (c && fp64_passes == 0) {
                 double shift = 11.0 * ((double)m * (double)n + (double)n * (double)(n + 1)) *
-                               0x1p-53 * sqrt(w2);
+                               0x1p-52 * sqrt(w2);
                 for (int64_t k = 0; k < n; ++k) W[IDX(k, k, n)] += shift;
                 c = or_cholesky_upper(n, W, n, Rk, n);
                 shifted = 1;

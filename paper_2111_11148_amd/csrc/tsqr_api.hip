@@ -34,6 +34,9 @@ namespace {
 constexpr int64_t kMaxSketchRows = 8192;
 constexpr int64_t kMaxN = 1024;     // widest n of the FP64 path
 constexpr int64_t kMaxNLowp = 256;  // widest n of the low-precision kernels
+// u of the suggested sCholeskyQR3 shift 11 (m n + n (n + 1)) u ||A||_2^2 (paper Section 2.1):
+// the machine precision 2^-52 the paper defines for double precision (Section 4.1)
+constexpr double kMachEps = 0x1p-52;
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -296,7 +299,7 @@ int run_cholqr(int npass, bool shifted, int64_t m, int64_t n, const double* A, i
     TSQR_PHASE("gram_reduce", launch_gram_reduce(L.gp, ni, part, W, n, st));
     if (pass == 0 && shifted) {
       if (shift < 0.0) {
-        const double c = 11.0 * ((double)m * (double)n + (double)n * (double)(n + 1)) * 0x1p-53;
+        const double c = 11.0 * ((double)m * (double)n + (double)n * (double)(n + 1)) * kMachEps;
         TSQR_CHECK(launch_pass_decide(ni, W, n, nullptr, nullptr, 0.0, need, dev, st));
         TSQR_PHASE("shift", launch_add_diag(ni, W, n, c, dev + 1, st));  // dev[1] = ||W||_F
       } else {
@@ -505,7 +508,7 @@ int run_chain_mixed(int variant, int lowp, int64_t m, int64_t n, const double* A
       TSQR_CHECK(hipStreamSynchronize(st));
       bool shifted = false;
       if (hpi != 0) {
-        const double u = 0x1p-53;
+        const double u = kMachEps;
         const double shift =
             11.0 * ((double)m * (double)n + (double)n * (double)(n + 1)) * u * hdev[1];
         TSQR_PHASE("potrf_shifted", launch_potrf(ni, W, n, Rk, n, stage, info, fac, st, shift));

@@ -15,22 +15,11 @@ import scipy.stats
 
 import oracle
 from inputs import sigma_logspaced, gen_matrix
+from paper_claims import paper_claims
 
 U64 = 2.0 ** -53  # unit roundoff
 EPS = 2.0 ** -52  # the paper's u (Section 4.1)
 
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_claims.txt")
-
-
-def paper_claims():
-    out = {}
-    for line in open(GOLDEN):
-        line = line.split("#", 1)[0].strip()
-        if not line:
-            continue
-        k, v = (x.strip() for x in line.split("="))
-        out[k] = float(v)
-    return out
 
 
 def F(x):

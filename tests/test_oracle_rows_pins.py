@@ -11,6 +11,7 @@ import scipy.stats
 
 import oracle
 from inputs import gen_matrix
+from paper_claims import paper_claims
 
 U64 = 2.0 ** -53
 
@@ -87,22 +88,31 @@ def test_rows_worst_case_identity_block():
 
 
 def test_suggested_shift_first_factor():
-    """shift < 0 adds 11 (mn + n(n+1)) u ||A^T A||_F to the Gram diagonal: one shifted
-    pass equals the pass with that shift computed here with NumPy, and differs from the
-    pass with twice the shift by the first-order amount."""
+    """shift < 0 adds 11 (mn + n(n+1)) u ||A^T A||_F to the Gram diagonal (Section 2.1),
+    with u the machine precision the paper fixes in Section 4.1 (read from the golden
+    file, not from the oracle).  One shifted pass equals the pass with that shift given
+    explicitly, and is told apart from the pass with u off by a factor of two either way
+    (the unit roundoff 2^-53 in place of 2^-52 is exactly that mistake)."""
+    u = paper_claims()["u"]
+    assert u == 2.0 ** -52
     m, n = 2048, 16
     A = gen_matrix(m, n, 1e3, 8)
     G = A.T @ A
-    sh = 11.0 * (m * n + n * (n + 1)) * U64 * np.linalg.norm(G)
+    sh = 11.0 * (m * n + n * (n + 1)) * u * np.linalg.norm(G)
     _, Ra, ia = oracle.cholqr_n(A, 1, shift=-1.0)
     _, Rb, ib = oracle.cholqr_n(A, 1, shift=sh)
-    _, Rc, ic = oracle.cholqr_n(A, 1, shift=2 * sh)
-    assert ia == ib == ic == 0
+    _, Rh, ih = oracle.cholqr_n(A, 1, shift=sh / 2)
+    _, Rd, idd = oracle.cholqr_n(A, 1, shift=2 * sh)
+    assert ia == ib == ih == idd == 0
     d_ab = np.linalg.norm(Ra - Rb) / np.linalg.norm(Rb)
-    d_ac = np.linalg.norm(Ra - Rc) / np.linalg.norm(Rc)
+    # R^T R = G + shift I: halving or doubling the shift moves R by the first-order amount
+    # (shift / 2) / ||G|| times a factor of order one, far above d_ab
+    d_ah = np.linalg.norm(Ra - Rh) / np.linalg.norm(Rh)
+    d_ad = np.linalg.norm(Ra - Rd) / np.linalg.norm(Rd)
+    first_order = 0.5 * sh / np.linalg.norm(G)
     assert d_ab < 1e-14
-    # R^T R = G + shift I: the first-order change of R is of size shift / ||G|| * cond
-    assert d_ac > 0.05 * sh / np.linalg.norm(G)
+    assert d_ah > 0.05 * first_order and d_ad > 0.05 * first_order
+    assert d_ab < 1e-3 * min(d_ah, d_ad)
 
 
 def test_scholqr3_with_suggested_shift_and_cholqr2_collapse():
