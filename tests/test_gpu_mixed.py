@@ -98,6 +98,15 @@ def test_sketch_lowp_parity(prec, m, n, s):
     print(f"prec={prec} m={m} n={n} s={s}: max err {err.max():.3e}, max err/tol "
           f"{(err / tol).max():.3f}")
     assert np.all(err <= tol)
+    # against the normals the device generates: only the device's FP32 product rounding
+    # and accumulation remain (GAMMA32); products of two FP32 or BF16 numbers are exact
+    # in FP64, so the reference below is exact up to its own FP64 sum (4 m u)
+    Zd = rnd(host(tsqr.sketch_normals(seed, 0, s, 0, m)), prec)
+    ref = rs * (Zd @ rnd(A, prec))
+    tol_d = rs * GAMMA32 * (np.abs(Zd) @ Ap) + 4 * m * U * np.abs(ref)
+    err_d = np.abs(Bg - ref)
+    print(f"  against device normals: max err/tol {(err_d / tol_d).max():.3f}")
+    assert np.all(err_d <= tol_d)
 
 
 def test_sketch_lowp_leading_dimension_and_determinism():

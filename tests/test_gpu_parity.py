@@ -14,6 +14,7 @@ import oracle
 import paper_2111_11148_amd as tsqr
 from inputs import gen_matrix
 from gpu_helpers import gpu_orthogonality, gpu_residual, host, rel_fro
+from sketch_bounds import fp64_sketch_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -69,7 +70,12 @@ def test_sketch_normals_match_oracle(i0, ni, j0, nj):
                                    (777, 1, 1), (2050, 100, 100), (513, 64, 129), (4100, 200, 400),
                                    (2000, 600, 1200)])
 def test_sketch_parity(m, n, s):
-    """|B_gpu - B_or| <= rs * (NORMAL_ABS_TOL sum_j |A_jc| + 4 m u sum_j |z_ij A_jc|)."""
+    """Against the oracle: |B_gpu - B_or| <= rs (NORMAL_ABS_TOL sum_j |A_jc| +
+    4 m u sum_j |z_ij A_jc|), where the first term is the device normals' FP32 evaluation.
+    FP64 arithmetic of the product (a property of the device path): B_gpu equals
+    rs (Z_dev A) for the normals Z_dev the device generates (read through the normals
+    accessor) to within the FP64 summation bound 4 m u |Z_dev||A|, which an FP32 product
+    fails by orders of magnitude (tests/test_sketch_bounds.py)."""
     A = gen_matrix(m, n, 1e6, 300 + m)
     seed = 7 + n
     Bg = host(tsqr.sketch(dev(A), s, seed))
@@ -78,6 +84,12 @@ def test_sketch_parity(m, n, s):
     rs = 1.0 / math.sqrt(s)
     tol = rs * (NORMAL_ABS_TOL * np.abs(A).sum(axis=0)[None, :] + 4 * m * U * (np.abs(Z) @ np.abs(A)))
     assert np.all(np.abs(Bg - Bo) <= tol)
+    Zd = host(tsqr.sketch_normals(seed, 0, s, 0, m))
+    ref = rs * (Zd @ A)
+    tol64 = fp64_sketch_tol(Zd, A, s, ref)
+    err = np.abs(Bg - ref)
+    print(f"m={m} n={n} s={s}: max |B - rs Z_dev A| / fp64 bound = {(err / tol64).max():.3e}")
+    assert np.all(err <= tol64)
 
 
 def test_sketch_leading_dimension_and_determinism():
@@ -370,7 +382,8 @@ def test_end_to_end_tall128_full_size(tall128, variant):
 
 
 def test_tall128_sketch_sampled_rows(tall128):
-    """Rows of the full-size sketch against the oracle's normals, one row at a time."""
+    """Rows of the full-size sketch against the oracle's normals, one row at a time, and
+    against the device's own normals at the FP64 summation bound."""
     A, Ad, s = tall128
     m = A.shape[0]
     Bg = host(tsqr.sketch(Ad, s, 11102))
@@ -381,6 +394,12 @@ def test_tall128_sketch_sampled_rows(tall128):
         exact = rs * (z @ A)
         tol = rs * (NORMAL_ABS_TOL * absA.sum(axis=0) + 4 * m * U * (np.abs(z) @ absA))
         assert np.all(np.abs(Bg[i] - exact) <= tol), i
+        # FP64 arithmetic of the product, against the normals the device generates
+        zd = host(tsqr.sketch_normals(11102, i, 1, 0, m))
+        ref = rs * (zd @ A)
+        tol64 = fp64_sketch_tol(zd, A, s, ref)
+        print(f"row {i}: max |B - rs z_dev A| / fp64 bound = {(np.abs(Bg[i] - ref[0]) / tol64[0]).max():.3e}")
+        assert np.all(np.abs(Bg[i] - ref[0]) <= tol64[0]), i
 
 
 def test_end_to_end_plain_forms_and_rless():
