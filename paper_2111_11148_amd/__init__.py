@@ -11,7 +11,10 @@ strides (1, ld), ld >= m (see :func:`colmajor`).
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
+import functools
+import inspect
 import os
 
 import torch
@@ -116,6 +119,22 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _on_stream(fn):
+    """Run `fn` with its `stream` argument (when given) as torch's current stream, so that
+    every tensor it allocates (outputs, workspace, info) comes from that stream's pool of
+    the caching allocator: a temporary freed on return is then not handed to work on
+    another stream while this call's kernels still use it."""
+    sig = inspect.signature(fn)
+
+    @functools.wraps(fn)
+    def wrapper(*args, **kwargs):
+        stream = sig.bind(*args, **kwargs).arguments.get("stream")
+        ctx = torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+        with ctx:
+            return fn(*args, **kwargs)
+    return wrapper
+
+
 def _mat(t: torch.Tensor, name: str, rows: int | None = None, cols: int | None = None) -> int:
     """Validate a column-major FP64 device matrix; return its leading dimension."""
     if not isinstance(t, torch.Tensor):
@@ -191,6 +210,7 @@ def alloc_workspace(m: int, n: int, sketch_rows: int, device="cuda") -> torch.Te
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
+@_on_stream
 def rxr_cholqr(A: torch.Tensor, sketch_rows: int, seed: int, variant: int = RQR,
                extra_pass: bool = True, Q: torch.Tensor | None = None,
                R: torch.Tensor | None = None, want_r: bool = True,
@@ -229,6 +249,7 @@ CHOLQR2 = 2
 SCHOLQR3 = 3
 
 
+@_on_stream
 def lstsq(A: torch.Tensor, b: torch.Tensor, sketch_rows: int, seed: int, variant: int = RQR,
           sketch: str = "gaussian", x: torch.Tensor | None = None,
           workspace: torch.Tensor | None = None, info: torch.Tensor | None = None, stream=None):
@@ -258,6 +279,7 @@ def cholqr_workspace_bytes(m: int, n: int) -> int:
     return int(load().tsqr_cholqr_workspace_bytes(m, n))
 
 
+@_on_stream
 def cholqr(A: torch.Tensor, algo: int = CHOLQR2, shift: float = -1.0,
            Q: torch.Tensor | None = None, R: torch.Tensor | None = None, want_r: bool = True,
            workspace: torch.Tensor | None = None, info: torch.Tensor | None = None,
@@ -293,6 +315,7 @@ def mixed_workspace_bytes(m: int, n: int, sketch_rows: int, lowp: int) -> int:
     return int(load().tsqr_mixed_workspace_bytes(m, n, sketch_rows, lowp))
 
 
+@_on_stream
 def rxr_cholqr_mixed(A: torch.Tensor, sketch_rows: int, seed: int, lowp: int = FP32,
                      variant: int = RQR, fp64_passes: int = 0, Q: torch.Tensor | None = None,
                      R: torch.Tensor | None = None, want_r: bool = True,
@@ -327,6 +350,7 @@ def rxr_cholqr_mixed(A: torch.Tensor, sketch_rows: int, seed: int, lowp: int = F
     return Q, R, info, passes.value
 
 
+@_on_stream
 def sketch_lowp(A: torch.Tensor, s: int, seed: int, lowp: int = FP32, stream=None):
     lda = _mat(A, "A")
     m, n = A.shape
@@ -338,6 +362,7 @@ def sketch_lowp(A: torch.Tensor, s: int, seed: int, lowp: int = FP32, stream=Non
     return B
 
 
+@_on_stream
 def apply_rinv_lowp(Y: torch.Tensor, Rinv: torch.Tensor, lowp: int = FP32, stream=None):
     """X = r(Y) r(Rinv) in the low-precision type (float32 or bfloat16 tensor, column-major)."""
     ldy = _mat(Y, "Y")
@@ -352,6 +377,7 @@ def apply_rinv_lowp(Y: torch.Tensor, Rinv: torch.Tensor, lowp: int = FP32, strea
     return X
 
 
+@_on_stream
 def gram_lowp(X: torch.Tensor, lowp: int = FP32, stream=None) -> torch.Tensor:
     want = torch.float32 if lowp == FP32 else torch.bfloat16
     if X.dtype != want or X.device.type != "cuda" or X.dim() != 2:
@@ -368,6 +394,7 @@ def gram_lowp(X: torch.Tensor, lowp: int = FP32, stream=None) -> torch.Tensor:
     return W
 
 
+@_on_stream
 def rqr_cholqr(A: torch.Tensor, sketch_rows: int, seed: int, stream=None):
     """Plain form of the C ABI (stream-ordered scratch allocation, extra pass on)."""
     lda = _mat(A, "A")
@@ -379,6 +406,7 @@ def rqr_cholqr(A: torch.Tensor, sketch_rows: int, seed: int, stream=None):
     return Q, R
 
 
+@_on_stream
 def rlu_cholqr(A: torch.Tensor, sketch_rows: int, seed: int, stream=None):
     lda = _mat(A, "A")
     m, n = A.shape
@@ -390,6 +418,7 @@ def rlu_cholqr(A: torch.Tensor, sketch_rows: int, seed: int, stream=None):
 
 
 # ------------------------------------------------------------------------- steps ----
+@_on_stream
 def sketch(A: torch.Tensor, s: int, seed: int, stream=None) -> torch.Tensor:
     lda = _mat(A, "A")
     m, n = A.shape
@@ -401,6 +430,7 @@ def sketch(A: torch.Tensor, s: int, seed: int, stream=None) -> torch.Tensor:
     return B
 
 
+@_on_stream
 def sketch_rows(A: torch.Tensor, s: int, seed: int, stream=None) -> torch.Tensor:
     """B = A(rows, :), the row-extraction sketch (s x n)."""
     lda = _mat(A, "A")
@@ -411,6 +441,7 @@ def sketch_rows(A: torch.Tensor, s: int, seed: int, stream=None) -> torch.Tensor
     return B
 
 
+@_on_stream
 def sketch_factor(B: torch.Tensor, variant: int = RQR, stream=None):
     ldb = _mat(B, "B")
     s, n = B.shape
@@ -424,6 +455,7 @@ def sketch_factor(B: torch.Tensor, variant: int = RQR, stream=None):
     return R0, info
 
 
+@_on_stream
 def trsm(Y: torch.Tensor, T: torch.Tensor, X: torch.Tensor | None = None, stream=None):
     ldy = _mat(Y, "Y")
     m, n = Y.shape
@@ -438,6 +470,7 @@ def trsm(Y: torch.Tensor, T: torch.Tensor, X: torch.Tensor | None = None, stream
     return X
 
 
+@_on_stream
 def gram(X: torch.Tensor, stream=None) -> torch.Tensor:
     ldx = _mat(X, "X")
     m, n = X.shape
@@ -449,6 +482,7 @@ def gram(X: torch.Tensor, stream=None) -> torch.Tensor:
     return W
 
 
+@_on_stream
 def potrf(W: torch.Tensor, stage: int = 2, stream=None):
     ldw = _mat(W, "W")
     n = W.shape[0]
@@ -459,6 +493,7 @@ def potrf(W: torch.Tensor, stage: int = 2, stream=None):
     return R, info
 
 
+@_on_stream
 def trmm_upper(A: torch.Tensor, B: torch.Tensor, stream=None) -> torch.Tensor:
     lda = _mat(A, "A")
     n = A.shape[0]
@@ -469,6 +504,7 @@ def trmm_upper(A: torch.Tensor, B: torch.Tensor, stream=None) -> torch.Tensor:
     return C
 
 
+@_on_stream
 def philox4x32_10(ctr: torch.Tensor, seed: int, stream=None) -> torch.Tensor:
     """ctr: (count, 4) int32 device tensor holding the counter words (bit patterns)."""
     if ctr.dtype != torch.int32 or ctr.device.type != "cuda" or ctr.dim() != 2 or ctr.shape[1] != 4:
@@ -480,6 +516,7 @@ def philox4x32_10(ctr: torch.Tensor, seed: int, stream=None) -> torch.Tensor:
     return out
 
 
+@_on_stream
 def sketch_normals(seed: int, i0: int, ni: int, j0: int, nj: int, device="cuda",
                    stream=None) -> torch.Tensor:
     Z = colmajor(ni, nj, device=device)

@@ -123,10 +123,7 @@ __global__ __launch_bounds__(256) void k_trsm_prep(int n, int jt, const double* 
 // TRSM launch shape: 16 wavefronts per workgroup, each tile loaded at the start of its own
 // iteration (measured: loading the next tile one iteration ahead, with 8 wavefronts for
 // the registers it needs, is not faster)
-#ifndef TSQR_TRSM_PF
-#define TSQR_TRSM_PF 0
-#define TSQR_TRSM_THREADS 1024
-#endif
+constexpr int kTrsmThreads = 1024;
 // Body of workgroup `wg` of `nwg` (persistent over 16-row tiles).
 template <int JT, bool kLds>
 __device__ __forceinline__ void trsm_mfma_body(int64_t m, int n, const double* __restrict__ Y,
@@ -171,14 +168,8 @@ __device__ __forceinline__ void trsm_mfma_body(int64_t m, int n, const double* _
 
   int64_t tile = (int64_t)wg * nw + wave_id();
   v4d xr[JT];
-  if (TSQR_TRSM_PF && tile < ntiles) load_tile(tile, xr);
   for (; tile < ntiles; tile += wstride) {
-    // the next tile's loads are in flight while this tile is solved (the last tile
-    // re-reads itself instead: always a valid address)
-    const int64_t nxt = tile + wstride < ntiles ? tile + wstride : tile;
-    v4d xn[JT];
-    if (TSQR_TRSM_PF) load_tile(nxt, xn);
-    else load_tile(tile, xr);
+    load_tile(tile, xr);
     // opaque per-iteration bases: the tiles are loop invariant and would otherwise be
     // hoisted into registers
     lds_f64* tlp = (lds_f64*)tl;
@@ -229,200 +220,18 @@ __device__ __forceinline__ void trsm_mfma_body(int64_t m, int n, const double* _
         for (int r = 0; r < 4; ++r)
           if (16 * b + 4 * q + r < n) xb[(16 * b + r) * xs] = xr[b][r];
     }
-    if (TSQR_TRSM_PF)
-#pragma unroll
-      for (int b = 0; b < JT; ++b) xr[b] = xn[b];
   }
 }
 
 template <int JT, bool kLds>
-__global__ __launch_bounds__(TSQR_TRSM_THREADS, 1) void k_trsm_mfma(int64_t m, int n,
+__global__ __launch_bounds__(kTrsmThreads, 1) void k_trsm_mfma(int64_t m, int n,
                                                       const double* __restrict__ Y, int64_t ldy,
                                                       const double* __restrict__ P,
                                                       double* X, int64_t ldx) {
   trsm_mfma_body<JT, kLds>(m, n, Y, ldy, P, X, ldx, (int)blockIdx.x, (int)gridDim.x);
 }
 
-// ------------------------------------------------------------------------------------
-// Off-diagonal update of the column-blocked solve: C = Y - X T for a kBlk x nb block T of
-// the triangular factor (nb <= kBlk), X m x kBlk (a solved block), Y and C m x nb.
-// T is staged once per workgroup in LDS (row-major, padded); each wavefront owns 16-row
-// tiles and computes the transposed product C^T(16b.., rows) = T^T X^T on FP64 MFMA:
-// A operand = T(k, 16b + l%16) from LDS, B operand = X(row, k) from global memory, and
-// accumulator register r of lane l is C(row l%16, 16b + 4r + l/16).  C may alias Y (each
-// wavefront reads its whole tile before writing it).
-// ------------------------------------------------------------------------------------
 constexpr int kBlk = 128;  // column block of the blocked solve
-
-__global__ __launch_bounds__(512) void k_trsm_update(int64_t m, int nb,
-                                                     const double* __restrict__ X, int64_t ldx,
-                                                     const double* __restrict__ T, int64_t ldt,
-                                                     const double* Y, int64_t ldy, double* C,
-                                                     int64_t ldc) {
-  constexpr int NB = kBlk / 16;  // column tiles of C
-  constexpr int KS = kBlk / 4;   // MFMA K-steps
-  constexpr int LDT = kBlk + 1;
-  extern __shared__ double ts[];  // kBlk x LDT
-  for (int e = threadIdx.x; e < kBlk * kBlk; e += blockDim.x) {
-    const int k = e % kBlk, c = e / kBlk;
-    ts[k * LDT + c] = (c < nb) ? T[(int64_t)c * ldt + k] : 0.0;
-  }
-  __syncthreads();
-
-  const int lane = lane_id();
-  const int q = lane >> 4, c16 = lane & 15;
-  const int64_t ntiles = (m + 15) / 16;
-  const int nw = blockDim.x / kWave;
-  const int64_t wstride = (int64_t)gridDim.x * nw;
-  // X(row, k) for k = 4kk + q, in chunks of KC K-steps; chunk c+1 is loaded while chunk c
-  // feeds the matrix cores, and the next tile's first chunk while the last one does
-  constexpr int KC = 8;
-  auto load_x = [&](int64_t t, int c, double (&xb)[KC]) {
-    const int64_t row = t * 16 + c16;
-    // per-lane base (row, column q of the chunk), then uniform strides of 4 columns
-    const double* xp = X + (int64_t)(4 * c * KC + q) * ldx + (row < m ? row : 0);
-    int64_t xs = ldx;
-    asm volatile("" : "+v"(xp), "+s"(xs));
-#pragma unroll
-    for (int j = 0; j < KC; ++j) xb[j] = xp[(4 * j) * xs];
-  };
-  int64_t tile = (int64_t)blockIdx.x * nw + wave_id();
-  double xa[KC], xn[KC];
-  if (tile < ntiles) load_x(tile, 0, xa);
-  for (; tile < ntiles; tile += wstride) {
-    const int64_t nxt = tile + wstride < ntiles ? tile + wstride : tile;  // valid address
-    const int64_t row = tile * 16 + c16;
-    const bool rok = row < m;
-    const int64_t rowc = rok ? row : 0;  // clamped, always a valid address
-    // Y(row, 16b + 4r + q) for the whole tile, issued now and used at the end; a column
-    // past nb reads column 0 (valid) and is never stored
-    double yv[NB][4];
-    {
-      const double* yp = Y + (int64_t)q * ldy + rowc;
-      int64_t ys = ldy;
-      int lim = nb - q;
-      asm volatile("" : "+v"(yp), "+s"(ys), "+v"(lim));
-      const int64_t back = -(int64_t)q * ys;
-#pragma unroll
-      for (int b = 0; b < NB; ++b)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int c0 = 16 * b + 4 * r;
-          yv[b][r] = yp[c0 < lim ? c0 * ys : back];
-        }
-    }
-    v4d acc[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) acc[b] = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int c = 0; c < KS / KC; ++c) {
-      if (c + 1 < KS / KC) load_x(tile, c + 1, xn);
-      else load_x(nxt, 0, xn);
-#pragma unroll
-      for (int j = 0; j < KC; ++j) {
-        // opaque per-step row pointer: keeps the step's operand reads next to its MFMAs
-        const lds_f64* tp = (const lds_f64*)ts + (4 * (c * KC + j) + q) * LDT + c16;
-        asm volatile("" : "+v"(tp));
-        const double xv = rok ? xa[j] : 0.0;
-#pragma unroll
-        for (int b = 0; b < NB; ++b) acc[b] = mfma_f64(tp[16 * b], xv, acc[b]);
-      }
-#pragma unroll
-      for (int j = 0; j < KC; ++j) xa[j] = xn[j];
-    }
-    if (rok) {
-      double* cp = C + (int64_t)q * ldc + row;
-      int64_t cs = ldc;
-      asm volatile("" : "+v"(cp), "+s"(cs));
-#pragma unroll
-      for (int b = 0; b < NB; ++b)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (16 * b + 4 * r + q < nb) cp[(16 * b + 4 * r) * cs] = yv[b][r] - acc[b][r];
-    }
-  }
-}
-
-// The same update against all earlier blocks at once, C = Y - X T for X of K = k0 columns
-// (the solved blocks) and the k0 x nb block column T(0:k0, block): one read of X instead of
-// one pass over C per earlier block.  A workgroup of 16 wavefronts holds 256 rows of C in
-// registers (one 16-row tile per wavefront) while T streams through LDS in 128-row
-// chunks; Y is read at the end.  K is a multiple of kBlk.
-__global__ __launch_bounds__(1024) void k_trsm_update_k(int64_t m, int nb, int K,
-                                                        const double* __restrict__ X,
-                                                        int64_t ldx, const double* __restrict__ T,
-                                                        int64_t ldt, const double* Y, int64_t ldy,
-                                                        double* C, int64_t ldc) {
-  constexpr int NB = kBlk / 16;  // column tiles of C
-  constexpr int KS = kBlk / 4;   // MFMA K-steps per chunk
-  constexpr int LDT = kBlk + 1;
-  constexpr int KC = 8;
-  extern __shared__ double ts[];  // kBlk x LDT
-  const int lane = lane_id();
-  const int q = lane >> 4, c16 = lane & 15;
-  const int64_t tile = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
-  const int64_t ntiles = (m + 15) / 16;
-  const bool tok = tile < ntiles;
-  const int64_t row = (tok ? tile : 0) * 16 + c16;
-  const bool rok = tok && row < m;
-  const int64_t rowc = rok ? row : 0;  // clamped, always a valid address
-  auto load_x = [&](int kc, int c, double (&xb)[KC]) {
-    const double* xp = X + (int64_t)(kc + 4 * c * KC + q) * ldx + rowc;
-    int64_t xs = ldx;
-    asm volatile("" : "+v"(xp), "+s"(xs));
-#pragma unroll
-    for (int j = 0; j < KC; ++j) xb[j] = xp[(4 * j) * xs];
-  };
-  v4d acc[NB];
-#pragma unroll
-  for (int b = 0; b < NB; ++b) acc[b] = v4d{0.0, 0.0, 0.0, 0.0};
-  double xa[KC], xn[KC];
-  load_x(0, 0, xa);
-  for (int kc = 0; kc < K; kc += kBlk) {
-    __syncthreads();  // every wavefront is done with the previous chunk of T
-    for (int e = threadIdx.x; e < kBlk * kBlk; e += blockDim.x) {
-      const int k = e % kBlk, c = e / kBlk;
-      ts[k * LDT + c] = (c < nb) ? T[(int64_t)c * ldt + kc + k] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < KS / KC; ++c) {
-      // next X chunk: the rest of this block of K, then the next block's first (the last
-      // chunk re-reads itself: always a valid address)
-      if (c + 1 < KS / KC) load_x(kc, c + 1, xn);
-      else load_x(kc + kBlk < K ? kc + kBlk : kc, 0, xn);
-#pragma unroll
-      for (int j = 0; j < KC; ++j) {
-        const lds_f64* tp = (const lds_f64*)ts + (4 * (c * KC + j) + q) * LDT + c16;
-        asm volatile("" : "+v"(tp));
-        const double xv = rok ? xa[j] : 0.0;
-#pragma unroll
-        for (int b = 0; b < NB; ++b) acc[b] = mfma_f64(tp[16 * b], xv, acc[b]);
-      }
-#pragma unroll
-      for (int j = 0; j < KC; ++j) xa[j] = xn[j];
-    }
-  }
-  if (rok) {
-    // Y(row, 16b + 4r + q); a column past nb is neither read nor stored
-    const double* yp = Y + (int64_t)q * ldy + row;
-    double* cp = C + (int64_t)q * ldc + row;
-    int64_t ys = ldy, cs = ldc;
-    asm volatile("" : "+v"(yp), "+v"(cp), "+s"(ys), "+s"(cs));
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      double yv[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const bool ok = 16 * b + 4 * r + q < nb;
-        yv[r] = yp[ok ? (16 * b + 4 * r) * ys : 0];
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (16 * b + 4 * r + q < nb) cp[(16 * b + 4 * r) * cs] = yv[r] - acc[b][r];
-    }
-  }
-}
 
 // A later column block of the blocked solve in one pass: C = Y - X0 T(0:K, block) against
 // all solved blocks, then the block's own substitution, without writing C.  Persistent
@@ -556,76 +365,38 @@ static hipError_t launch_trsm_block(int64_t m, int n, const double* Y, int64_t l
                                     const double* T, int64_t ldt, double* X, int64_t ldx,
                                     double* scratch, hipStream_t st);
 
-// X = Y T^{-1}.  Up to kBlk columns: one substitution kernel.  Wider: by column blocks,
-// X_k = (Y_k - sum_{j<k} X_j T_jk) T_kk^{-1} (the update kernel, then the substitution of
-// the diagonal block in place).
-#ifndef TSQR_TRSM_UPDATE_K
-#define TSQR_TRSM_UPDATE_K 1
-#endif
-constexpr bool kTrsmUpdateK = TSQR_TRSM_UPDATE_K;
-#ifndef TSQR_TRSM_FUSED
-#define TSQR_TRSM_FUSED 1
-#endif
-constexpr bool kTrsmFused = TSQR_TRSM_FUSED;
-
+// X = Y T^{-1}.  Up to kBlk columns: one substitution kernel.  Wider: by column blocks of
+// kBlk; the first block is the substitution kernel, every later block one pass of
+// k_trsm_fused (update against all solved blocks, then the block's own substitution).
 hipError_t launch_trsm(int64_t m, int n, const double* Y, int64_t ldy, const double* T,
                        int64_t ldt, double* X, int64_t ldx, double* scratch, hipStream_t st) {
   if (m <= 0 || n <= 0) return hipSuccess;
   if (n <= kBlk) return launch_trsm_block(m, n, Y, ldy, T, ldt, X, ldx, scratch, st);
   const int64_t ntiles = (m + 15) / 16;
-  int64_t ublocks = (ntiles + 7) / 8;
   const int64_t cap = (int64_t)device_cu_count();
-  if (ublocks > cap) ublocks = cap;
-  const size_t ush = (size_t)kBlk * (kBlk + 1) * sizeof(double);
-  for (int k0 = 0; k0 < n; k0 += kBlk) {
+  hipError_t e = launch_trsm_block(m, kBlk, Y, ldy, T, ldt, X, ldx, scratch, st);
+  if (e != hipSuccess) return e;
+  for (int k0 = kBlk; k0 < n; k0 += kBlk) {
     const int nbk = (n - k0) < kBlk ? (n - k0) : kBlk;
-    if (k0 >= kBlk && kTrsmFused) {
-      // update against all solved blocks and this block's substitution in one pass
-      int jt = 1;
-      while (jt < (nbk + 15) / 16) jt <<= 1;
-      hipLaunchKernelGGL(k_trsm_prep, dim3(jt), dim3(256), 0, st, nbk, jt,
-                         T + (int64_t)k0 * ldt + k0, ldt, scratch);
-      hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
-      const int64_t ngroups = (ntiles + 15) / 16;
-      const int64_t grid = ngroups < cap ? ngroups : cap;
-      const double* yk = Y + (int64_t)k0 * ldy;
-      double* xk = X + (int64_t)k0 * ldx;
+    int jt = 1;
+    while (jt < (nbk + 15) / 16) jt <<= 1;
+    hipLaunchKernelGGL(k_trsm_prep, dim3(jt), dim3(256), 0, st, nbk, jt,
+                       T + (int64_t)k0 * ldt + k0, ldt, scratch);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t ngroups = (ntiles + 15) / 16;
+    const int64_t grid = ngroups < cap ? ngroups : cap;
+    const double* yk = Y + (int64_t)k0 * ldy;
+    double* xk = X + (int64_t)k0 * ldx;
 #define TSQR_TF(J)                                                                             \
   if (jt == J) {                                                                               \
     const size_t sh = ((size_t)(J * (J - 1) / 2 + 2 * J) * 256 + 32 * (16 * J + 1)) * sizeof(double); \
     hipLaunchKernelGGL(k_trsm_fused<J>, dim3((unsigned)grid), dim3(1024), sh, st, m, nbk, k0, X,  \
                        ldx, T + (int64_t)k0 * ldt, ldt, yk, ldy, scratch, xk, ldx);             \
   }
-      TSQR_TF(1) TSQR_TF(2) TSQR_TF(4) TSQR_TF(8)
+    TSQR_TF(1) TSQR_TF(2) TSQR_TF(4) TSQR_TF(8)
 #undef TSQR_TF
-      e = hipGetLastError();
-      if (e != hipSuccess) return e;
-      continue;
-    }
-    if (k0 >= 2 * kBlk && kTrsmUpdateK) {
-      // all earlier blocks in one pass: X(:, 0:k0) read once
-      const int64_t wgs = (ntiles + 15) / 16;
-      hipLaunchKernelGGL(k_trsm_update_k, dim3((unsigned)wgs), dim3(1024), ush, st, m, nbk, k0,
-                         X, ldx, T + (int64_t)k0 * ldt, ldt, Y + (int64_t)k0 * ldy, ldy,
-                         X + (int64_t)k0 * ldx, ldx);
-      const hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    } else
-    for (int j0 = 0; j0 < k0; j0 += kBlk) {
-      const double* src = (j0 == 0) ? Y + (int64_t)k0 * ldy : X + (int64_t)k0 * ldx;
-      const int64_t lds_ = (j0 == 0) ? ldy : ldx;
-      hipLaunchKernelGGL(k_trsm_update, dim3((unsigned)ublocks), dim3(512), ush, st, m, nbk,
-                         X + (int64_t)j0 * ldx, ldx, T + (int64_t)k0 * ldt + j0, ldt, src, lds_,
-                         X + (int64_t)k0 * ldx, ldx);
-      const hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    }
-    const double* src = (k0 == 0) ? Y : X;
-    const int64_t lds_ = (k0 == 0) ? ldy : ldx;
-    const hipError_t e = launch_trsm_block(m, nbk, src + (int64_t)k0 * lds_, lds_,
-                                           T + (int64_t)k0 * ldt + k0, ldt,
-                                           X + (int64_t)k0 * ldx, ldx, scratch, st);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -641,10 +412,10 @@ static hipError_t launch_trsm_block(int64_t m, int n, const double* Y, int64_t l
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t ntiles = (m + 15) / 16;
-  int64_t blocks = (ntiles + TSQR_TRSM_THREADS / 64 - 1) / (TSQR_TRSM_THREADS / 64);
+  int64_t blocks = (ntiles + kTrsmThreads / 64 - 1) / (kTrsmThreads / 64);
   const int64_t cap = (int64_t)device_cu_count();
   if (blocks > cap) blocks = cap;
-  dim3 grid((unsigned)blocks), block(TSQR_TRSM_THREADS);
+  dim3 grid((unsigned)blocks), block(kTrsmThreads);
 #define TSQR_TRSM(J, L)                                                                    \
   if (jt == J) {                                                                           \
     const size_t sh = L ? (size_t)(J * (J - 1) / 2 + 2 * J) * 256 * sizeof(double) : 0;    \

@@ -167,6 +167,27 @@ def test_trsm_parity(m, n):
     assert rel_fro(Xg, Xo) <= 10 * n * EPS * 1e3
 
 
+@pytest.mark.parametrize("n,kappa", [(64, 1e14), (128, 1e14), (128, 1e12), (200, 1e13)])
+def test_trsm_ill_conditioned_sketch_factor(n, kappa):
+    """T = R0 of the sketch of an ill-conditioned A (as in the first solve of the chain):
+    its 16 x 16 diagonal blocks are ill-conditioned, so the solve takes the correction
+    step after multiplying by their inverses.  The row-wise backward error stays at the
+    substitution's level, |A - X T| <= 8 n u |X||T|, and X = A T^{-1} is well conditioned
+    (the preconditioning of the paper's Section 3: cond(X) = cond(S Q_A) = O(1))."""
+    m, s = 20000, 2 * n
+    A = gen_matrix(m, n, kappa, 900 + n)
+    T, info = oracle.householder_r(oracle.sketch_apply(A, s, 31 + n))
+    assert info == 0
+    Xg = host(tsqr.trsm(dev(A), dev(T)))
+    back = np.abs(A - Xg @ T)
+    ratio = back / (n * U * (np.abs(Xg) @ np.abs(T)) + 1e-300)
+    sv = np.linalg.svd(Xg, compute_uv=False)
+    print(f"n={n} kappa={kappa:g}: cond(T)={np.linalg.cond(T):.2e}, max backward error "
+          f"/ (n u |X||T|) = {ratio.max():.3f}, cond(X) = {sv[0] / sv[-1]:.2f}")
+    assert ratio.max() <= 8
+    assert sv[0] / sv[-1] < 50
+
+
 @pytest.mark.parametrize("n", [64, 200])
 def test_trsm_in_place_and_ld(n):
     m = 3000
