@@ -36,8 +36,8 @@ METRIC = "tall-skinny QR GFLOP/s + roofline %, m=2^20 n=128; mixed vs FP64 at or
 # Kernel sources whose counter readings profiles/traffic_*.json refer to.
 KERNEL_SOURCES = {
     "sketch": ["paper_2111_11148_amd/csrc/k_sketch.hip", "paper_2111_11148_amd/csrc/tsqr_device.hpp"],
-    "trsm_r0": ["paper_2111_11148_amd/csrc/k_tall.hip", "paper_2111_11148_amd/csrc/tsqr_device.hpp"],
-    "gram1": ["paper_2111_11148_amd/csrc/k_tall.hip", "paper_2111_11148_amd/csrc/tsqr_device.hpp"],
+    "trsm": ["paper_2111_11148_amd/csrc/k_tall.hip", "paper_2111_11148_amd/csrc/tsqr_device.hpp"],
+    "gram": ["paper_2111_11148_amd/csrc/k_tall.hip", "paper_2111_11148_amd/csrc/tsqr_device.hpp"],
 }
 
 
@@ -81,23 +81,19 @@ def load_traffic(kernel: str, workload: str):
 
 
 def gpu_metrics(A, Q, R):
-    """Orthogonality and residual with blocked FP64 products on the device."""
-    import torch
+    """Orthogonality ||Q^T Q - I||_F and residual ||A - QR||_F / ||A||_F, evaluated on the
+    device with double-double accumulation (the library's metric kernels)."""
+    import paper_2111_11148_amd as tsqr
 
-    m, n = A.shape
-    G = None
-    num = den = None
-    Rc = R.contiguous()
-    for r0 in range(0, m, 4096):
-        q = Q[r0:r0 + 4096].contiguous()
-        g = q.t().contiguous() @ q
-        G = g if G is None else G + g
-        a = A[r0:r0 + 4096]
-        e = a - q @ Rc
-        num = (e * e).sum() if num is None else num + (e * e).sum()
-        den = (a * a).sum() if den is None else den + (a * a).sum()
-    G -= torch.eye(n, dtype=G.dtype, device=G.device)
-    return float(torch.linalg.matrix_norm(G)), float(torch.sqrt(num) / torch.sqrt(den))
+    return tsqr.metrics(Q, A, R)
+
+
+def rel_r_diff(R_dev, R_ref) -> float:
+    """||R - R_ref||_F / ||R_ref||_F against a host reference."""
+    import numpy as np
+
+    Rh = np.asarray(R_dev.cpu().numpy(), dtype=np.float64)
+    return float(np.linalg.norm(Rh - R_ref) / np.linalg.norm(R_ref))
 
 
 def cached_matrix(cache_dir, name, m, n, kappa, seed):
@@ -173,8 +169,20 @@ def mixed_comparison(args, kappas):
         j = list(wl.kappas).index(kappa)
         A_h = cached_matrix(args.cache_dir, wl.name, m, n, kappa, wl.gen_seeds[j])
         A = tsqr.to_device_colmajor(np.asarray(A_h))
-        del A_h
         row = {"kappa": kappa}
+        R_or = None
+        if args.mixed_oracle:
+            # the FP64 oracle's R of the same matrix: every result's R is stated against it
+            import oracle
+
+            t0 = time.perf_counter()
+            ref = oracle.rxr_cholqr(np.asfortranarray(A_h), s, seed, variant=oracle.RQR,
+                                    extra_pass=True)
+            R_or = ref["R"]
+            row["fp64_oracle"] = {"seconds": round(time.perf_counter() - t0, 2),
+                                  "info": int(ref["info"]), "cores": oracle.num_threads()}
+            del ref
+        del A_h
 
         def fp64():
             tsqr.rxr_cholqr(A, s, seed, Q=Q, R=R, workspace=work64, info=info)
@@ -182,7 +190,9 @@ def mixed_comparison(args, kappas):
         ms = timed(fp64, args.mixed_steps, 2)
         ortho, res = gpu_metrics(A, Q, R)
         row["fp64"] = {"ms": round(ms, 4), "gflops": round(F / ms / 1e6, 2), "ortho": ortho,
-                       "residual": res, "info": int(info.item()), "phases_ms": phases_of(fp64)}
+                       "residual": res, "info": int(info.item()),
+                       "rel_R_vs_fp64_oracle": None if R_or is None else rel_r_diff(R, R_or),
+                       "phases_ms": phases_of(fp64)}
         for name, lowp in (("fp32", tsqr.FP32), ("bf16", tsqr.BF16)):
             ws = torch.empty(tsqr.mixed_workspace_bytes(m, n, s, lowp), dtype=torch.uint8,
                              device="cuda")
@@ -199,6 +209,7 @@ def mixed_comparison(args, kappas):
             row[name] = {"ms": round(ms_m, 4), "gflops_equiv": round(F / ms_m / 1e6, 2),
                          "fp64_passes": npass[-1], "lowp_stage": "apply_lowp" in ph,
                          "ortho": o_m, "residual": r_m, "info": int(info.item()),
+                         "rel_R_vs_fp64_oracle": None if R_or is None else rel_r_diff(R, R_or),
                          "speedup_vs_fp64": round(ms / ms_m, 3) if ok else None,
                          "phases_ms": ph}
             del ws
@@ -432,6 +443,205 @@ def batched_comparison(args):
                      "speedup_vs_fp64_batch": round(ms / ms32, 3)}}
 
 
+# Kernels of the FP64 chain: the phases (library event names) each one runs under, the
+# algorithmic work of one launch, and the roof that bounds it (SURVEY-style per-unit
+# figures: sketch 2smn flops over 8mn bytes, TRSM mn^2 flops over 16mn bytes, Gram
+# mn(n+1) flops over 8mn bytes; at n = 128 the TRSM's 8 flop/B is below the FP64 ridge of
+# 78.6 TFLOP/s / 8 TB/s = 9.8 flop/B, so it is HBM-bound, while the sketch (64 flop/B) and
+# the Gram (16 flop/B) are FP64-bound).
+def kernel_table(m: int, n: int, s: int, variant: str) -> dict:
+    fac = "sketch_lu" if variant == "rlu" else "sketch_qr"
+    return {
+        "sketch": {"symbol": "k_sketch_f64", "phases": ["sketch"], "flops": 2.0 * s * m * n,
+                   "bytes": 8.0 * m * n},
+        "trsm": {"symbol": "k_trsm_mfma", "phases": ["trsm_r0", "trsm_r1", "trsm_r2"],
+                 "flops": 1.0 * m * n * n, "bytes": 16.0 * m * n},
+        "gram": {"symbol": "k_gram_f64", "phases": ["gram1", "gram2"],
+                 "flops": 1.0 * m * n * (n + 1), "bytes": 8.0 * m * n},
+        "sketch_factor": {"symbol": "k_geqrf_reg" if variant != "rlu" else "k_getrf_reg",
+                          "phases": [fac], "flops": None, "bytes": None},
+        "potrf": {"symbol": "k_chol_* / k_potrf_reg", "phases": ["potrf1", "potrf2"],
+                  "flops": n ** 3 / 3.0, "bytes": None},
+        "trsm_prep": {"symbol": "k_trsm_prep",
+                      "phases": ["trsm_prep_r0", "trsm_prep_r1", "trsm_prep_r2"],
+                      "flops": None, "bytes": None},
+    }
+
+
+def roof_of(entry: dict, avg_ms: float) -> dict:
+    """Roofline of one kernel from its average launch duration: bound by whichever of
+    flops / FP64 peak and bytes / HBM peak is larger."""
+    out = {"symbol": entry["symbol"], "avg_ms": round(avg_ms, 4)}
+    fl, by = entry["flops"], entry["bytes"]
+    t_f = fl / (PEAK_FP64_TFLOPS * 1e12) if fl else 0.0
+    t_b = by / (PEAK_HBM_GBS * 1e9) if by else 0.0
+    if fl is None or (by is None and t_f * 1e3 < 0.05 * avg_ms):
+        out["bound"] = "latency"
+        return out
+    if t_b > t_f:
+        ach = by / (avg_ms * 1e-3) / 1e9
+        out.update(bound="hbm", achieved=round(ach, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                   frac=round(ach / PEAK_HBM_GBS, 4))
+        if fl:
+            out["mfma_frac"] = round(fl / (avg_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)
+    else:
+        ach = fl / (avg_ms * 1e-3) / 1e12
+        out.update(bound="mfma", achieved=round(ach, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                   frac=round(ach / PEAK_FP64_TFLOPS, 4))
+        if by:
+            out["hbm_gbs"] = round(by / (avg_ms * 1e-3) / 1e9, 1)
+    return out
+
+
+def attainable_peaks(reps: int = 5) -> dict:
+    """Measured peaks of this GPU: the best of a sweep of launch shapes of plain streaming
+    kernels over 1 GiB (read, write, copy) and of independent MFMA chains (FP64, FP32,
+    BF16), each timed with events on the launch stream."""
+    import torch
+
+    import paper_2111_11148_amd as tsqr
+
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    sink = torch.zeros(1, dtype=torch.float64, device="cuda")
+    out = {}
+
+    def ev_time(fn):
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps  # ms
+
+    for name, kind, moved in (("read", tsqr.PROBE_READ, nbytes),
+                              ("write", tsqr.PROBE_WRITE, nbytes),
+                              ("copy", tsqr.PROBE_COPY, 2 * nbytes)):
+        best = (0.0, None)
+        for wgs in (2, 4, 8, 16, 32):
+            for unroll in ((1,) if kind == tsqr.PROBE_WRITE else (2, 4, 8)):
+                for nt in ((False,) if kind == tsqr.PROBE_READ else (False, True)):
+                    ms = ev_time(lambda: tsqr.probe_stream(kind, src, dst, nbytes, sink, wgs,
+                                                           unroll, nt))
+                    gbs = moved / (ms * 1e-3) / 1e9
+                    if gbs > best[0]:
+                        best = (gbs, {"wgs_per_cu": wgs, "unroll": unroll, "nontemporal": nt})
+        out[f"hbm_{name}_gbs"] = round(best[0], 1)
+        out[f"hbm_{name}_shape"] = best[1]
+    del src, dst
+    spec = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2500e12, "bf16_32x32": 2500e12}
+    for name, kind in (("fp64", tsqr.PROBE_FP64), ("fp32", tsqr.PROBE_FP32),
+                       ("bf16", tsqr.PROBE_BF16), ("bf16_32x32", tsqr.PROBE_BF16_32)):
+        best = (0.0, None)
+        per = {3: 32768.0, 2: 16384.0}.get(kind, 2048.0)
+        for w in (1, 2, 4, 8):
+            for c in (4, 8, 16):
+                # about 2 ms per launch at the spec rate
+                per_iter = 256 * w * 4 * c * per
+                iters = max(16, int(2e-3 * spec[name] / per_iter))
+                fl = [0.0]
+
+                def run():
+                    fl[0] = tsqr.probe_mfma(kind, iters, sink, w, c)
+                ms = ev_time(run)
+                tf = fl[0] / (ms * 1e-3) / 1e12
+                if tf > best[0]:
+                    best = (tf, {"waves_per_simd": w, "chains": c})
+        out[f"mfma_{name}_tflops"] = round(best[0], 2)
+        out[f"mfma_{name}_shape"] = best[1]
+    out["spec"] = {"hbm_gbs": PEAK_HBM_GBS, "mfma_fp64_tflops": PEAK_FP64_TFLOPS,
+                   "mfma_fp32_tflops": 157.3, "mfma_bf16_tflops": 2500.0}
+    print(f"# attainable: {out}", file=sys.stderr, flush=True)
+    torch.cuda.empty_cache()
+    return out
+
+
+def step_t_roof(m: int, n: int, s: int, extra_pass: bool) -> float:
+    """Phase-sum roofline (seconds): phases separated by global dependences add up; each
+    is bound by max(flops / FP64 peak, algorithmic bytes / HBM peak), with the method's
+    algorithmic bytes = one read of A per phase plus the final write of Q."""
+    F = flops(m, n, s, "rqr", extra_pass)
+    T = 8.0 * m * n
+    P, BW = PEAK_FP64_TFLOPS * 1e12, PEAK_HBM_GBS * 1e9
+    phase_fb = [(F["sketch"], T), (F["trsm"] + F["gram"], T)]
+    if extra_pass:
+        phase_fb += [(F["trsm"] + F["gram"], T), (F["trsm"], 2 * T)]
+    else:
+        phase_fb += [(F["trsm"], 2 * T)]
+    return sum(max(fl / P, by / BW) for fl, by in phase_fb)
+
+
+def per_kernel(recs, steps: int, table: dict) -> dict:
+    """Per-step time and per-launch average of each kernel from phase records."""
+    out = {}
+    for key, ent in table.items():
+        ms = [t for name, t in recs if name in ent["phases"]]
+        if ms:
+            out[key] = {"per_step_ms": sum(ms) / steps, "avg_ms": sum(ms) / len(ms),
+                        "launches_per_step": len(ms) / steps}
+    return out
+
+
+def factor_leg(A, m, n, s, seed, variant, extra_pass, steps, label, oracle_R=None):
+    """Time one whole factorization on a resident matrix; report throughput, the step
+    roofline, per-kernel rooflines, device double-double metrics and, when the oracle's R
+    of the same matrix is given, the relative R difference."""
+    import torch
+
+    import paper_2111_11148_amd as tsqr
+
+    Q, R = tsqr.colmajor(m, n), tsqr.colmajor(n, n)
+    work = tsqr.alloc_workspace(m, n, s)
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    vcode = tsqr.RQR if variant == "rqr" else tsqr.RLU
+
+    def step():
+        tsqr.rxr_cholqr(A, s, seed, variant=vcode, extra_pass=extra_pass, Q=Q, R=R,
+                        workspace=work, info=info)
+
+    ms = timed(step, steps, 2)
+    torch.cuda.synchronize()
+    tsqr.profile_start()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    recs = tsqr.profile_stop()
+    table = kernel_table(m, n, s, variant)
+    pk = per_kernel(recs, steps, table)
+    ortho, res = gpu_metrics(A, Q, R)
+    F = flops(m, n, s, variant, extra_pass)["total"]
+    t_roof = step_t_roof(m, n, s, extra_pass)
+    out = {"workload": label, "m": m, "n": n, "s": s, "variant": variant,
+           "extra_pass": extra_pass, "ms_per_step": round(ms, 4),
+           "gflops": round(F / (ms * 1e-3) / 1e9, 2), "step_t_roof_ms": round(t_roof * 1e3, 4),
+           "step_roofline_frac": round(t_roof * 1e3 / ms, 4), "ortho": ortho, "residual": res,
+           "info": int(info.item()),
+           "kernels": {k: roof_of(table[k], v["avg_ms"]) | {"per_step_ms": round(v["per_step_ms"], 4)}
+                       for k, v in pk.items()}}
+    if oracle_R is not None:
+        out["rel_R_vs_oracle"] = rel_r_diff(R, oracle_R)
+    print(f"# {label}: {ms:.3f} ms/step, ortho {ortho:.3e}, residual {res:.3e}",
+          file=sys.stderr, flush=True)
+    del Q, R, work
+    return out
+
+
+def oracle_timed(A_h, s, seed, variant, extra_pass):
+    import numpy as np
+
+    import oracle
+
+    t0 = time.perf_counter()
+    r = oracle.rxr_cholqr(np.asfortranarray(A_h), s, seed,
+                          variant=oracle.RQR if variant == "rqr" else oracle.RLU,
+                          extra_pass=extra_pass)
+    return r, time.perf_counter() - t0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -443,10 +653,22 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cache-dir", default=None,
                     help="directory to keep the generated input matrix between runs")
+    ap.add_argument("--peaks", type=int, default=1,
+                    help="measure attainable HBM and MFMA peaks with the probe kernels")
+    ap.add_argument("--other-variant", type=int, default=1,
+                    help="also time the other sketch factorization (rLU when rQR is the "
+                         "headline) on the same matrix, with its oracle R difference")
+    ap.add_argument("--wide", type=int, default=1,
+                    help="time the wide1024 workload (m=2^18, n=1024, s=2048, plain)")
+    ap.add_argument("--wide-oracle", type=int, default=1,
+                    help="state the wide1024 R difference against the oracle (about a "
+                         "minute of CPU work)")
     ap.add_argument("--mixed-kappas", default="1e4,1e8,1e12",
                     help="condition numbers of the mixed-precision comparison (mixed256 "
                          "workload, m=2^20, n=256, s=512); empty to skip it")
     ap.add_argument("--mixed-steps", type=int, default=5)
+    ap.add_argument("--mixed-oracle", type=int, default=1,
+                    help="state each mixed256 result's R difference against the FP64 oracle")
     ap.add_argument("--baseline-kappas", default="1e5,1e10,1e12",
                     help="condition numbers of the comparison with CholeskyQR2 / sCholeskyQR3 "
                          "and the row-extraction sketch (m=2^20, n=128); empty to skip it")
@@ -472,7 +694,7 @@ def main() -> int:
     import torch
 
     import paper_2111_11148_amd as tsqr
-    from inputs import WORKLOADS, gen_matrix
+    from inputs import WORKLOADS
 
     if args.copy_calibration:
         nel = args.copy_calibration // 8
@@ -505,21 +727,23 @@ def main() -> int:
         step()
     torch.cuda.synchronize()
 
-    # per-phase breakdown: HIP events around every launch, in steps of their own
+    # per-kernel breakdown: HIP events around every launch, in steps of their own
     tsqr.profile_start()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     recs_all = tsqr.profile_stop()
-    phase_tot, phase_cnt = {}, {}
+    phase_tot = {}
     for name, ms in recs_all:
         phase_tot[name] = phase_tot.get(name, 0.0) + ms
-        phase_cnt[name] = phase_cnt.get(name, 0) + 1
     per_step = {k: phase_tot[k] / args.steps for k in phase_tot}
-    dom = max(per_step, key=per_step.get)  # dominant kernel: largest share of the step
+    table = kernel_table(m, n, s, args.variant)
+    pk = per_kernel(recs_all, args.steps, table)
+    # dominant kernel: the largest share of the step, all of its launches together
+    dom = max(pk, key=lambda k: pk[k]["per_step_ms"])
 
     # timed region: events recorded only around the dominant kernel's launches
-    tsqr.profile_start(only=dom)
+    tsqr.profile_start(only=",".join(table[dom]["phases"]))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -567,36 +791,30 @@ def main() -> int:
         del Qe, Re, g
 
     # the dominant kernel's average launch duration, from the events of the timed steps
-    dom_ms = [ms for name, ms in recs if name == dom]
-    phases = {dom: sum(dom_ms) / len(dom_ms)} if dom_ms else {}
+    dom_ms = [t for name, t in recs if name in table[dom]["phases"]]
+    dom_avg = sum(dom_ms) / len(dom_ms)
+    roof = roof_of(table[dom], dom_avg)
+    roof["kernel"] = dom
+    roof["launches_per_step"] = round(len(dom_ms) / args.steps, 2)
+    roof["traffic"] = load_traffic(dom, wl.name) if dom in KERNEL_SOURCES else None
+    kernels = {k: roof_of(table[k], v["avg_ms"]) | {"per_step_ms": round(v["per_step_ms"], 4)}
+               for k, v in pk.items()}
 
     F = flops(m, n, s, args.variant, extra_pass)
     value = F["total"] / (ms_per_step * 1e-3) / 1e9
+    t_roof = step_t_roof(m, n, s, extra_pass)
 
-    dom_flops = {"sketch": F["sketch"], "trsm_r0": F["trsm"], "trsm_r1": F["trsm"],
-                 "trsm_r2": F["trsm"], "gram1": F["gram"], "gram2": F["gram"]}.get(dom)
-    roof = None
-    if dom_flops is not None and dom in phases:
-        achieved = dom_flops / (phases[dom] * 1e-3) / 1e12
-        traffic = load_traffic(dom, wl.name) if dom in KERNEL_SOURCES else None
-        roof = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3),
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
-                "avg_ms": round(phases[dom], 4)}
-
-    # step roofline: phases separated by global dependences add up; each phase is bound
-    # by max(flops / FP64 peak, algorithmic bytes / HBM bandwidth), with the algorithmic
-    # bytes of the method = one read of A per phase plus the final write of Q.
-    T = 8.0 * m * n
-    P, BW = PEAK_FP64_TFLOPS * 1e12, PEAK_HBM_GBS * 1e9
-    phase_fb = [(F["sketch"], T), (F["trsm"] + F["gram"], T)]
-    if extra_pass:
-        phase_fb += [(F["trsm"] + F["gram"], T), (F["trsm"], 2 * T)]
-    else:
-        phase_fb += [(F["trsm"], 2 * T)]
-    t_roof = sum(max(fl / P, by / BW) for fl, by in phase_fb)
+    peaks = attainable_peaks() if args.peaks else None
+    if peaks:
+        # the same achieved rate against what the probe kernels reach on this GPU
+        if roof.get("bound") == "hbm":
+            roof["frac_of_attainable_copy"] = round(roof["achieved"] / peaks["hbm_copy_gbs"], 4)
+        elif roof.get("bound") == "mfma":
+            roof["frac_of_attainable_mfma"] = round(
+                roof["achieved"] / peaks["mfma_fp64_tflops"], 4)
 
     cpu = None
+    rel_R = None
     if not args.no_cpu_baseline:
         import oracle
 
@@ -615,11 +833,45 @@ def main() -> int:
                "kind": "oracle",
                "sample": f"first {ms_} rows of the same matrix (n={n}, s={s}), {reps} full "
                          f"factorizations, {dt:.2f} s each ({t_all:.1f} s), info={r['info']}"}
+        if ms_ == m:
+            rel_R = rel_r_diff(R, r["R"])
+        del As, r
+
+    other = None
+    if args.other_variant:
+        ov = "rlu" if args.variant == "rqr" else "rqr"
+        R_o = None
+        if not args.no_cpu_baseline:
+            ro, t_o = oracle_timed(A_h, s, seed, ov, extra_pass)
+            R_o = ro["R"]
+        other = factor_leg(A, m, n, s, seed, ov, extra_pass, args.steps,
+                           f"{wl.name}-{ov}-fp64", oracle_R=R_o)
+        if R_o is not None:
+            other["oracle_seconds"] = round(t_o, 2)
+
+    del A, Q, R, work
+    torch.cuda.empty_cache()
+
+    wide = None
+    if args.wide:
+        ww = WORKLOADS["wide1024"]
+        Aw_h = cached_matrix(args.cache_dir, ww.name, ww.m, ww.n, ww.kappas[0], ww.gen_seeds[0])
+        Aw = tsqr.to_device_colmajor(np.asarray(Aw_h))
+        R_w, t_w = None, None
+        if args.wide_oracle and not args.no_cpu_baseline:
+            rw, t_w = oracle_timed(Aw_h, ww.s, ww.sketch_seed, "rqr", ww.extra_pass)
+            R_w = rw["R"]
+            del rw
+        wide = factor_leg(Aw, ww.m, ww.n, ww.s, ww.sketch_seed, "rqr", ww.extra_pass,
+                          5, f"{ww.name}-rqr-fp64", oracle_R=R_w)
+        if t_w is not None:
+            wide["oracle_seconds"] = round(t_w, 2)
+        del Aw, Aw_h
+        torch.cuda.empty_cache()
 
     mixed = None
     kappas = [float(k) for k in args.mixed_kappas.split(",") if k.strip()]
     if kappas:
-        del A, Q, R, work
         torch.cuda.empty_cache()
         mixed = mixed_comparison(args, kappas)
 
@@ -657,13 +909,19 @@ def main() -> int:
                    "flops_per_step": F["total"]},
         "roofline": roof,
         "step_roofline_frac": round(t_roof * 1e3 / ms_per_step, 4),
+        "step_t_roof_ms": round(t_roof * 1e3, 4),
+        "kernels": kernels,
+        "attainable_peaks": peaks,
         "cpu_baseline": cpu,
         "ortho": ortho,
         "residual": res,
+        "rel_R_vs_oracle": rel_R,
         "info": binfo,
         "phases_ms": {k: round(v, 4) for k, v in per_step.items()},
         "graph": None if graph is None else dict(
             graph, gflops=round(F["total"] / (graph["ms_per_step"] * 1e-3) / 1e9, 3)),
+        "other_variant": other,
+        "wide1024": wide,
         "mixed_vs_fp64": mixed,
         "baselines": baselines,
         "paper_shaped": paper_shaped,

@@ -367,19 +367,65 @@ int tsqr_sketch_normals(uint64_t seed, int64_t i0, int64_t ni, int64_t j0, int64
                         double* Zout, int64_t ldz, void* stream);
 
 /* ------------------------------------------------------------------------------------
+ * Accuracy metrics and roofline probes (measurement; not part of the factorization)
+ * ------------------------------------------------------------------------------------ */
+
+/* The paper's two accuracy measures (Section 4.2), evaluated with double-double
+ * accumulation (error-free FMA products, two-sum additions) in a fixed summation order:
+ *   d_out[0] = ||Q^T Q - I||_F,   d_out[1] = ||A - Q R||_F / ||A||_F.
+ * A plain FP64 sum over m rows would carry an error near sqrt(m) u, above the values
+ * being measured once m is large; here each Gram entry and each entry of A - Q R is
+ * accurate to about m u^2 of its terms, so both results have essentially full precision.
+ * m, n        : rows and columns of Q (and A), m >= 1, 1 <= n <= 65536.   (args 1, 2)
+ * A, lda      : the factorized matrix, lda >= m; NULL skips the residual (d_out[1] =
+ *               NaN).                                                      (args 3, 4)
+ * Q, ldq      : m x n, ldq >= m.                                           (args 5, 6)
+ * R, ldr      : n x n as returned (every entry is used), ldr >= n; NULL skips the
+ *               residual.                                                   (args 7, 8)
+ * d_out       : two device doubles.                                        (arg 9)
+ * work        : device workspace of tsqr_metrics_workspace_bytes(m, n) bytes (0 for
+ *               invalid sizes); TSQR_ERR_WORKSPACE if smaller or NULL.     (args 10, 11) */
+size_t tsqr_metrics_workspace_bytes(int64_t m, int64_t n);
+int tsqr_metrics(int64_t m, int64_t n, const double* A, int64_t lda, const double* Q,
+                 int64_t ldq, const double* R, int64_t ldr, double* d_out, void* work,
+                 size_t work_bytes, void* stream);
+
+/* Attainable-bandwidth probe: one pass of a plain streaming kernel with 16-byte accesses
+ * over `bytes` bytes (rounded down to a multiple of 16): kind 0 reads src, 1 writes dst,
+ * 2 copies src to dst.  Launch shape: wgs_per_cu workgroups of 256 threads per compute
+ * unit (1..64), `unroll` words (1, 2, 4, 8) in flight per thread per loop trip, and
+ * nontemporal != 0 for streaming stores.  Device pointers, 16-byte aligned; d_sink is one
+ * device double that the read probe may write (it keeps the loads from being removed).
+ * Errors: -1 kind, -2 src NULL (kinds 0, 2), -3 dst NULL (kinds 1, 2), -4 bytes < 16,
+ * -5 wgs_per_cu, -6 unroll, -8 d_sink. */
+int tsqr_probe_stream(int kind, const void* src, void* dst, size_t bytes, int wgs_per_cu,
+                      int unroll, int nontemporal, double* d_sink, void* stream);
+
+/* Attainable matrix-core rate probe: `chains` (4, 8, 16) independent accumulator chains
+ * per wavefront, `iters` MFMAs each, on waves_per_simd (1, 2, 4, 8) workgroups of four
+ * wavefronts per compute unit.  kind 0: FP64 16x16x4, 1: FP32 16x16x4, 2: BF16 16x16x32,
+ * 3: BF16 32x32x16 (FP32 accumulation for the BF16 forms).  *flops (host) is set to the
+ * flops of the launch (2 per multiply-add).  Errors: -1 kind, -2 waves_per_simd, -3 chains,
+ * -4 iters < 1, -5 d_sink NULL, -6 flops NULL. */
+int tsqr_probe_mfma(int kind, int waves_per_simd, int chains, int64_t iters, double* d_sink,
+                    double* flops, void* stream);
+
+/* ------------------------------------------------------------------------------------
  * Phase timing (tracing)
  * ------------------------------------------------------------------------------------ */
 
 /* While enabled, the whole-factorization entry points record a pair of HIP events on
  * their stream around every kernel they launch (named "sketch", "sketch_reduce",
- * "sketch_qr" or "sketch_lu", "trsm_r0", "gram1", "gram1_reduce", "potrf1", "trsm_r1",
- * "gram2", "gram2_reduce", "potrf2", "trsm_r2", "trmm", "poison").  tsqr_profile_start()
+ * "sketch_qr" or "sketch_lu", "trsm_prep_r0", "trsm_r0", "gram1", "gram1_reduce", "potrf1",
+ * "trsm_prep_r1", "trsm_r1", "gram2", "gram2_reduce", "potrf2", "trsm_prep_r2", "trsm_r2",
+ * "trmm", "poison"; the "trsm_prep" phases prepare the triangular factor's operand tiles,
+ * the "trsm" phases are the solves themselves).  tsqr_profile_start()
  * clears the records and enables recording; tsqr_profile_stop() disables it, waits for
  * the recorded events and returns the number of records (or TSQR_ERR_HIP);
  * tsqr_profile_record(i) returns the i-th record's name (static storage) and duration in
- * milliseconds (-1 if i is out of range).  tsqr_profile_only(name) limits the recording
- * to the phase of that name (NULL: every phase), so that a timed run carries only the
- * events it needs.  Process-wide; not meant for concurrent use. */
+ * milliseconds (-1 if i is out of range).  tsqr_profile_only(names) limits the recording
+ * to the phases named in the comma-separated list `names` (NULL: every phase), so that a
+ * timed run carries only the events it needs.  Process-wide; not meant for concurrent use. */
 int tsqr_profile_start(void);
 int tsqr_profile_stop(void);
 int tsqr_profile_record(int i, const char** name, double* ms);

@@ -77,6 +77,11 @@ _SIGS = {
     "tsqr_batched_run": (_int, [_vp, _vp]),
     "tsqr_batched_launches": (_int, [_vp]),
     "tsqr_batched_destroy": (None, [_vp]),
+    "tsqr_metrics_workspace_bytes": (_sz, [_i64, _i64]),
+    "tsqr_metrics": (_int, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _sz, _vp]),
+    "tsqr_probe_stream": (_int, [_int, _vp, _vp, _sz, _int, _int, _int, _vp, _vp]),
+    "tsqr_probe_mfma": (_int, [_int, _int, _int, _i64, _vp, ctypes.POINTER(ctypes.c_double),
+                               _vp]),
     "tsqr_profile_start": (_int, []),
     "tsqr_profile_only": (_int, [ctypes.c_char_p]),
     "tsqr_profile_stop": (_int, []),
@@ -196,6 +201,53 @@ def profile_stop():
                "tsqr_profile_record")
         out.append((name.value.decode(), ms.value))
     return out
+
+
+# ------------------------------------------------------- accuracy metrics, probes ----
+@_on_stream
+def metrics(Q: torch.Tensor, A: torch.Tensor | None = None, R: torch.Tensor | None = None,
+            stream=None):
+    """(||Q^T Q - I||_F, ||A - Q R||_F / ||A||_F) with double-double accumulation on the
+    device; the residual is NaN when A or R is not given.  Returns two Python floats."""
+    ldq = _mat(Q, "Q")
+    m, n = Q.shape
+    lda = _mat(A, "A", m, n) if A is not None else m
+    ldr = _mat(R, "R", n, n) if R is not None else n
+    lib = load()
+    work = torch.empty(max(1, int(lib.tsqr_metrics_workspace_bytes(m, n))), dtype=torch.uint8,
+                       device=Q.device)
+    out = torch.empty(2, dtype=torch.float64, device=Q.device)
+    rc = lib.tsqr_metrics(m, n, A.data_ptr() if A is not None else None, lda, Q.data_ptr(), ldq,
+                          R.data_ptr() if R is not None else None, ldr, out.data_ptr(),
+                          work.data_ptr(), work.numel(), _stream(stream))
+    _check(rc, "tsqr_metrics")
+    o = out.cpu()
+    return float(o[0]), float(o[1])
+
+
+PROBE_READ, PROBE_WRITE, PROBE_COPY = 0, 1, 2
+PROBE_FP64, PROBE_FP32, PROBE_BF16, PROBE_BF16_32 = 0, 1, 2, 3
+
+
+def probe_stream(kind: int, src: torch.Tensor | None, dst: torch.Tensor | None, nbytes: int,
+                 sink: torch.Tensor, wgs_per_cu: int = 16, unroll: int = 4,
+                 nontemporal: bool = False, stream=None) -> None:
+    """One pass of the streaming probe (read / write / copy of nbytes)."""
+    rc = load().tsqr_probe_stream(kind, src.data_ptr() if src is not None else None,
+                                  dst.data_ptr() if dst is not None else None, nbytes,
+                                  wgs_per_cu, unroll, int(bool(nontemporal)), sink.data_ptr(),
+                                  _stream(stream))
+    _check(rc, "tsqr_probe_stream")
+
+
+def probe_mfma(kind: int, iters: int, sink: torch.Tensor, waves_per_simd: int = 2,
+               chains: int = 8, stream=None) -> float:
+    """One launch of the matrix-core probe; returns its flop count."""
+    fl = ctypes.c_double()
+    rc = load().tsqr_probe_mfma(kind, waves_per_simd, chains, iters, sink.data_ptr(),
+                                ctypes.byref(fl), _stream(stream))
+    _check(rc, "tsqr_probe_mfma")
+    return fl.value
 
 
 # ------------------------------------------------------------------ whole method ----

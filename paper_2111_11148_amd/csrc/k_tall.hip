@@ -362,19 +362,31 @@ size_t trsm_scratch_doubles(int n) {
 }
 
 static hipError_t launch_trsm_block(int64_t m, int n, const double* Y, int64_t ldy,
-                                    const double* T, int64_t ldt, double* X, int64_t ldx,
-                                    double* scratch, hipStream_t st);
+                                    double* X, int64_t ldx, double* scratch, hipStream_t st);
 
-// X = Y T^{-1}.  Up to kBlk columns: one substitution kernel.  Wider: by column blocks of
-// kBlk; the first block is the substitution kernel, every later block one pass of
-// k_trsm_fused (update against all solved blocks, then the block's own substitution).
-hipError_t launch_trsm(int64_t m, int n, const double* Y, int64_t ldy, const double* T,
-                       int64_t ldt, double* X, int64_t ldx, double* scratch, hipStream_t st) {
+// Operand preparation of the first column block (all of T up to kBlk columns).
+hipError_t launch_trsm_prepare(int n, const double* T, int64_t ldt, double* scratch,
+                               hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int nb = n < kBlk ? n : kBlk;
+  int jt = 1;
+  while (jt < (nb + 15) / 16) jt <<= 1;
+  hipLaunchKernelGGL(k_trsm_prep, dim3(jt), dim3(256), 0, st, nb, jt, T, ldt, scratch);
+  return hipGetLastError();
+}
+
+// X = Y T^{-1} after launch_trsm_prepare.  Up to kBlk columns: one substitution kernel.
+// Wider: by column blocks of kBlk; the first block is the substitution kernel, every later
+// block one pass of k_trsm_fused (update against all solved blocks, then the block's own
+// substitution).
+hipError_t launch_trsm_solve(int64_t m, int n, const double* Y, int64_t ldy, const double* T,
+                             int64_t ldt, double* X, int64_t ldx, double* scratch,
+                             hipStream_t st) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  if (n <= kBlk) return launch_trsm_block(m, n, Y, ldy, T, ldt, X, ldx, scratch, st);
+  if (n <= kBlk) return launch_trsm_block(m, n, Y, ldy, X, ldx, scratch, st);
   const int64_t ntiles = (m + 15) / 16;
   const int64_t cap = (int64_t)device_cu_count();
-  hipError_t e = launch_trsm_block(m, kBlk, Y, ldy, T, ldt, X, ldx, scratch, st);
+  hipError_t e = launch_trsm_block(m, kBlk, Y, ldy, X, ldx, scratch, st);
   if (e != hipSuccess) return e;
   for (int k0 = kBlk; k0 < n; k0 += kBlk) {
     const int nbk = (n - k0) < kBlk ? (n - k0) : kBlk;
@@ -402,15 +414,20 @@ hipError_t launch_trsm(int64_t m, int n, const double* Y, int64_t ldy, const dou
   return hipSuccess;
 }
 
+hipError_t launch_trsm(int64_t m, int n, const double* Y, int64_t ldy, const double* T,
+                       int64_t ldt, double* X, int64_t ldx, double* scratch, hipStream_t st) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const hipError_t e = launch_trsm_prepare(n, T, ldt, scratch, st);
+  if (e != hipSuccess) return e;
+  return launch_trsm_solve(m, n, Y, ldy, T, ldt, X, ldx, scratch, st);
+}
+
+// The substitution kernel over up to kBlk columns, operands prepared in `scratch`.
 static hipError_t launch_trsm_block(int64_t m, int n, const double* Y, int64_t ldy,
-                                    const double* T, int64_t ldt, double* X, int64_t ldx,
-                                    double* scratch, hipStream_t st) {
+                                    double* X, int64_t ldx, double* scratch, hipStream_t st) {
   int jt = 1;
   while (jt < (n + 15) / 16) jt <<= 1;
   if (jt > 8) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_trsm_prep, dim3(jt), dim3(256), 0, st, n, jt, T, ldt, scratch);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   const int64_t ntiles = (m + 15) / 16;
   int64_t blocks = (ntiles + kTrsmThreads / 64 - 1) / (kTrsmThreads / 64);
   const int64_t cap = (int64_t)device_cu_count();

@@ -100,9 +100,20 @@ std::vector<std::pair<const char*, double>> g_prof_done;
 std::vector<hipEvent_t> g_prof_pool;
 std::string g_prof_only;  // empty: every phase
 
+// g_prof_only: empty, or a comma-separated list of phase names
 bool prof_on(const char* name) {
   std::lock_guard<std::mutex> g(g_prof_mu);
-  return g_prof_on && (g_prof_only.empty() || g_prof_only == name);
+  if (!g_prof_on) return false;
+  if (g_prof_only.empty()) return true;
+  const size_t len = strlen(name);
+  size_t pos = 0;
+  while (pos <= g_prof_only.size()) {
+    size_t end = g_prof_only.find(',', pos);
+    if (end == std::string::npos) end = g_prof_only.size();
+    if (end - pos == len && g_prof_only.compare(pos, len, name) == 0) return true;
+    pos = end + 1;
+  }
+  return false;
 }
 
 void prof_release(hipEvent_t e) {
@@ -176,17 +187,20 @@ int run_chain(int variant, int64_t m, int64_t n, const double* A, int64_t lda, i
   TSQR_PHASE(variant == 1 ? "sketch_lu" : "sketch_qr",
              launch_sketch_factor(variant, si, ni, B, s, R0, n, info, fac, st));
   // A1 = A R0^{-1} (into Q), W1 = A1^T A1, R1 = chol(W1), Q1 = A1 R1^{-1}
-  TSQR_PHASE("trsm_r0", launch_trsm(m, ni, A, lda, R0, n, Q, ldq, Tt, st));
+  TSQR_PHASE("trsm_prep_r0", launch_trsm_prepare(ni, R0, n, Tt, st));
+  TSQR_PHASE("trsm_r0", launch_trsm_solve(m, ni, A, lda, R0, n, Q, ldq, Tt, st));
   TSQR_PHASE("gram1", launch_gram(L.gp, m, ni, Q, ldq, part, st));
   TSQR_PHASE("gram1_reduce", launch_gram_reduce(L.gp, ni, part, W, n, st));
   TSQR_PHASE("potrf1", launch_potrf(ni, W, n, R1, n, 2, info, fac, st));
-  TSQR_PHASE("trsm_r1", launch_trsm(m, ni, Q, ldq, R1, n, Q, ldq, Tt, st));
+  TSQR_PHASE("trsm_prep_r1", launch_trsm_prepare(ni, R1, n, Tt, st));
+  TSQR_PHASE("trsm_r1", launch_trsm_solve(m, ni, Q, ldq, R1, n, Q, ldq, Tt, st));
   if (extra_pass) {
     // W2 = Q1^T Q1, R2 = chol(W2), Q = Q1 R2^{-1}
     TSQR_PHASE("gram2", launch_gram(L.gp, m, ni, Q, ldq, part, st));
     TSQR_PHASE("gram2_reduce", launch_gram_reduce(L.gp, ni, part, W, n, st));
     TSQR_PHASE("potrf2", launch_potrf(ni, W, n, R2, n, 3, info, fac, st));
-    TSQR_PHASE("trsm_r2", launch_trsm(m, ni, Q, ldq, R2, n, Q, ldq, Tt, st));
+    TSQR_PHASE("trsm_prep_r2", launch_trsm_prepare(ni, R2, n, Tt, st));
+    TSQR_PHASE("trsm_r2", launch_trsm_solve(m, ni, Q, ldq, R2, n, Q, ldq, Tt, st));
   }
   if (R) {
     if (extra_pass) {
@@ -969,6 +983,58 @@ int tsqr_sketch_normals(uint64_t seed, int64_t i0, int64_t ni, int64_t j0, int64
   if (ni * nj > 0 && !Zout) return -6;
   if (ldz < ni || ldz < 1) return -7;
   if (launch_sketch_normals(seed, i0, ni, j0, nj, Zout, ldz, (hipStream_t)stream) != hipSuccess)
+    return TSQR_ERR_HIP;
+  return TSQR_OK;
+}
+
+size_t tsqr_metrics_workspace_bytes(int64_t m, int64_t n) {
+  if (m < 1 || n < 1 || n > 65536) return 0;
+  return metrics_workspace_bytes(m, (int)n);
+}
+
+int tsqr_metrics(int64_t m, int64_t n, const double* A, int64_t lda, const double* Q,
+                 int64_t ldq, const double* R, int64_t ldr, double* d_out, void* work,
+                 size_t work_bytes, void* stream) {
+  if (m < 1) return -1;
+  if (n < 1 || n > 65536) return -2;
+  if (A && lda < m) return -4;
+  if (!Q) return -5;
+  if (ldq < m) return -6;
+  if (R && ldr < n) return -8;
+  if (!d_out) return -9;
+  if (!work || work_bytes < metrics_workspace_bytes(m, (int)n)) return TSQR_ERR_WORKSPACE;
+  if (launch_metrics(m, (int)n, A, lda, Q, ldq, R, ldr, d_out, work, (hipStream_t)stream) !=
+      hipSuccess)
+    return TSQR_ERR_HIP;
+  return TSQR_OK;
+}
+
+int tsqr_probe_stream(int kind, const void* src, void* dst, size_t bytes, int wgs_per_cu,
+                      int unroll, int nontemporal, double* d_sink, void* stream) {
+  if (kind < 0 || kind > 2) return -1;
+  if (kind != 1 && !src) return -2;
+  if (kind != 0 && !dst) return -3;
+  if (bytes < 16) return -4;
+  if (wgs_per_cu < 1 || wgs_per_cu > 64) return -5;
+  if (unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8) return -6;
+  if (!d_sink) return -8;
+  if (launch_probe_stream(kind, src, dst, bytes, wgs_per_cu, unroll, nontemporal, d_sink,
+                          (hipStream_t)stream) != hipSuccess)
+    return TSQR_ERR_HIP;
+  return TSQR_OK;
+}
+
+int tsqr_probe_mfma(int kind, int waves_per_simd, int chains, int64_t iters, double* d_sink,
+                    double* flops, void* stream) {
+  if (kind < 0 || kind > 3) return -1;
+  if (waves_per_simd != 1 && waves_per_simd != 2 && waves_per_simd != 4 && waves_per_simd != 8)
+    return -2;
+  if (chains != 4 && chains != 8 && chains != 16) return -3;
+  if (iters < 1) return -4;
+  if (!d_sink) return -5;
+  if (!flops) return -6;
+  if (launch_probe_mfma(kind, waves_per_simd, chains, iters, d_sink, flops,
+                        (hipStream_t)stream) != hipSuccess)
     return TSQR_ERR_HIP;
   return TSQR_OK;
 }

@@ -49,6 +49,12 @@ hipError_t launch_gram_reduce(const GramPlan& p, int n, const double* part, doub
 size_t trsm_scratch_doubles(int n);
 hipError_t launch_trsm(int64_t m, int n, const double* Y, int64_t ldy, const double* T,
                        int64_t ldt, double* X, int64_t ldx, double* scratch, hipStream_t st);
+// the same in two steps: operand preparation (k_trsm_prep), then the solve
+hipError_t launch_trsm_prepare(int n, const double* T, int64_t ldt, double* scratch,
+                               hipStream_t st);
+hipError_t launch_trsm_solve(int64_t m, int n, const double* Y, int64_t ldy, const double* T,
+                             int64_t ldt, double* X, int64_t ldx, double* scratch,
+                             hipStream_t st);
 // R0 from the s x n sketch: Householder (variant 0) or partial-pivot LU (variant 1);
 // `scratch` holds sketch_factor_scratch_doubles(s, n) doubles.
 size_t sketch_factor_scratch_doubles(int s, int n);
@@ -156,6 +162,18 @@ hipError_t launch_b_trmm(int which, const BItem* items, int nitems, const BProb*
                          hipStream_t st);
 hipError_t launch_b_poison(const BItem* items, int nitems, const BProb* probs, hipStream_t st);
 hipError_t launch_b_set_info(const BItem* items, int nitems, const BProb* probs, hipStream_t st);
+
+// ---- accuracy metrics (double-double) and attainable-peak probes -------------------------
+size_t metrics_workspace_bytes(int64_t m, int n);
+// out[0] = ||Q^T Q - I||_F; out[1] = ||A - Q R||_F / ||A||_F (NaN when A or R is null)
+hipError_t launch_metrics(int64_t m, int n, const double* A, int64_t lda, const double* Q,
+                          int64_t ldq, const double* R, int64_t ldr, double* out, void* work,
+                          hipStream_t st);
+hipError_t launch_probe_stream(int kind, const void* src, void* dst, size_t bytes,
+                               int wgs_per_cu, int unroll, int nontemporal, double* sink,
+                               hipStream_t st);
+hipError_t launch_probe_mfma(int kind, int waves_per_simd, int chains, int64_t iters,
+                             double* sink, double* flops, hipStream_t st);
 
 // ---- test / debug kernels -------------------------------------------------------------
 hipError_t launch_philox_words(int64_t count, const uint32_t* ctr, uint64_t seed, uint32_t* out,

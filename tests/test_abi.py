@@ -182,3 +182,40 @@ def test_lstsq_argument_codes(lib):
     assert f(0, 0, 64, 8, A, 64, b, 16, 1, None, W, 1, None, None) == -10
     assert f(0, 0, 64, 8, A, 64, b, 16, 1, x, None, 1, None, None) == -11
     assert f(0, 1, 64, 8, A, 64, b, 16, 1, x, W, 1, None, None) == -101  # workspace too small
+
+
+def test_metrics_and_probe_argument_codes(lib):
+    A = ctypes.c_void_p(0x10000000)
+    Q = ctypes.c_void_p(0x20000000)
+    R = ctypes.c_void_p(0x30000000)
+    out = ctypes.c_void_p(0x40000000)
+    W = ctypes.c_void_p(0x50000000)
+    nb = lib.tsqr_metrics_workspace_bytes(1000, 40)
+    assert nb > 0 and lib.tsqr_metrics_workspace_bytes(0, 4) == 0
+    f = lib.tsqr_metrics
+    assert f(0, 4, A, 8, Q, 8, R, 4, out, W, nb, None) == -1        # m < 1
+    assert f(8, 0, A, 8, Q, 8, R, 4, out, W, nb, None) == -2        # n < 1
+    assert f(8, 4, A, 7, Q, 8, R, 4, out, W, nb, None) == -4        # lda < m
+    assert f(8, 4, A, 8, None, 8, R, 4, out, W, nb, None) == -5     # Q NULL
+    assert f(8, 4, A, 8, Q, 7, R, 4, out, W, nb, None) == -6        # ldq < m
+    assert f(8, 4, A, 8, Q, 8, R, 3, out, W, nb, None) == -8        # ldr < n
+    assert f(8, 4, A, 8, Q, 8, R, 4, None, W, nb, None) == -9       # d_out NULL
+    assert f(1000, 40, A, 1000, Q, 1000, R, 40, out, W, nb - 1, None) == -101  # workspace
+    assert f(1000, 40, A, 1000, Q, 1000, R, 40, out, None, nb, None) == -101
+    g = lib.tsqr_probe_stream
+    assert g(3, A, Q, 1 << 20, 16, 4, 0, out, None) == -1
+    assert g(0, None, Q, 1 << 20, 16, 4, 0, out, None) == -2
+    assert g(1, A, None, 1 << 20, 16, 4, 0, out, None) == -3
+    assert g(2, A, Q, 8, 16, 4, 0, out, None) == -4
+    assert g(2, A, Q, 1 << 20, 0, 4, 0, out, None) == -5
+    assert g(2, A, Q, 1 << 20, 16, 3, 0, out, None) == -6
+    assert g(2, A, Q, 1 << 20, 16, 4, 0, None, None) == -8
+    h = lib.tsqr_probe_mfma
+    fl = ctypes.c_double()
+    assert h(4, 2, 8, 10, out, ctypes.byref(fl), None) == -1
+    assert h(0, 3, 8, 10, out, ctypes.byref(fl), None) == -2
+    assert h(0, 2, 5, 10, out, ctypes.byref(fl), None) == -3
+    assert h(0, 2, 8, 0, out, ctypes.byref(fl), None) == -4
+    assert h(0, 2, 8, 10, None, ctypes.byref(fl), None) == -5
+    assert h(0, 2, 8, 10, out, None, None) == -6
+

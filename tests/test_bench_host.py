@@ -60,3 +60,23 @@ def test_traffic_only_for_the_measured_source(tmp_path, monkeypatch):
     assert b.load_traffic("sketch", "other_workload") is None
     (tmp_path / "k.hip").write_text("kernel, changed\n")
     assert b.load_traffic("sketch", "w") is None
+
+
+def test_kernel_roofs_and_step_bound():
+    b = _bench()
+    m, n, s = 1 << 20, 128, 256
+    t = b.kernel_table(m, n, s, "rqr")
+    # the TRSM moves 16mn bytes for mn^2 flops: 8 flop/B < 78.6/8 = 9.8, so HBM-bound
+    r = b.roof_of(t["trsm"], 0.5)
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s"
+    assert r["achieved"] == pytest.approx(16 * m * n / 0.5e-3 / 1e9, rel=1e-4)
+    assert r["frac"] == pytest.approx(r["achieved"] / 8000.0, rel=1e-3)
+    # the sketch (64 flop/B) and the Gram (16 flop/B) are FP64 matrix-core bound
+    assert b.roof_of(t["sketch"], 1.0)["bound"] == "mfma"
+    g = b.roof_of(t["gram"], 0.4)
+    assert g["bound"] == "mfma"
+    assert g["achieved"] == pytest.approx(m * n * (n + 1) / 0.4e-3 / 1e12, rel=1e-4)
+    assert b.roof_of(t["sketch_factor"], 0.2)["bound"] == "latency"
+    # phase-sum roofline of the tall step (2.02 ms) and of the wide plain one (24.5 ms)
+    assert b.step_t_roof(m, n, s, True) * 1e3 == pytest.approx(2.016, abs=0.01)
+    assert b.step_t_roof(1 << 18, 1024, 2048, False) * 1e3 == pytest.approx(24.5, abs=0.1)

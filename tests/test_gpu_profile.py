@@ -8,8 +8,9 @@ from inputs.matrices import gen_matrix
 
 pytestmark = pytest.mark.gpu
 
-CHAIN = ["sketch", "sketch_reduce", "sketch_qr", "trsm_r0", "gram1", "gram1_reduce", "potrf1",
-         "trsm_r1", "gram2", "gram2_reduce", "potrf2", "trsm_r2", "trmm", "trmm", "poison"]
+CHAIN = ["sketch", "sketch_reduce", "sketch_qr", "trsm_prep_r0", "trsm_r0", "gram1",
+         "gram1_reduce", "potrf1", "trsm_prep_r1", "trsm_r1", "gram2", "gram2_reduce", "potrf2",
+         "trsm_prep_r2", "trsm_r2", "trmm", "trmm", "poison"]
 
 
 def test_profile_records_and_filter():
