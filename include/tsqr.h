@@ -101,6 +101,23 @@ int tsqr_rxr_cholqr_ws(int variant, int64_t m, int64_t n, const double* A, int64
                        int64_t ldq, double* R, int64_t ldr, void* work, size_t work_bytes,
                        int* d_info, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): tsqr_rxr_cholqr_ws with its workspace
+ * taken from a fixed device array of TSQR_STATIC_SCRATCH_BYTES bytes that the library
+ * holds on each GPU it runs on until the process ends.  Nothing is allocated and no
+ * library routine that allocates is called.  Same arguments and codes as
+ * tsqr_rxr_cholqr_ws without (work, work_bytes); d_info may be NULL (the info word then
+ * lives in the array).  Sizes whose workspace (tsqr_workspace_bytes) exceeds
+ * TSQR_STATIC_SCRATCH_BYTES return TSQR_ERR_WORKSPACE before any work is enqueued: every
+ * n <= 128 with s <= 256 fits, at any m.  Every call on one GPU shares that GPU's array:
+ * calls that overlap in time on one GPU (on different streams, or from several host
+ * threads) race and give wrong results; calls on one stream are ordered and safe.  Each
+ * call overwrites everything it reads from the array before reading it. */
+#define TSQR_STATIC_SCRATCH_BYTES (72ull << 20)
+int tsqr_rxr_cholqr_noalloc(int variant, int64_t m, int64_t n, const double* A, int64_t lda,
+                            int64_t sketch_rows, uint64_t seed, int extra_pass, double* Q,
+                            int64_t ldq, double* R, int64_t ldr, int* d_info, void* stream);
+
 /* Row-extraction sketch (paper Section 2.3, "Row Extraction", the sketch of the paper's
  * experiments): rQR/rLU-CholeskyQR with B = P A, P selecting s rows drawn independently,
  * each uniformly from the m rows (the sampling of Theorem "Equal Probability Case"; a row

@@ -38,6 +38,8 @@ _SIGS = {
     "tsqr_workspace_bytes": (_sz, [_i64, _i64, _i64]),
     "tsqr_rxr_cholqr_ws": (_int, [_int, _i64, _i64, _vp, _i64, _i64, _u64, _int, _vp, _i64, _vp,
                                   _i64, _vp, _sz, _vp, _vp]),
+    "tsqr_rxr_cholqr_noalloc": (_int, [_int, _i64, _i64, _vp, _i64, _i64, _u64, _int, _vp, _i64,
+                                       _vp, _i64, _vp, _vp]),
     "tsqr_rxr_cholqr_rows_ws": (_int, [_int, _i64, _i64, _vp, _i64, _i64, _u64, _int, _vp, _i64,
                                        _vp, _i64, _vp, _sz, _vp, _vp]),
     "tsqr_sketch_rows": (_int, [_i64, _i64, _vp, _i64, _i64, _u64, _vp, _i64, _vp]),
@@ -293,6 +295,28 @@ def rxr_cholqr(A: torch.Tensor, sketch_rows: int, seed: int, variant: int = RQR,
                                workspace.data_ptr(), workspace.numel(), info.data_ptr(),
                                _stream(stream))
     _check(rc, name)
+    return Q, R, info
+
+
+STATIC_SCRATCH_BYTES = 72 << 20
+
+
+def rxr_cholqr_noalloc(A: torch.Tensor, sketch_rows: int, seed: int, Q: torch.Tensor,
+                       R: torch.Tensor | None, info: torch.Tensor | None, variant: int = RQR,
+                       extra_pass: bool = True, stream=None):
+    """The no-allocation entry point: the library's fixed per-GPU scratch array serves as
+    the workspace; every output (Q, R, info) is the caller's, and this call allocates
+    nothing.  Calls that overlap in time on one GPU race.  Returns (Q, R, info)."""
+    lda = _mat(A, "A")
+    m, n = A.shape
+    ldq = _mat(Q, "Q", m, n)
+    ldr = _mat(R, "R", n, n) if R is not None else n
+    rc = load().tsqr_rxr_cholqr_noalloc(variant, m, n, A.data_ptr(), lda, sketch_rows, seed,
+                                        int(bool(extra_pass)), Q.data_ptr(), ldq,
+                                        R.data_ptr() if R is not None else None, ldr,
+                                        info.data_ptr() if info is not None else None,
+                                        _stream(stream))
+    _check(rc, "tsqr_rxr_cholqr_noalloc")
     return Q, R, info
 
 

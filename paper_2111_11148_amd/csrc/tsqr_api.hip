@@ -549,6 +549,32 @@ int run_chain_mixed(int variant, int lowp, int64_t m, int64_t n, const double* A
 
 using namespace tsqr;
 
+// ---- no-allocation entry point: the workspace lives in a device array of fixed size ----
+// Each GPU that loads the library holds its own copy of `scratch` until the process ends.
+// In host code the array's name is only a stand-in for the symbol; the device address is
+// resolved once per device (with that device current) and kept.
+static __device__ __align__(256) unsigned char scratch[TSQR_STATIC_SCRATCH_BYTES];
+
+namespace tsqr {
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_addr[64] = {nullptr};
+
+// Device address of this device's copy of `scratch`, or null on failure.
+void* static_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch_addr[dev] = ptr;
+  }
+  return g_scratch_addr[dev];
+}
+}  // namespace
+}  // namespace tsqr
+
 extern "C" {
 
 const char* tsqr_version(void) { return "libtsqr 0.1 (gfx950, FP64 MFMA)"; }
@@ -632,6 +658,32 @@ int tsqr_rxr_cholqr_ws(int variant, int64_t m, int64_t n, const double* A, int64
   if (!work) return -13;
   if (n > kMaxN) return TSQR_ERR_UNSUPPORTED;
   if (work_bytes < make_layout(m, n, sketch_rows).total) return TSQR_ERR_WORKSPACE;
+  return run_chain(variant, m, n, A, lda, sketch_rows, seed, extra_pass != 0, Q, ldq, R, ldr, work,
+                   d_info, (hipStream_t)stream);
+}
+
+int tsqr_rxr_cholqr_noalloc(int variant, int64_t m, int64_t n, const double* A, int64_t lda,
+                            int64_t sketch_rows, uint64_t seed, int extra_pass, double* Q,
+                            int64_t ldq, double* R, int64_t ldr, int* d_info, void* stream) {
+  if (variant != TSQR_VARIANT_RQR && variant != TSQR_VARIANT_RLU) return -1;
+  const ArgErr e = validate(m, n, A, lda, sketch_rows, Q, ldq, R, ldr);
+  switch (e) {
+    case E_OK: break;
+    case E_M: return -2;
+    case E_N: return -3;
+    case E_A: return -4;
+    case E_LDA: return -5;
+    case E_S: return -6;
+    case E_Q: return -9;
+    case E_LDQ: return -10;
+    case E_R: return -11;
+    case E_LDR: return -12;
+  }
+  if (n > kMaxN) return TSQR_ERR_UNSUPPORTED;
+  if (make_layout(m, n, sketch_rows).total > (size_t)TSQR_STATIC_SCRATCH_BYTES)
+    return TSQR_ERR_WORKSPACE;
+  void* work = static_scratch();
+  if (!work) return TSQR_ERR_HIP;
   return run_chain(variant, m, n, A, lda, sketch_rows, seed, extra_pass != 0, Q, ldq, R, ldr, work,
                    d_info, (hipStream_t)stream);
 }

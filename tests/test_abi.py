@@ -219,3 +219,14 @@ def test_metrics_and_probe_argument_codes(lib):
     assert h(0, 2, 8, 10, None, ctypes.byref(fl), None) == -5
     assert h(0, 2, 8, 10, out, None, None) == -6
 
+
+def test_noalloc_refuses_sizes_beyond_the_array(lib):
+    # refused before any work is enqueued: a workspace above the fixed per-GPU array
+    assert lib.tsqr_workspace_bytes(1 << 20, 256, 512) > (72 << 20)
+    assert lib.tsqr_workspace_bytes(1 << 24, 128, 256) <= (72 << 20)
+    A = ctypes.c_void_p(0x10000000)
+    Q = ctypes.c_void_p(0x7000000000)
+    f = lib.tsqr_rxr_cholqr_noalloc
+    assert f(0, 1 << 20, 256, A, 1 << 20, 512, 1, 1, Q, 1 << 20, None, 256, None, None) == -101
+    assert f(2, 1 << 20, 128, A, 1 << 20, 256, 1, 1, Q, 1 << 20, None, 128, None, None) == -1
+    assert f(0, 1 << 20, 128, A, 1 << 20, 100, 1, 1, Q, 1 << 20, None, 128, None, None) == -6
