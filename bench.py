@@ -196,18 +196,19 @@ def mixed_comparison(args, kappas):
         for name, lowp in (("fp32", tsqr.FP32), ("bf16", tsqr.BF16)):
             ws = torch.empty(tsqr.mixed_workspace_bytes(m, n, s, lowp), dtype=torch.uint8,
                              device="cuda")
-            npass = []
+            report = torch.zeros(2, dtype=torch.int32, device="cuda")
 
             def mixed():
-                npass.append(tsqr.rxr_cholqr_mixed(A, s, seed, lowp, Q=Q, R=R, workspace=ws,
-                                                   info=info)[3])
+                tsqr.rxr_cholqr_mixed(A, s, seed, lowp, Q=Q, R=R, workspace=ws, info=info,
+                                      report=report)
 
             ms_m = timed(mixed, args.mixed_steps, 2)
             o_m, r_m = gpu_metrics(A, Q, R)
             ok = o_m <= 1e-12 and row["fp64"]["ortho"] <= 1e-12 and int(info.item()) == 0
             ph = phases_of(mixed)
             row[name] = {"ms": round(ms_m, 4), "gflops_equiv": round(F / ms_m / 1e6, 2),
-                         "fp64_passes": npass[-1], "lowp_stage": "apply_lowp" in ph,
+                         "fp64_passes": int(report[0].item()),
+                         "lowp_stage": bool(report[1].item()),
                          "ortho": o_m, "residual": r_m, "info": int(info.item()),
                          "rel_R_vs_fp64_oracle": None if R_or is None else rel_r_diff(R, R_or),
                          "speedup_vs_fp64": round(ms / ms_m, 3) if ok else None,

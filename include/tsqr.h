@@ -201,13 +201,18 @@ int tsqr_cholqr_ws(int algo, int64_t m, int64_t n, const double* A, int64_t lda,
  *     FP64 A, W = Q1^T Q1, Rk = chol(W), Q = Q1 Rk^{-1}, R = Rk ... R01.
  * fp64_passes (arg 9): 1, 2 or 3 fixed FP64 passes, or 0 = automatic: a further pass runs
  *   while the Gram matrix of a pass's input deviates from I by more than 1/2 in Frobenius
- *   norm (or a breakdown occurred), at most 3 passes.  The automatic mode also skips the
- *   low-precision A1/W1/R1 stage (R01 = R0, low precision for the sketch only) unless
+ *   norm or its Cholesky factorization broke down (it is then retried with the shift
+ *   11 (m n + n (n + 1)) u ||W||_F on the diagonal, u = 2^-52, the shifted CholeskyQR of
+ *   Section 2.1), at most 3 passes.  The automatic mode also skips the low-precision
+ *   A1/W1/R1 stage (R01 = R0, low precision for the sketch only) unless
  *   ||R0||_F ||R0^{-1}||_F u_p <= 1 (u_p = 2^-24 for FP32, 2^-8 for BF16): beyond that
- *   bound on cond(R0) u_p the stage cannot save an FP64 pass.  The automatic mode waits
- *   on the host for that decision and once per pass; the fixed modes never wait and
- *   always run the stage.
- * passes_out (arg 16): host int receiving the number of FP64 passes run, or NULL.
+ *   bound on cond(R0) u_p the stage cannot save an FP64 pass.  Every decision is taken on
+ *   the device (the stage's and the passes' kernels are enqueued and return at once when
+ *   not needed), so no mode waits on the host and every mode may be captured into a graph.
+ *   If the third pass of the automatic mode still needed the shifted retry, the pass
+ *   budget ran out: *d_info = 5000 and Q and R are NaN.
+ * d_report (arg 16): NULL, or two device ints receiving [0] the number of FP64 passes
+ *   run and [1] 1 if the low-precision stage ran (0 if the automatic mode skipped it).
  * lowp (arg 2): TSQR_LOWP_FP32 or TSQR_LOWP_BF16.  Other arguments as in
  * tsqr_rxr_cholqr_ws (shifted by one position); info stages 3 and 4 are the FP64 passes.
  * Workspace: tsqr_mixed_workspace_bytes(m, n, s, lowp) bytes.  n <= 256 (the
@@ -216,7 +221,7 @@ size_t tsqr_mixed_workspace_bytes(int64_t m, int64_t n, int64_t sketch_rows, int
 int tsqr_rxr_cholqr_mixed_ws(int variant, int lowp, int64_t m, int64_t n, const double* A,
                              int64_t lda, int64_t sketch_rows, uint64_t seed, int fp64_passes,
                              double* Q, int64_t ldq, double* R, int64_t ldr, void* work,
-                             size_t work_bytes, int* d_info, int* passes_out, void* stream);
+                             size_t work_bytes, int* d_info, int* d_report, void* stream);
 
 /* Low-precision steps of the mixed variant (step-wise validation):
  *   tsqr_sketch_lowp: B = S A (s x n FP64, ldb >= s) with the entries of S and A rounded

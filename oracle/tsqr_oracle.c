@@ -791,7 +791,7 @@ int or_rxr_cholqr_mixed(int variant, int prec, int64_t m, int64_t n, const doubl
          * 11 (m n + n (n+1)) u ||W||_F on the diagonal (shifted CholeskyQR, paper
          * Section 2.1); another pass follows while dev > 1/2 or the shift was used, at
          * most three passes. */
-        int maxp = fp64_passes > 0 ? fp64_passes : 3, more = 1;
+        int maxp = fp64_passes > 0 ? fp64_passes : 3, more = 1, last_shifted = 0;
         for (int pass = 0; pass < maxp && more && !info; ++pass) {
             or_gram(m, n, Q, ldq, W, n);
             double dev2 = 0.0, w2 = 0.0;
@@ -814,8 +814,12 @@ int or_rxr_cholqr_mixed(int variant, int prec, int64_t m, int64_t n, const doubl
             or_trmm_upper(n, Rk, n, Racc, n, T, n);
             memcpy(Racc, T, nn * sizeof(double));
             ++npass;
+            last_shifted = shifted;
             if (fp64_passes == 0) more = shifted || !(sqrt(dev2) <= 0.5);
         }
+        /* the pass budget ran out: the last allowed pass itself needed the shift, so its
+         * output is not yet orthonormal */
+        if (!info && fp64_passes == 0 && npass == maxp && last_shifted) info = 5000;
     }
     if (!info)
         for (int64_t j = 0; j < n; ++j)

@@ -64,8 +64,7 @@ _SIGS = {
     "tsqr_version": (ctypes.c_char_p, []),
     "tsqr_mixed_workspace_bytes": (_sz, [_i64, _i64, _i64, _int]),
     "tsqr_rxr_cholqr_mixed_ws": (_int, [_int, _int, _i64, _i64, _vp, _i64, _i64, _u64, _int, _vp,
-                                        _i64, _vp, _i64, _vp, _sz, _vp,
-                                        ctypes.POINTER(ctypes.c_int), _vp]),
+                                        _i64, _vp, _i64, _vp, _sz, _vp, _vp, _vp]),
     "tsqr_sketch_lowp": (_int, [_int, _i64, _i64, _vp, _i64, _i64, _u64, _vp, _i64, _vp, _sz, _vp]),
     "tsqr_rinv_lowp_bytes": (_sz, [_i64, _int]),
     "tsqr_apply_rinv_lowp": (_int, [_int, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz,
@@ -396,11 +395,14 @@ def rxr_cholqr_mixed(A: torch.Tensor, sketch_rows: int, seed: int, lowp: int = F
                      variant: int = RQR, fp64_passes: int = 0, Q: torch.Tensor | None = None,
                      R: torch.Tensor | None = None, want_r: bool = True,
                      workspace: torch.Tensor | None = None, info: torch.Tensor | None = None,
-                     stream=None):
+                     report: torch.Tensor | None = None, stream=None):
     """Mixed-precision variant (low-precision sketch, apply and first Gram; FP64 passes).
 
-    fp64_passes: 1-3 fixed FP64 CholeskyQR passes, or 0 for the automatic rule.
-    Returns (Q, R, info, passes)."""
+    fp64_passes: 1-3 fixed FP64 CholeskyQR passes, or 0 for the automatic rule (decided on
+    the device: the call never waits, so it may be captured into a graph).
+    Returns (Q, R, info, report): info a 1-element int32 device tensor, report a
+    2-element one holding the number of FP64 passes run and whether the low-precision
+    stage ran (1) or was skipped (0)."""
     lda = _mat(A, "A")
     m, n = A.shape
     if Q is None:
@@ -416,14 +418,15 @@ def rxr_cholqr_mixed(A: torch.Tensor, sketch_rows: int, seed: int, lowp: int = F
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
     if info is None:
         info = torch.zeros(1, dtype=torch.int32, device=A.device)
-    passes = ctypes.c_int(0)
+    if report is None:
+        report = torch.zeros(2, dtype=torch.int32, device=A.device)
     rc = load().tsqr_rxr_cholqr_mixed_ws(variant, lowp, m, n, A.data_ptr(), lda, sketch_rows,
                                          seed, fp64_passes, Q.data_ptr(), ldq,
                                          R.data_ptr() if R is not None else None, ldr,
                                          workspace.data_ptr(), workspace.numel(),
-                                         info.data_ptr(), ctypes.byref(passes), _stream(stream))
+                                         info.data_ptr(), report.data_ptr(), _stream(stream))
     _check(rc, "tsqr_rxr_cholqr_mixed_ws")
-    return Q, R, info, passes.value
+    return Q, R, info, report
 
 
 @_on_stream

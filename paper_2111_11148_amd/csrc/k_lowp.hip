@@ -354,7 +354,9 @@ __host__ __device__ constexpr size_t rinv_elems(int jt) {
 
 template <int PREC>
 __global__ void k_rinv_prep(int n, int jt, const double* __restrict__ Rinv, int64_t ldr,
-                            typename LowT<PREC>::E* __restrict__ out) {
+                            typename LowT<PREC>::E* __restrict__ out,
+                            const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;  // gated off on the device
   const size_t total = rinv_elems<PREC>(jt);
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x) {
@@ -393,7 +395,9 @@ constexpr int kApplyThreads = 1024;
 template <int PREC, int JT, bool FULL>
 __global__ __launch_bounds__(kApplyThreads) void k_apply_rinv_lowp(
     int64_t m, int n, const double* __restrict__ Y, int64_t ldy,
-    const typename LowT<PREC>::E* __restrict__ Ri, typename LowT<PREC>::E* X, int64_t ldx) {
+    const typename LowT<PREC>::E* __restrict__ Ri, typename LowT<PREC>::E* X, int64_t ldx,
+    const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;  // gated off on the device
   typedef typename LowT<PREC>::E E;
   typedef __attribute__((address_space(1))) const double g_f64;
   typedef __attribute__((address_space(3))) E lds_e;
@@ -564,7 +568,9 @@ template <int PREC, int JT, int NW, int NS, bool VEC>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) void k_gram_lowp(int64_t m, int n,
                                                        const typename LowT<PREC>::E* __restrict__ X,
                                                        int64_t ldx, int64_t rows_per_block,
-                                                       int ntiles, double* __restrict__ part) {
+                                                       int ntiles, double* __restrict__ part,
+                                                       const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;  // gated off on the device
   typedef typename LowT<PREC>::E E;
   constexpr bool F32 = PREC == TSQR_LOWP_FP32;
   constexpr int KC = 64;
@@ -740,7 +746,7 @@ hipError_t launch_sketch_lowp(int prec, const SketchPlan& p, int64_t m, int n, c
 }
 
 hipError_t launch_rinv_prep(int prec, int n, const double* Rinv, int64_t ldr, void* out,
-                            hipStream_t st) {
+                            hipStream_t st, const int* gate) {
   const int jt = jt_pow2(n);
   if (jt > 16) return hipErrorInvalidValue;
   const size_t total = prec == TSQR_LOWP_FP32 ? rinv_elems<TSQR_LOWP_FP32>(jt)
@@ -749,15 +755,16 @@ hipError_t launch_rinv_prep(int prec, int n, const double* Rinv, int64_t ldr, vo
   if (blocks > 2048) blocks = 2048;
   if (prec == TSQR_LOWP_FP32)
     hipLaunchKernelGGL(k_rinv_prep<TSQR_LOWP_FP32>, dim3(blocks), dim3(256), 0, st, n, jt, Rinv,
-                       ldr, (float*)out);
+                       ldr, (float*)out, gate);
   else
     hipLaunchKernelGGL(k_rinv_prep<TSQR_LOWP_BF16>, dim3(blocks), dim3(256), 0, st, n, jt, Rinv,
-                       ldr, (__bf16*)out);
+                       ldr, (__bf16*)out, gate);
   return hipGetLastError();
 }
 
 hipError_t launch_apply_rinv_lowp(int prec, int64_t m, int n, const double* Y, int64_t ldy,
-                                  const void* Ri, void* X, int64_t ldx, hipStream_t st) {
+                                  const void* Ri, void* X, int64_t ldx, hipStream_t st,
+                                  const int* gate) {
   const int jt = jt_pow2(n);
   const int64_t ntiles = (m + 15) / 16;
   const int nt = kApplyThreads;
@@ -774,10 +781,10 @@ hipError_t launch_apply_rinv_lowp(int prec, int64_t m, int n, const double* Y, i
     const size_t sh = rinv_elems<PR>(J) * sizeof(E);                                           \
     if (full)                                                                                  \
       hipLaunchKernelGGL((k_apply_rinv_lowp<PR, J, true>), grid, block, sh, st, m, n, Y, ldy,   \
-                         (const E*)Ri, (E*)X, ldx);                                            \
+                         (const E*)Ri, (E*)X, ldx, gate);                                      \
     else                                                                                       \
       hipLaunchKernelGGL((k_apply_rinv_lowp<PR, J, false>), grid, block, sh, st, m, n, Y, ldy,  \
-                         (const E*)Ri, (E*)X, ldx);                                            \
+                         (const E*)Ri, (E*)X, ldx, gate);                                      \
     return hipGetLastError();                                                                  \
   }
   TSQR_APL(TSQR_LOWP_FP32, 1) TSQR_APL(TSQR_LOWP_FP32, 2) TSQR_APL(TSQR_LOWP_FP32, 4)
@@ -810,7 +817,7 @@ hipError_t launch_b_sketch_lowp(int prec, int IT, int JT, int NW, const BItem* i
 }
 
 hipError_t launch_gram_lowp(int prec, const GramPlan& p, int64_t m, int n, const void* X,
-                            int64_t ldx, double* part, hipStream_t st) {
+                            int64_t ldx, double* part, hipStream_t st, const int* gate) {
   const int64_t epl = prec == TSQR_LOWP_FP32 ? 4 : 8;
   const bool vec = ((reinterpret_cast<uintptr_t>(X) & 15) == 0) && (ldx % epl == 0) &&
                    (m % epl == 0);
@@ -820,11 +827,11 @@ hipError_t launch_gram_lowp(int prec, const GramPlan& p, int64_t m, int n, const
     if (vec)                                                                                  \
       hipLaunchKernelGGL((k_gram_lowp<PR, J, NW_, NS_, true>), dim3(p.kblocks, NS_),           \
                          dim3(NW_ * 64), 0, st, m, n, (const E*)X, ldx, p.rows_per_block,      \
-                         p.ntiles, part);                                                     \
+                         p.ntiles, part, gate);                                               \
     else                                                                                      \
       hipLaunchKernelGGL((k_gram_lowp<PR, J, NW_, NS_, false>), dim3(p.kblocks, NS_),          \
                          dim3(NW_ * 64), 0, st, m, n, (const E*)X, ldx, p.rows_per_block,      \
-                         p.ntiles, part);                                                     \
+                         p.ntiles, part, gate);                                               \
     return hipGetLastError();                                                                 \
   }
   TSQR_GRL(TSQR_LOWP_FP32, 1, 4, 1) TSQR_GRL(TSQR_LOWP_FP32, 2, 4, 1)

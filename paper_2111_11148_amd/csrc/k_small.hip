@@ -828,7 +828,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_potrf_reg(int n, const double
                                                              int64_t ldw, double* __restrict__ R,
                                                              int64_t ldr, int stage,
                                                              int* __restrict__ info,
-                                                             double shift) {
+                                                             double shift,
+                                                             const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;  // gated off on the device
   potrf_reg_body<RPL, CPW>(n, W, ldw, R, ldr, stage, info, shift);
 }
 
@@ -846,7 +848,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_potrf_reg(int n, const double
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_chol_init(int n, const double* __restrict__ W,
                                                    int64_t ldw, double* __restrict__ R,
-                                                   int64_t ldr, double shift) {
+                                                   int64_t ldr, double shift,
+                                                   const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;  // gated off on the device
   const int c = blockIdx.x;
   for (int i = threadIdx.x; i < n; i += blockDim.x)
     R[(int64_t)c * ldr + i] = (i <= c) ? W[(int64_t)c * ldw + i] + (i == c ? shift : 0.0) : 0.0;
@@ -857,7 +861,9 @@ constexpr int kCholPanelThreads = 256;
 template <int NB>
 __global__ __launch_bounds__(kCholPanelThreads) void k_chol_panel(int n, double* R, int64_t ldr,
                                                               int j0, int stage,
-                                                              int* __restrict__ info) {
+                                                              int* __restrict__ info,
+                                                              const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;  // gated off on the device
   constexpr int LDD = NB + 1;
   __shared__ double D[NB * LDD];  // D[k * LDD + c] = R11(k, c)
   __shared__ int fail_sh;
@@ -920,7 +926,9 @@ __global__ __launch_bounds__(kCholPanelThreads) void k_chol_panel(int n, double*
 // (q, c16) feeds R12(4kk + q, 16ta + c16) and R12(4kk + q, 16tb + c16); accumulator
 // register r is tile entry (4r + q, c16).
 template <int NB>
-__global__ __launch_bounds__(256) void k_chol_trail(int n, double* R, int64_t ldr, int j0) {
+__global__ __launch_bounds__(256) void k_chol_trail(int n, double* R, int64_t ldr, int j0,
+                                                    const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;  // gated off on the device
   const int lane = lane_id(), wave = wave_id();
   const int q = lane >> 4, c16 = lane & 15;
   const int ta = 4 * blockIdx.y + wave, tb = blockIdx.x;
@@ -952,19 +960,20 @@ __global__ __launch_bounds__(256) void k_chol_trail(int n, double* R, int64_t ld
 
 template <int NB>
 static hipError_t potrf_multi_t(int n, const double* W, int64_t ldw, double* R, int64_t ldr,
-                                int stage, int* info, hipStream_t st, double shift) {
+                                int stage, int* info, hipStream_t st, double shift,
+                                const int* gate) {
   static_assert(NB <= kWave && NB % 4 == 0, "one wavefront factors the diagonal block");
-  hipLaunchKernelGGL(k_chol_init, dim3(n), dim3(256), 0, st, n, W, ldw, R, ldr, shift);
+  hipLaunchKernelGGL(k_chol_init, dim3(n), dim3(256), 0, st, n, W, ldw, R, ldr, shift, gate);
   hipError_t e = hipGetLastError();
   for (int j0 = 0; j0 < n && e == hipSuccess; j0 += NB) {
     hipLaunchKernelGGL(k_chol_panel<NB>, dim3(1), dim3(kCholPanelThreads), 0, st, n, R, ldr, j0,
-                       stage, info);
+                       stage, info, gate);
     e = hipGetLastError();
     const int t = n - j0 - NB;
     if (t > 0 && e == hipSuccess) {
       const int tt = (t + 15) / 16;
       hipLaunchKernelGGL(k_chol_trail<NB>, dim3(tt, (tt + 3) / 4), dim3(256), 0, st, n, R, ldr,
-                         j0);
+                         j0, gate);
       e = hipGetLastError();
     }
   }
@@ -1000,7 +1009,9 @@ __device__ __forceinline__ void trmm_upper_body(int n, const double* __restrict_
 __global__ __launch_bounds__(256) void k_trmm_upper(int n, const double* __restrict__ A,
                                                     int64_t lda, const double* __restrict__ B,
                                                     int64_t ldb, double* __restrict__ C,
-                                                    int64_t ldc) {
+                                                    int64_t ldc,
+                                                    const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;  // gated off on the device
   trmm_upper_body(n, A, lda, B, ldb, C, ldc, (int)blockIdx.x, (int)blockIdx.y);
 }
 
@@ -1068,7 +1079,9 @@ __global__ __launch_bounds__(1024) void k_pass_decide(int n, const double* __res
                                                      int64_t ldw, const int* __restrict__ lp_info,
                                                      const int* __restrict__ info, double thresh,
                                                      int* __restrict__ need,
-                                                     double* __restrict__ dev_out) {
+                                                     double* __restrict__ dev_out,
+                                                     const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;  // gated off on the device
   __shared__ double red[1024], red2[1024];
   double acc = 0.0, acc2 = 0.0;
   // a column per 64-lane group (rows coalesced, no index division)
@@ -1413,17 +1426,18 @@ constexpr int kPotrfMultiMin = TSQR_POTRF_MULTI_MIN;  // larger n: one launch pe
 constexpr int kPotrfMultiNB = TSQR_POTRF_MULTI_NB;
 
 hipError_t launch_potrf(int n, const double* W, int64_t ldw, double* R, int64_t ldr, int stage,
-                        int* info, double* scratch, hipStream_t st, double shift) {
+                        int* info, double* scratch, hipStream_t st, double shift,
+                        const int* gate) {
   (void)scratch;
   if (n < 1 || n > kMaxS) return hipErrorInvalidValue;
   if (n > kPotrfMultiMin)
-    return potrf_multi_t<kPotrfMultiNB>(n, W, ldw, R, ldr, stage, info, st, shift);
+    return potrf_multi_t<kPotrfMultiNB>(n, W, ldw, R, ldr, stage, info, st, shift, gate);
   const int cpw = pow2_at_least((n + 15) / 16);  // n <= 64: one row of 64 lanes
   dim3 grid(1), block(kSmallThreads);
 #define TSQR_POTRF(CPW_)                                                                      \
   if (cpw == CPW_) {                                                                          \
     hipLaunchKernelGGL((k_potrf_reg<1, CPW_>), grid, block, 0, st, n, W, ldw, R, ldr, stage, \
-                       info, shift);                                                          \
+                       info, shift, gate);                                                    \
     return hipGetLastError();                                                                 \
   }
   TSQR_POTRF(1) TSQR_POTRF(2) TSQR_POTRF(4)
@@ -1432,9 +1446,10 @@ hipError_t launch_potrf(int n, const double* W, int64_t ldw, double* R, int64_t 
 }
 
 hipError_t launch_trmm_upper(int n, const double* A, int64_t lda, const double* B, int64_t ldb,
-                             double* C, int64_t ldc, hipStream_t st) {
+                             double* C, int64_t ldc, hipStream_t st, const int* gate) {
   const int nb = (n + 15) / 16;
-  hipLaunchKernelGGL(k_trmm_upper, dim3(nb, nb), dim3(256), 0, st, n, A, lda, B, ldb, C, ldc);
+  hipLaunchKernelGGL(k_trmm_upper, dim3(nb, nb), dim3(256), 0, st, n, A, lda, B, ldb, C, ldc,
+                     gate);
   return hipGetLastError();
 }
 
@@ -1468,23 +1483,81 @@ hipError_t launch_trmm_or_copy(const int* flag, int n, const double* A, int64_t 
 // W(k, k) += coef * (*scale) (or coef when scale is null): the diagonal shift of the first
 // Gram matrix in shifted CholeskyQR, with the scale read on the device (no host wait).
 __global__ __launch_bounds__(256) void k_add_diag(int n, double* __restrict__ W, int64_t ldw,
-                                                  double coef, const double* __restrict__ scale) {
+                                                  double coef, const double* __restrict__ scale,
+                                                  const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;  // gated off on the device
   const double sh = scale ? coef * *scale : coef;
   for (int k = threadIdx.x + blockIdx.x * blockDim.x; k < n; k += blockDim.x * gridDim.x)
     W[(int64_t)k * ldw + k] += sh;
 }
 
 hipError_t launch_add_diag(int n, double* W, int64_t ldw, double coef, const double* scale,
-                           hipStream_t st) {
-  hipLaunchKernelGGL(k_add_diag, dim3((n + 255) / 256), dim3(256), 0, st, n, W, ldw, coef, scale);
+                           hipStream_t st, const int* gate) {
+  hipLaunchKernelGGL(k_add_diag, dim3((n + 255) / 256), dim3(256), 0, st, n, W, ldw, coef, scale,
+                     gate);
   return hipGetLastError();
 }
 
 hipError_t launch_pass_decide(int n, const double* W, int64_t ldw, const int* lp_info,
                               const int* info, double thresh, int* need, double* dev_out,
-                              hipStream_t st) {
+                              hipStream_t st, const int* gate) {
   hipLaunchKernelGGL(k_pass_decide, dim3(1), dim3(1024), 0, st, n, W, ldw, lp_info, info, thresh,
-                     need, dev_out);
+                     need, dev_out, gate);
+  return hipGetLastError();
+}
+
+// ---- decisions of the mixed-precision chain (one thread) ---------------------------------
+__global__ void k_mixed_ctl(int op, int k, int arg, double arg2, MixedCtl* __restrict__ c,
+                            int* __restrict__ info, int* __restrict__ d_passes) {
+  switch (op) {
+    case kCtlInit:
+      c->stage = 1;
+      c->lp_info = 0;
+      for (int p = 0; p <= kMaxMixedPasses; ++p) c->gate[p] = arg > 0 ? (p < arg) : (p == 0);
+      for (int p = 0; p < kMaxMixedPasses; ++p) {
+        c->skip[p] = 0;
+        c->bd[p] = 0;
+        c->shifted[p] = 0;
+      }
+      c->one = 1;
+      c->passes = 0;
+      break;
+    case kCtlStage:
+      c->stage = (c->norms[1] * c->norms[3] * arg2 <= 1.0) ? 1 : 0;
+      c->lp_info = c->stage ? 0 : -1;
+      break;
+    case kCtlPassBegin:
+      c->bd[k] = 0;
+      c->skip[k] = c->gate[k] ? 0 : 1;
+      break;
+    case kCtlShift:
+      c->shifted[k] = (c->gate[k] && c->bd[k] != 0) ? 1 : 0;
+      break;
+    case kCtlNext:
+      // another pass while this pass needed the shift or its input's Gram matrix deviated
+      // from I by more than arg2 (NaN counts as deviating)
+      c->gate[k + 1] = (k + 1 < arg && c->gate[k] &&
+                        (c->shifted[k] || !(c->dev[k][0] <= arg2))) ? 1 : 0;
+      break;
+    case kCtlEnd: {
+      int p = 0;
+      for (int q = 0; q < kMaxMixedPasses; ++q) p += c->gate[q];
+      c->passes = p;
+      if (p == arg && arg > 0 && c->shifted[arg - 1] && info && *info == 0) *info = 5000;
+      if (d_passes) {
+        d_passes[0] = p;
+        d_passes[1] = c->stage;
+      }
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+hipError_t launch_mixed_ctl(int op, int k, int arg, double arg2, MixedCtl* c, int* info,
+                            int* d_passes, hipStream_t st) {
+  hipLaunchKernelGGL(k_mixed_ctl, dim3(1), dim3(1), 0, st, op, k, arg, arg2, c, info, d_passes);
   return hipGetLastError();
 }
 

@@ -116,7 +116,9 @@ __device__ __forceinline__ void trsm_prep_body(int n, int jt, const double* __re
 }
 
 __global__ __launch_bounds__(256) void k_trsm_prep(int n, int jt, const double* __restrict__ T,
-                                                   int64_t ldt, double* __restrict__ P) {
+                                                   int64_t ldt, double* __restrict__ P,
+                                                   const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;  // gated off on the device
   trsm_prep_body(n, jt, T, ldt, P, (int)blockIdx.x);
 }
 
@@ -227,7 +229,9 @@ template <int JT, bool kLds>
 __global__ __launch_bounds__(kTrsmThreads, 1) void k_trsm_mfma(int64_t m, int n,
                                                       const double* __restrict__ Y, int64_t ldy,
                                                       const double* __restrict__ P,
-                                                      double* X, int64_t ldx) {
+                                                      double* X, int64_t ldx,
+                                                      const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;  // gated off on the device
   trsm_mfma_body<JT, kLds>(m, n, Y, ldy, P, X, ldx, (int)blockIdx.x, (int)gridDim.x);
 }
 
@@ -248,7 +252,9 @@ __global__ __launch_bounds__(1024, 1) void k_trsm_fused(int64_t m, int n, int K,
                                                        const double* __restrict__ Tk,
                                                        int64_t ldt, const double* Y, int64_t ldy,
                                                        const double* __restrict__ P, double* Xk,
-                                                       int64_t ldxk) {
+                                                       int64_t ldxk,
+                                                       const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;  // gated off on the device
   constexpr int NOFF = JT * (JT - 1) / 2;
   constexpr int NTILE = NOFF + 2 * JT;
   constexpr int KCH = 32;          // rows of T per staged chunk (8 K-steps)
@@ -362,16 +368,17 @@ size_t trsm_scratch_doubles(int n) {
 }
 
 static hipError_t launch_trsm_block(int64_t m, int n, const double* Y, int64_t ldy,
-                                    double* X, int64_t ldx, double* scratch, hipStream_t st);
+                                    double* X, int64_t ldx, double* scratch, hipStream_t st,
+                                    const int* gate);
 
 // Operand preparation of the first column block (all of T up to kBlk columns).
 hipError_t launch_trsm_prepare(int n, const double* T, int64_t ldt, double* scratch,
-                               hipStream_t st) {
+                               hipStream_t st, const int* gate) {
   if (n <= 0) return hipSuccess;
   const int nb = n < kBlk ? n : kBlk;
   int jt = 1;
   while (jt < (nb + 15) / 16) jt <<= 1;
-  hipLaunchKernelGGL(k_trsm_prep, dim3(jt), dim3(256), 0, st, nb, jt, T, ldt, scratch);
+  hipLaunchKernelGGL(k_trsm_prep, dim3(jt), dim3(256), 0, st, nb, jt, T, ldt, scratch, gate);
   return hipGetLastError();
 }
 
@@ -381,19 +388,19 @@ hipError_t launch_trsm_prepare(int n, const double* T, int64_t ldt, double* scra
 // substitution).
 hipError_t launch_trsm_solve(int64_t m, int n, const double* Y, int64_t ldy, const double* T,
                              int64_t ldt, double* X, int64_t ldx, double* scratch,
-                             hipStream_t st) {
+                             hipStream_t st, const int* gate) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  if (n <= kBlk) return launch_trsm_block(m, n, Y, ldy, X, ldx, scratch, st);
+  if (n <= kBlk) return launch_trsm_block(m, n, Y, ldy, X, ldx, scratch, st, gate);
   const int64_t ntiles = (m + 15) / 16;
   const int64_t cap = (int64_t)device_cu_count();
-  hipError_t e = launch_trsm_block(m, kBlk, Y, ldy, X, ldx, scratch, st);
+  hipError_t e = launch_trsm_block(m, kBlk, Y, ldy, X, ldx, scratch, st, gate);
   if (e != hipSuccess) return e;
   for (int k0 = kBlk; k0 < n; k0 += kBlk) {
     const int nbk = (n - k0) < kBlk ? (n - k0) : kBlk;
     int jt = 1;
     while (jt < (nbk + 15) / 16) jt <<= 1;
     hipLaunchKernelGGL(k_trsm_prep, dim3(jt), dim3(256), 0, st, nbk, jt,
-                       T + (int64_t)k0 * ldt + k0, ldt, scratch);
+                       T + (int64_t)k0 * ldt + k0, ldt, scratch, gate);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t ngroups = (ntiles + 15) / 16;
@@ -404,7 +411,7 @@ hipError_t launch_trsm_solve(int64_t m, int n, const double* Y, int64_t ldy, con
   if (jt == J) {                                                                               \
     const size_t sh = ((size_t)(J * (J - 1) / 2 + 2 * J) * 256 + 32 * (16 * J + 1)) * sizeof(double); \
     hipLaunchKernelGGL(k_trsm_fused<J>, dim3((unsigned)grid), dim3(1024), sh, st, m, nbk, k0, X,  \
-                       ldx, T + (int64_t)k0 * ldt, ldt, yk, ldy, scratch, xk, ldx);             \
+                       ldx, T + (int64_t)k0 * ldt, ldt, yk, ldy, scratch, xk, ldx, gate);             \
   }
     TSQR_TF(1) TSQR_TF(2) TSQR_TF(4) TSQR_TF(8)
 #undef TSQR_TF
@@ -415,16 +422,18 @@ hipError_t launch_trsm_solve(int64_t m, int n, const double* Y, int64_t ldy, con
 }
 
 hipError_t launch_trsm(int64_t m, int n, const double* Y, int64_t ldy, const double* T,
-                       int64_t ldt, double* X, int64_t ldx, double* scratch, hipStream_t st) {
+                       int64_t ldt, double* X, int64_t ldx, double* scratch, hipStream_t st,
+                       const int* gate) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  const hipError_t e = launch_trsm_prepare(n, T, ldt, scratch, st);
+  const hipError_t e = launch_trsm_prepare(n, T, ldt, scratch, st, gate);
   if (e != hipSuccess) return e;
-  return launch_trsm_solve(m, n, Y, ldy, T, ldt, X, ldx, scratch, st);
+  return launch_trsm_solve(m, n, Y, ldy, T, ldt, X, ldx, scratch, st, gate);
 }
 
 // The substitution kernel over up to kBlk columns, operands prepared in `scratch`.
 static hipError_t launch_trsm_block(int64_t m, int n, const double* Y, int64_t ldy,
-                                    double* X, int64_t ldx, double* scratch, hipStream_t st) {
+                                    double* X, int64_t ldx, double* scratch, hipStream_t st,
+                                    const int* gate) {
   int jt = 1;
   while (jt < (n + 15) / 16) jt <<= 1;
   if (jt > 8) return hipErrorInvalidValue;
@@ -437,7 +446,7 @@ static hipError_t launch_trsm_block(int64_t m, int n, const double* Y, int64_t l
   if (jt == J) {                                                                           \
     const size_t sh = L ? (size_t)(J * (J - 1) / 2 + 2 * J) * 256 * sizeof(double) : 0;    \
     hipLaunchKernelGGL((k_trsm_mfma<J, L>), grid, block, sh, st, m, n, Y, ldy, scratch, X, \
-                       ldx);                                                               \
+                       ldx, gate);                                                         \
     return hipGetLastError();                                                              \
   }
   TSQR_TRSM(1, true) TSQR_TRSM(2, true) TSQR_TRSM(4, true) TSQR_TRSM(8, true)
@@ -589,7 +598,9 @@ __device__ __forceinline__ void gram_f64_body(int64_t m, int n, const double* __
 template <int JT, int NW, int NS, bool VEC>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) void k_gram_f64(
     int64_t m, int n, const double* __restrict__ X, int64_t ldx, int64_t rows_per_block,
-    int ntiles, double* __restrict__ part) {
+    int ntiles, double* __restrict__ part,
+    const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;  // gated off on the device
   gram_f64_body<JT, NW, NS, VEC>(m, n, X, ldx, rows_per_block, ntiles, part, (int)blockIdx.x,
                                  (int)blockIdx.y);
 }
@@ -623,7 +634,9 @@ __device__ __forceinline__ void gram_reduce_body(int kblocks, int ntiles, int n,
 
 __global__ __launch_bounds__(256) void k_gram_reduce(int kblocks, int ntiles, int n,
                                                      const double* __restrict__ part,
-                                                     double* __restrict__ W, int64_t ldw) {
+                                                     double* __restrict__ W, int64_t ldw,
+                                                     const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;  // gated off on the device
   gram_reduce_body(kblocks, ntiles, n, part, W, ldw, (int)blockIdx.x);
 }
 
@@ -646,7 +659,9 @@ __host__ __device__ inline void wide_pair(int t, int& bi, int& bj) {
 
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k_gram_wide(
     int64_t m, int n, const double* __restrict__ X, int64_t ldx, int64_t rows_per_block,
-    int npairs, double* __restrict__ part) {
+    int npairs, double* __restrict__ part,
+    const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;  // gated off on the device
   constexpr int KC = 32, NC = kWideBlk, LDN = NC + 1;
   constexpr int THREADS = 512;
   constexpr int CPP = THREADS / (KC / 2);      // 32 columns per pass
@@ -707,7 +722,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
 // diagonal block pair only the entries with i <= j are taken (each written once).
 __global__ __launch_bounds__(256) void k_gram_wide_reduce(int kblocks, int npairs, int n,
                                                           const double* __restrict__ part,
-                                                          double* __restrict__ W, int64_t ldw) {
+                                                          double* __restrict__ W, int64_t ldw,
+                                                          const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;  // gated off on the device
   __shared__ double red[16][17];
   const size_t E = (size_t)npairs * 64 * 256;
   const int g = threadIdx.x / 16, o = threadIdx.x % 16;
@@ -763,10 +780,10 @@ GramPlan plan_gram(int64_t m, int n) {
 }
 
 hipError_t launch_gram(const GramPlan& p, int64_t m, int n, const double* X, int64_t ldx,
-                       double* part, hipStream_t st) {
+                       double* part, hipStream_t st, const int* gate) {
   if (p.wide) {
     hipLaunchKernelGGL(k_gram_wide, dim3(p.kblocks, p.npairs), dim3(512), 0, st, m, n, X, ldx,
-                       p.rows_per_block, p.npairs, part);
+                       p.rows_per_block, p.npairs, part, gate);
     return hipGetLastError();
   }
   const bool vec = ((reinterpret_cast<uintptr_t>(X) & 15) == 0) && ((ldx & 1) == 0) &&
@@ -776,10 +793,10 @@ hipError_t launch_gram(const GramPlan& p, int64_t m, int n, const double* X, int
     const dim3 grid(p.kblocks, NS_);                                                       \
     if (vec)                                                                               \
       hipLaunchKernelGGL((k_gram_f64<J, NW_, NS_, true>), grid, dim3(NW_ * 64), 0, st, m, n, \
-                         X, ldx, p.rows_per_block, p.ntiles, part);                        \
+                         X, ldx, p.rows_per_block, p.ntiles, part, gate);                  \
     else                                                                                   \
       hipLaunchKernelGGL((k_gram_f64<J, NW_, NS_, false>), grid, dim3(NW_ * 64), 0, st, m,  \
-                         n, X, ldx, p.rows_per_block, p.ntiles, part);                     \
+                         n, X, ldx, p.rows_per_block, p.ntiles, part, gate);               \
     return hipGetLastError();                                                               \
   }
   TSQR_GRAM(1, 4, 1) TSQR_GRAM(2, 4, 1) TSQR_GRAM(4, 4, 1) TSQR_GRAM(8, 4, 1)
@@ -789,17 +806,17 @@ hipError_t launch_gram(const GramPlan& p, int64_t m, int n, const double* X, int
 }
 
 hipError_t launch_gram_reduce(const GramPlan& p, int n, const double* part, double* W,
-                              int64_t ldw, hipStream_t st) {
+                              int64_t ldw, hipStream_t st, const int* gate) {
   if (p.wide) {
     const size_t E = (size_t)p.npairs * 64 * 256;
     hipLaunchKernelGGL(k_gram_wide_reduce, dim3((unsigned)((E + 15) / 16)), dim3(256), 0, st,
-                       p.kblocks, p.npairs, n, part, W, ldw);
+                       p.kblocks, p.npairs, n, part, W, ldw, gate);
     return hipGetLastError();
   }
   const size_t E = (size_t)p.ntiles * 256;
   const int blocks = (int)((E + 15) / 16);
   hipLaunchKernelGGL(k_gram_reduce, dim3(blocks), dim3(256), 0, st, p.kblocks, p.ntiles, n, part,
-                     W, ldw);
+                     W, ldw, gate);
   return hipGetLastError();
 }
 

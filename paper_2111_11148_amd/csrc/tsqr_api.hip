@@ -391,11 +391,10 @@ int run_lstsq(int variant, int sketch_kind, int64_t m, int64_t n, const double* 
 
 // ---- mixed precision ---------------------------------------------------------------
 // Extra workspace after the FP64 layout: A1 in the input type, R0^{-1} (FP64 and rounded),
-// identity, R01 = R1 R0, two more n x n factors, the low-precision breakdown word, the
-// pass decision and the deviation ||W - I||_F.
+// identity, R01 = R1 R0, two more n x n factors and the chain's control words.
 struct MixedLayout {
   Layout base;
-  size_t A1, Rinv, Ri_lp, Id, R01, R3, Rt, lp_info, need, dev, total;
+  size_t A1, Rinv, Ri_lp, Id, R01, R3, Rt, ctl, total;
 };
 
 MixedLayout make_mixed_layout(int64_t m, int64_t n, int64_t s, int lowp) {
@@ -410,9 +409,7 @@ MixedLayout make_mixed_layout(int64_t m, int64_t n, int64_t s, int lowp) {
   L.R01 = off; off += align256(nn);
   L.R3 = off; off += align256(nn);
   L.Rt = off; off += align256(nn);
-  L.lp_info = off; off += 256;
-  L.need = off; off += 256;
-  L.dev = off; off += 256;
+  L.ctl = off; off += align256(sizeof(MixedCtl));
   L.total = off;
   return L;
 }
@@ -425,15 +422,12 @@ constexpr double kPassThresh = 0.5;
 // runs only when ||R0||_F ||R0^{-1}||_F u_p <= 1, an upper bound of cond(R0) u_p: then the
 // rounding of A to the input type perturbs A R0^{-1} by well under one and the stage can
 // leave a single FP64 pass. Otherwise it could not save a pass, and the FP64 passes start
-// from A R0^{-1} (low precision for the sketch only).
-inline bool use_lowp_stage(int lowp, double r0_fro, double rinv_fro) {
-  const double up = lowp == TSQR_LOWP_BF16 ? 0x1p-8 : 0x1p-24;
-  return r0_fro * rinv_fro * up <= 1.0;
-}
+// from A R0^{-1} (low precision for the sketch only).  u_p of each input type:
+inline double lowp_unit(int lowp) { return lowp == TSQR_LOWP_BF16 ? 0x1p-8 : 0x1p-24; }
 
 int run_chain_mixed(int variant, int lowp, int64_t m, int64_t n, const double* A, int64_t lda,
                     int64_t s, uint64_t seed, int fp64_passes, double* Q, int64_t ldq,
-                    double* R, int64_t ldr, void* work, int* d_info, int* passes_out,
+                    double* R, int64_t ldr, void* work, int* d_info, int* d_report,
                     hipStream_t st) {
   const MixedLayout M = make_mixed_layout(m, n, s, lowp);
   const Layout& L = M.base;
@@ -455,14 +449,13 @@ int run_chain_mixed(int variant, int lowp, int64_t m, int64_t n, const double* A
   double* R01 = (double*)(base + M.R01);
   double* R3 = (double*)(base + M.R3);
   double* Rt = (double*)(base + M.Rt);
-  int* lp_info = (int*)(base + M.lp_info);
-  int* need = (int*)(base + M.need);
-  double* dev = (double*)(base + M.dev);
+  MixedCtl* c = (MixedCtl*)(base + M.ctl);
   const int ni = (int)n, si = (int)s;
-  const int max_passes = fp64_passes > 0 ? fp64_passes : 3;
+  const bool automatic = fp64_passes == 0;
+  const int max_passes = automatic ? kMaxMixedPasses : fp64_passes;
 
   TSQR_CHECK(launch_set_int(info, 0, st));
-  TSQR_CHECK(launch_set_int(lp_info, 0, st));
+  TSQR_CHECK(launch_mixed_ctl(kCtlInit, 0, fp64_passes, 0.0, c, info, nullptr, st));
   // low-precision sketch, FP64 factor of the sketch, FP64 inverse
   TSQR_PHASE("sketch_lowp", launch_sketch_lowp(lowp, L.sp, m, ni, A, lda, seed, part, st));
   TSQR_PHASE("sketch_reduce",
@@ -471,76 +464,62 @@ int run_chain_mixed(int variant, int lowp, int64_t m, int64_t n, const double* A
              launch_sketch_factor(variant, si, ni, B, s, R0, n, info, fac, st));
   TSQR_CHECK(launch_identity(ni, Id, st));
   TSQR_PHASE("trtri_r0", launch_trsm(n, ni, Id, n, R0, n, Rinv, n, Tt, st));
-  bool stage = true;
-  if (fp64_passes == 0) {
-    // ||R0||_F into dev[1], ||R0^{-1}||_F into dev[3] (dev[0], dev[2] and need[0] are
-    // scratch here), read on the host
-    double h[4] = {0.0, 0.0, 0.0, 0.0};
-    TSQR_CHECK(launch_pass_decide(ni, R0, n, nullptr, nullptr, 0.0, need, dev, st));
-    TSQR_CHECK(launch_pass_decide(ni, Rinv, n, nullptr, nullptr, 0.0, need, dev + 2, st));
-    TSQR_CHECK(hipMemcpyAsync(h, dev, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
-    TSQR_CHECK(hipStreamSynchronize(st));
-    stage = use_lowp_stage(lowp, h[1], h[3]);
+  if (automatic) {
+    // ||R0||_F and ||R0^{-1}||_F on the device, then the stage decision (R12)
+    TSQR_CHECK(launch_pass_decide(ni, R0, n, nullptr, nullptr, 0.0, c->need + 3, c->norms, st));
+    TSQR_CHECK(launch_pass_decide(ni, Rinv, n, nullptr, nullptr, 0.0, c->need + 4, c->norms + 2,
+                                  st));
+    TSQR_CHECK(launch_mixed_ctl(kCtlStage, 0, 0, lowp_unit(lowp), c, info, nullptr, st));
   }
-  if (stage) {
-    TSQR_PHASE("rinv_round", launch_rinv_prep(lowp, ni, Rinv, n, Ri_lp, st));
-    // low-precision preconditioner apply and first Gram matrix
-    TSQR_PHASE("apply_lowp", launch_apply_rinv_lowp(lowp, m, ni, A, lda, Ri_lp, A1, m, st));
-    TSQR_PHASE("gram_lowp", launch_gram_lowp(lowp, L.gp, m, ni, A1, m, part, st));
-    TSQR_PHASE("gram1_reduce", launch_gram_reduce(L.gp, ni, part, W, n, st));
-    TSQR_PHASE("potrf1", launch_potrf(ni, W, n, R1, n, 2, lp_info, fac, st));
-  } else {
-    TSQR_CHECK(launch_set_int(lp_info, -1, st));  // stage not run: R01 = R0
-  }
+  // low-precision preconditioner apply, first Gram matrix and its Cholesky factor (gated:
+  // in the automatic mode they return at once when the stage is not worth running)
+  const int* sg = &c->stage;
+  TSQR_PHASE("rinv_round", launch_rinv_prep(lowp, ni, Rinv, n, Ri_lp, st, sg));
+  TSQR_PHASE("apply_lowp", launch_apply_rinv_lowp(lowp, m, ni, A, lda, Ri_lp, A1, m, st, sg));
+  TSQR_PHASE("gram_lowp", launch_gram_lowp(lowp, L.gp, m, ni, A1, m, part, st, sg));
+  TSQR_PHASE("gram1_reduce", launch_gram_reduce(L.gp, ni, part, W, n, st, sg));
+  TSQR_PHASE("potrf1", launch_potrf(ni, W, n, R1, n, 2, &c->lp_info, fac, st, 0.0, sg));
   // R01 = R1 R0, or R0 alone when the low-precision Cholesky broke down or did not run
-  TSQR_PHASE("trmm", launch_trmm_or_copy(lp_info, ni, R1, n, R0, n, R01, n, st));
-  // FP64 CholeskyQR passes on A R01^{-1}
+  TSQR_PHASE("trmm", launch_trmm_or_copy(&c->lp_info, ni, R1, n, R0, n, R01, n, st));
+  // FP64 CholeskyQR passes on A R01^{-1}, from the FP64 A
   TSQR_PHASE("trsm_r01", launch_trsm(m, ni, A, lda, R01, n, Q, ldq, Tt, st));
-  // FP64 CholeskyQR passes.  Fixed mode: exactly fp64_passes passes, no waiting.
-  // Automatic mode (fp64_passes == 0): the host reads, per pass, the deviation
-  // ||W - I||_F and ||W||_F of the pass's Gram matrix and the Cholesky status; a
-  // breakdown is retried once with the shift 11 (m n + n (n + 1)) u ||W||_F on the
-  // diagonal (the shifted CholeskyQR of the paper's Section 2.1), and another pass
-  // follows while the pass input deviated by more than 1/2 or needed the shift.
+  // Pass k (gated by gate[k]): W = Q^T Q, Rk = chol(W), Q = Q Rk^{-1}, R = Rk R.  Fixed
+  // mode: exactly fp64_passes passes.  Automatic mode: a breakdown is retried with the
+  // shift 11 (m n + n (n + 1)) u ||W||_F on the diagonal (the shifted CholeskyQR of the
+  // paper's Section 2.1), and pass k + 1 runs while pass k needed the shift or its input
+  // deviated from orthonormality by more than the threshold.  Every decision is taken by
+  // a one-thread kernel from device data; the host never waits.
   double* Rcur = R01;  // R accumulated so far
-  int passes = 0;
-  bool more = true;
-  for (int pass = 0; pass < max_passes && more; ++pass) {
+  for (int pass = 0; pass < max_passes; ++pass) {
     double* Rk = (pass == 0) ? R2 : R3;
     double* Rnext = (Rcur == Racc) ? Rt : Racc;
     const int stage = 3 + (pass > 0);
-    TSQR_PHASE("gram", launch_gram(L.gp, m, ni, Q, ldq, part, st));
-    TSQR_PHASE("gram_reduce", launch_gram_reduce(L.gp, ni, part, W, n, st));
-    if (fp64_passes == 0) {
-      double hdev[2] = {0.0, 0.0};
-      int hpi = 0;
-      TSQR_CHECK(launch_set_int(need + 1, 0, st));
-      TSQR_CHECK(launch_pass_decide(ni, W, n, nullptr, nullptr, kPassThresh, need, dev, st));
-      TSQR_PHASE("potrf", launch_potrf(ni, W, n, Rk, n, stage, need + 1, fac, st));
-      TSQR_CHECK(hipMemcpyAsync(hdev, dev, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-      TSQR_CHECK(hipMemcpyAsync(&hpi, need + 1, sizeof(int), hipMemcpyDeviceToHost, st));
-      TSQR_CHECK(hipStreamSynchronize(st));
-      bool shifted = false;
-      if (hpi != 0) {
-        const double u = kMachEps;
-        const double shift =
-            11.0 * ((double)m * (double)n + (double)n * (double)(n + 1)) * u * hdev[1];
-        TSQR_PHASE("potrf_shifted", launch_potrf(ni, W, n, Rk, n, stage, info, fac, st, shift));
-        shifted = true;
-      }
-      more = shifted || !(hdev[0] <= kPassThresh);
+    const int* g = &c->gate[pass];
+    TSQR_CHECK(launch_mixed_ctl(kCtlPassBegin, pass, 0, 0.0, c, info, nullptr, st));
+    TSQR_PHASE("gram", launch_gram(L.gp, m, ni, Q, ldq, part, st, g));
+    TSQR_PHASE("gram_reduce", launch_gram_reduce(L.gp, ni, part, W, n, st, g));
+    if (automatic) {
+      TSQR_CHECK(launch_pass_decide(ni, W, n, nullptr, nullptr, kPassThresh, c->need + pass,
+                                    c->dev[pass], st, g));
+      TSQR_PHASE("potrf", launch_potrf(ni, W, n, Rk, n, stage, &c->bd[pass], fac, st, 0.0, g));
+      TSQR_CHECK(launch_mixed_ctl(kCtlShift, pass, 0, 0.0, c, info, nullptr, st));
+      const double coef = 11.0 * ((double)m * (double)n + (double)n * (double)(n + 1)) * kMachEps;
+      const int* sh = &c->shifted[pass];
+      TSQR_CHECK(launch_add_diag(ni, W, n, coef, &c->dev[pass][1], st, sh));
+      TSQR_PHASE("potrf_shifted", launch_potrf(ni, W, n, Rk, n, stage, info, fac, st, 0.0, sh));
     } else {
-      TSQR_PHASE("potrf", launch_potrf(ni, W, n, Rk, n, stage, info, fac, st));
+      TSQR_PHASE("potrf", launch_potrf(ni, W, n, Rk, n, stage, info, fac, st, 0.0, g));
     }
-    TSQR_PHASE("trsm", launch_trsm(m, ni, Q, ldq, Rk, n, Q, ldq, Tt, st));
-    TSQR_PHASE("trmm", launch_trmm_upper(ni, Rk, n, Rcur, n, Rnext, n, st));
+    TSQR_PHASE("trsm", launch_trsm(m, ni, Q, ldq, Rk, n, Q, ldq, Tt, st, g));
+    TSQR_PHASE("trmm", launch_trmm_or_copy(&c->skip[pass], ni, Rk, n, Rcur, n, Rnext, n, st));
+    if (automatic)
+      TSQR_CHECK(launch_mixed_ctl(kCtlNext, pass, max_passes, kPassThresh, c, info, nullptr, st));
     Rcur = Rnext;
-    ++passes;
   }
-  if (R) TSQR_CHECK(hipMemcpy2DAsync(R, ldr * sizeof(double), Rcur, n * sizeof(double),
-                                     n * sizeof(double), n, hipMemcpyDeviceToDevice, st));
+  TSQR_CHECK(
+      launch_mixed_ctl(kCtlEnd, 0, automatic ? max_passes : 0, 0.0, c, info, d_report, st));
+  if (R) TSQR_PHASE("trmm", launch_trmm_or_copy(&c->one, ni, Rcur, n, Rcur, n, R, ldr, st));
   TSQR_PHASE("poison", launch_poison(info, m, ni, Q, ldq, R, ldr, st));
-  if (passes_out) *passes_out = passes;
   return TSQR_OK;
 }
 
@@ -793,7 +772,7 @@ size_t tsqr_mixed_workspace_bytes(int64_t m, int64_t n, int64_t sketch_rows, int
 int tsqr_rxr_cholqr_mixed_ws(int variant, int lowp, int64_t m, int64_t n, const double* A,
                              int64_t lda, int64_t sketch_rows, uint64_t seed, int fp64_passes,
                              double* Q, int64_t ldq, double* R, int64_t ldr, void* work,
-                             size_t work_bytes, int* d_info, int* passes_out, void* stream) {
+                             size_t work_bytes, int* d_info, int* d_report, void* stream) {
   if (variant != TSQR_VARIANT_RQR && variant != TSQR_VARIANT_RLU) return -1;
   if (lowp != TSQR_LOWP_FP32 && lowp != TSQR_LOWP_BF16) return -2;
   const ArgErr e = validate(m, n, A, lda, sketch_rows, Q, ldq, R, ldr);
@@ -814,7 +793,7 @@ int tsqr_rxr_cholqr_mixed_ws(int variant, int lowp, int64_t m, int64_t n, const 
   if (n > kMaxNLowp) return TSQR_ERR_UNSUPPORTED;
   if (work_bytes < make_mixed_layout(m, n, sketch_rows, lowp).total) return TSQR_ERR_WORKSPACE;
   return run_chain_mixed(variant, lowp, m, n, A, lda, sketch_rows, seed, fp64_passes, Q, ldq, R,
-                         ldr, work, d_info, passes_out, (hipStream_t)stream);
+                         ldr, work, d_info, d_report, (hipStream_t)stream);
 }
 
 int tsqr_sketch_lowp(int lowp, int64_t m, int64_t n, const double* A, int64_t lda, int64_t s,

@@ -35,26 +35,30 @@ struct GramPlan {
 GramPlan plan_gram(int64_t m, int n);
 
 // ---- launchers ----------------------------------------------------------------------
+// The launchers that take `gate` (a device int, or null) enqueue kernels that return at
+// once when *gate == 0: a chain can then decide on the device whether a step runs, with
+// no host wait, and stays capturable in a graph.
 hipError_t launch_sketch(const SketchPlan& p, int64_t m, int n, const double* A, int64_t lda,
                          int s, uint64_t seed, double* part, hipStream_t st);
 // B(s x n, ld ldb) = scale * sum of the sketch partials
 hipError_t launch_sketch_reduce(const SketchPlan& p, int s, int n, const double* part,
                                 double scale, double* B, int64_t ldb, hipStream_t st);
 hipError_t launch_gram(const GramPlan& p, int64_t m, int n, const double* X, int64_t ldx,
-                       double* part, hipStream_t st);
+                       double* part, hipStream_t st, const int* gate = nullptr);
 // W(n x n, ld ldw, both triangles) = sum of the Gram partials
 hipError_t launch_gram_reduce(const GramPlan& p, int n, const double* part, double* W,
-                              int64_t ldw, hipStream_t st);
+                              int64_t ldw, hipStream_t st, const int* gate = nullptr);
 // X = Y T^{-1} (T upper n x n); X may alias Y; `scratch` holds trsm_scratch_doubles(n)
 size_t trsm_scratch_doubles(int n);
 hipError_t launch_trsm(int64_t m, int n, const double* Y, int64_t ldy, const double* T,
-                       int64_t ldt, double* X, int64_t ldx, double* scratch, hipStream_t st);
+                       int64_t ldt, double* X, int64_t ldx, double* scratch, hipStream_t st,
+                       const int* gate = nullptr);
 // the same in two steps: operand preparation (k_trsm_prep), then the solve
 hipError_t launch_trsm_prepare(int n, const double* T, int64_t ldt, double* scratch,
-                               hipStream_t st);
+                               hipStream_t st, const int* gate = nullptr);
 hipError_t launch_trsm_solve(int64_t m, int n, const double* Y, int64_t ldy, const double* T,
                              int64_t ldt, double* X, int64_t ldx, double* scratch,
-                             hipStream_t st);
+                             hipStream_t st, const int* gate = nullptr);
 // R0 from the s x n sketch: Householder (variant 0) or partial-pivot LU (variant 1);
 // `scratch` holds sketch_factor_scratch_doubles(s, n) doubles.
 size_t sketch_factor_scratch_doubles(int s, int n);
@@ -63,17 +67,18 @@ hipError_t launch_sketch_factor(int variant, int s, int n, const double* B, int6
                                 hipStream_t st);
 // Cholesky of the symmetric W (both triangles stored) into upper R; info stage
 hipError_t launch_potrf(int n, const double* W, int64_t ldw, double* R, int64_t ldr, int stage,
-                        int* info, double* scratch, hipStream_t st, double shift = 0.0);
+                        int* info, double* scratch, hipStream_t st, double shift = 0.0,
+                        const int* gate = nullptr);
 // C = A B for upper-triangular n x n matrices
 hipError_t launch_trmm_upper(int n, const double* A, int64_t lda, const double* B, int64_t ldb,
-                             double* C, int64_t ldc, hipStream_t st);
+                             double* C, int64_t ldc, hipStream_t st, const int* gate = nullptr);
 // If *info != 0, fill Q (m x n) and R (n x n, optional) with NaN
 hipError_t launch_poison(const int* info, int64_t m, int n, double* Q, int64_t ldq, double* R,
                          int64_t ldr, hipStream_t st);
 hipError_t launch_sketch_rows(int64_t m, int n, const double* A, int64_t lda, int s,
                               uint64_t seed, double* B, int64_t ldb, hipStream_t st);
 hipError_t launch_add_diag(int n, double* W, int64_t ldw, double coef, const double* scale,
-                           hipStream_t st);
+                           hipStream_t st, const int* gate = nullptr);
 hipError_t launch_gemv_t(int64_t m, int n, const double* X, int64_t ldx, const double* b,
                          double* part, double* c, hipStream_t st);
 size_t gemv_part_doubles(int64_t m, int n);
@@ -88,7 +93,37 @@ hipError_t launch_trmm_or_copy(const int* flag, int n, const double* A, int64_t 
 // *need = breakdown in lp_info/info or ||W - I||_F > thresh (one workgroup)
 hipError_t launch_pass_decide(int n, const double* W, int64_t ldw, const int* lp_info,
                               const int* info, double thresh, int* need, double* dev_out,
-                              hipStream_t st);
+                              hipStream_t st, const int* gate = nullptr);
+
+// ---- decisions of the mixed-precision chain, taken on the device --------------------------
+// Control words of one mixed-precision factorization (in its workspace).  gate[k] = 1 when
+// FP64 pass k runs; every kernel of pass k is gated by it, so the automatic mode enqueues
+// its largest number of passes and the unneeded ones return at once.
+constexpr int kMaxMixedPasses = 3;
+struct MixedCtl {
+  int stage;                     // the low-precision A R0^{-1} / Gram / Cholesky stage runs
+  int lp_info;                   // its Cholesky breakdown (-1 when the stage did not run)
+  int gate[kMaxMixedPasses + 1];  // pass k runs
+  int skip[kMaxMixedPasses];     // 1 - gate[k]: the R product of pass k is a copy
+  int bd[kMaxMixedPasses];       // pass k's unshifted Cholesky broke down
+  int shifted[kMaxMixedPasses];  // pass k retries with the shifted Cholesky
+  int need[kMaxMixedPasses + 2]; // scratch of the deviation kernel
+  int one;                       // constant 1
+  int passes;                    // passes run
+  double dev[kMaxMixedPasses][2];  // ||W - I||_F and ||W||_F of pass k's Gram matrix
+  double norms[4];               // ||R0||_F at [1], ||R0^{-1}||_F at [3]
+};
+enum MixedOp {
+  kCtlInit,       // fixed passes (arg): gates of the fixed schedule; 0: automatic
+  kCtlStage,      // stage = ||R0||_F ||R0^{-1}||_F u_p <= 1 (u_p = arg2)
+  kCtlPassBegin,  // pass k: bd[k] = 0, skip[k] = !gate[k]
+  kCtlShift,      // pass k: shifted[k] = gate[k] && bd[k]
+  kCtlNext,       // pass k: gate[k+1] = gate[k] && (shifted[k] || dev[k][0] > arg2), k+1 < max
+  kCtlEnd         // passes = sum of gates; *info = 5000 when the last allowed pass needed
+                  // the shifted retry (the pass budget ran out); d_report = {passes, stage}
+};
+hipError_t launch_mixed_ctl(int op, int k, int arg, double arg2, MixedCtl* c, int* info,
+                            int* d_passes, hipStream_t st);
 
 // ---- low-precision phases (precision codes TSQR_LOWP_FP32 / TSQR_LOWP_BF16) -------------
 size_t lowp_elem_bytes(int prec);
@@ -96,11 +131,12 @@ size_t rinv_lowp_bytes(int prec, int n);
 hipError_t launch_sketch_lowp(int prec, const SketchPlan& p, int64_t m, int n, const double* A,
                               int64_t lda, uint64_t seed, double* part, hipStream_t st);
 hipError_t launch_rinv_prep(int prec, int n, const double* Rinv, int64_t ldr, void* out,
-                            hipStream_t st);
+                            hipStream_t st, const int* gate = nullptr);
 hipError_t launch_apply_rinv_lowp(int prec, int64_t m, int n, const double* Y, int64_t ldy,
-                                  const void* Ri, void* X, int64_t ldx, hipStream_t st);
+                                  const void* Ri, void* X, int64_t ldx, hipStream_t st,
+                                  const int* gate = nullptr);
 hipError_t launch_gram_lowp(int prec, const GramPlan& p, int64_t m, int n, const void* X,
-                            int64_t ldx, double* part, hipStream_t st);
+                            int64_t ldx, double* part, hipStream_t st, const int* gate = nullptr);
 
 // ---- batched factorizations -------------------------------------------------------------
 // One problem of a batch as the batched kernels see it (device copy in the workspace).
