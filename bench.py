@@ -394,6 +394,25 @@ def batched_comparison(args):
     for i in range(len(descs)):
         worst = max(worst, gpu_metrics(As[i], b.Q[i], b.R[i])[0])
 
+    # the batch as one persistent launch (plus the kernel that clears its counters), with
+    # its own autotuned blocking, eager and captured into a graph
+    bp = tsqr.Batch(As, ss, seeds)
+    tuning_p, _ = bp.autotune(persistent=True)
+    ms_p = timed(lambda: bp.run(persistent=True), args.batch_steps, 2)
+    info_p = bool(torch.all(bp.info == 0).item())
+    worst_p = max(gpu_metrics(As[i], bp.Q[i], bp.R[i])[0] for i in range(len(descs)))
+    gp = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(st):
+        bp.run(stream=st, persistent=True)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(gp, stream=st):
+        bp.run(stream=st, persistent=True)
+    ms_pg = timed(gp.replay, args.batch_steps, 2)
+    del gp
+    print(f"# batched persistent: {ms_p:.3f} ms eager, {ms_pg:.3f} ms in a graph "
+          f"({len(descs) / ms_pg * 1e3:.0f} problems/s), {bp.tasks} tasks",
+          file=sys.stderr, flush=True)
+
     # baseline: one explicit-workspace call per problem, workspaces and outputs preallocated
     Qs = [tsqr.colmajor(A.shape[0], A.shape[1]) for A in As]
     Rs = [tsqr.colmajor(A.shape[1], A.shape[1]) for A in As]
@@ -436,6 +455,13 @@ def batched_comparison(args):
             "loop_problems_per_s": round(len(descs) / ms_loop * 1e3, 1),
             "loop_ms_per_batch": round(ms_loop, 4), "speedup_vs_loop": round(ms_loop / ms, 3),
             "launches_per_run": b.launches, "tuning": tuning.as_dict(),
+            "persistent": {"ms_per_batch": round(ms_p, 4),
+                           "ms_per_batch_graph": round(ms_pg, 4),
+                           "problems_per_s": round(len(descs) / ms_pg * 1e3, 1),
+                           "launches_per_run": 2, "tasks": bp.tasks,
+                           "tuning": tuning_p.as_dict(),
+                           "speedup_vs_phase_graph": round(ms / ms_pg, 3),
+                           "all_info_zero": info_p, "worst_ortho": worst_p},
             "autotune_ms": round(tuned_ms, 4), "graph": True, "all_info_zero": info_ok,
             "worst_ortho": worst,
             "fp32": {"problems_per_s": round(len(descs) / ms32 * 1e3, 1),

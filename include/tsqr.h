@@ -304,12 +304,42 @@ int tsqr_batched_autotune(int variant, int precision, int64_t count,
                           const tsqr_problem* problems, void* work, size_t work_bytes, int* d_info,
                           void* stream, tsqr_batch_tuning* best, double* best_ms);
 
+/* The same search timing the persistent launch (tsqr_batched_run_persistent), over coarser
+ * candidates (2048 to 16384 rows, 64 to 512 tiles): its tasks pay a publish and, for the
+ * solves, an operand staging each. */
+int tsqr_batched_autotune_persistent(int variant, int precision, int64_t count,
+                                     const tsqr_problem* problems, void* work, size_t work_bytes,
+                                     int* d_info, void* stream, tsqr_batch_tuning* best,
+                                     double* best_ms);
+
 /* Enqueue the whole batch on `stream`.  Kernel launches only (no allocation, copy or host
  * synchronisation), so a stream capture of this call records the batch as one graph. */
 int tsqr_batched_run(tsqr_batch* plan, void* stream);
 
-/* Number of kernel launches one run enqueues (one per phase and width class). */
+/* The same batch as ONE persistent kernel (preceded by one small kernel that clears its
+ * counters): one workgroup per compute unit takes tasks from a queue in the plan's order
+ * (every sketch task, then the solves by R0, the first Gram matrices, the solves by R1,
+ * the second Gram matrices, the solves by R2); per-problem dependency counters in the
+ * workspace let a task start as soon as its own problem's previous step is complete, and
+ * the workgroup that completes a problem's last split-K task finishes that step (the
+ * fixed-order reduction, the small factorization, the R product).  Results agree with
+ * tsqr_batched_run to rounding (different reduction order) and are reproducible run to
+ * run.  Kernel launches only, so it may be captured into a graph.  If the scheduler's
+ * bounded wait ever gave up, every problem's info is 9000. */
+int tsqr_batched_run_persistent(tsqr_batch* plan, void* stream);
+
+/* The same, with the scheduler's time accounted (measurement): d_stats is NULL or 18
+ * device counters (unsigned 64-bit, caller-zeroed, accumulated) of wall-clock ticks at
+ * 100 MHz summed over the workgroups, per task kind k (0 sketch, 1-3 the solves by R0,
+ * R1, R2, 4-5 the Gram matrices 1, 2): [3k] waiting for the problem's previous step,
+ * [3k+1] the task itself, [3k+2] the finishing step (and publishing) after it. */
+int tsqr_batched_run_persistent_timed(tsqr_batch* plan, unsigned long long* d_stats,
+                                      void* stream);
+
+/* Number of kernel launches one run of tsqr_batched_run enqueues (one per phase and width
+ * class), and number of tasks of the persistent schedule. */
 int tsqr_batched_launches(const tsqr_batch* plan);
+int tsqr_batched_tasks(const tsqr_batch* plan);
 
 void tsqr_batched_destroy(tsqr_batch* plan);
 

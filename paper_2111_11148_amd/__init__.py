@@ -75,8 +75,13 @@ _SIGS = {
                                    ctypes.POINTER(_vp)]),
     "tsqr_batched_autotune": (_int, [_int, _int, _i64, _vp, _vp, _sz, _vp, _vp, _vp,
                                      ctypes.POINTER(ctypes.c_double)]),
+    "tsqr_batched_autotune_persistent": (_int, [_int, _int, _i64, _vp, _vp, _sz, _vp, _vp, _vp,
+                                     ctypes.POINTER(ctypes.c_double)]),
     "tsqr_batched_run": (_int, [_vp, _vp]),
+    "tsqr_batched_run_persistent": (_int, [_vp, _vp]),
+    "tsqr_batched_run_persistent_timed": (_int, [_vp, _vp, _vp]),
     "tsqr_batched_launches": (_int, [_vp]),
+    "tsqr_batched_tasks": (_int, [_vp]),
     "tsqr_batched_destroy": (None, [_vp]),
     "tsqr_metrics_workspace_bytes": (_sz, [_i64, _i64]),
     "tsqr_metrics": (_int, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _sz, _vp]),
@@ -664,15 +669,16 @@ class Batch:
         self._plan = plan
         self.count = count
 
-    def autotune(self, stream=None):
-        """Measure candidate blockings on this batch; returns (BatchTuning, ms per run).
-        Re-plans this batch with the winner."""
+    def autotune(self, stream=None, persistent: bool = False):
+        """Measure candidate blockings on this batch, for the phase-by-phase schedule or the
+        persistent launch; returns (BatchTuning, ms per run).  Re-plans this batch with the
+        winner."""
         best, ms = BatchTuning(), ctypes.c_double(0.0)
-        _check(load().tsqr_batched_autotune(self._variant, self._precision, self.count,
-                                            ctypes.cast(self._probs, _vp), self.work.data_ptr(),
-                                            self._nbytes, self.info.data_ptr(), _stream(stream),
-                                            ctypes.byref(best), ctypes.byref(ms)),
-               "tsqr_batched_autotune")
+        name = "tsqr_batched_autotune_persistent" if persistent else "tsqr_batched_autotune"
+        _check(getattr(load(), name)(self._variant, self._precision, self.count,
+                                     ctypes.cast(self._probs, _vp), self.work.data_ptr(),
+                                     self._nbytes, self.info.data_ptr(), _stream(stream),
+                                     ctypes.byref(best), ctypes.byref(ms)), name)
         plan = _vp()
         _check(load().tsqr_batched_create(self._variant, self._precision, self.count,
                                           ctypes.cast(self._probs, _vp), self.work.data_ptr(),
@@ -682,12 +688,32 @@ class Batch:
         self._plan = plan
         return best, ms.value
 
-    def run(self, stream=None):
-        _check(load().tsqr_batched_run(self._plan, _stream(stream)), "tsqr_batched_run")
+    def run(self, stream=None, persistent: bool = False):
+        """Enqueue the batch: one launch per phase and width class, or (persistent=True)
+        one persistent kernel after a counter-clearing kernel."""
+        if persistent:
+            _check(load().tsqr_batched_run_persistent(self._plan, _stream(stream)),
+                   "tsqr_batched_run_persistent")
+        else:
+            _check(load().tsqr_batched_run(self._plan, _stream(stream)), "tsqr_batched_run")
+
+    def run_persistent_timed(self, stats: torch.Tensor, stream=None):
+        """The persistent run with its scheduler time accumulated into `stats` (18 int64:
+        per task kind, ticks of 10 ns waiting, in the task, and finishing the step)."""
+        if stats.dtype != torch.int64 or stats.numel() < 18 or not stats.is_contiguous():
+            raise ValueError("stats must be a contiguous int64 tensor of 18 entries")
+        _check(load().tsqr_batched_run_persistent_timed(self._plan, stats.data_ptr(),
+                                                        _stream(stream)),
+               "tsqr_batched_run_persistent_timed")
 
     @property
     def launches(self) -> int:
         return int(load().tsqr_batched_launches(self._plan))
+
+    @property
+    def tasks(self) -> int:
+        """Tasks of the persistent schedule."""
+        return int(load().tsqr_batched_tasks(self._plan))
 
     def __del__(self):
         plan = getattr(self, "_plan", None)

@@ -1,7 +1,8 @@
 """Build ``paper_2111_11148_amd/libtsqr.so`` from the HIP sources in ``csrc/`` for gfx950.
 
-Each ``.hip`` file is compiled to an object in ``_build/`` (in parallel), then linked into
-one shared library exporting the C ABI of ``include/tsqr.h``.
+Each translation unit (every ``.hip`` file except the parts that ``k_chain.hip`` includes)
+is compiled to an object in ``_build/`` (in parallel), then linked into one shared library
+exporting the C ABI of ``include/tsqr.h``.
 """
 from __future__ import annotations
 
@@ -36,8 +37,14 @@ def _compile(src: str, obj: str, verbose: bool) -> None:
         print(err, flush=True)
 
 
+# Sources compiled only as part of k_chain.hip (one translation unit, so that the persistent
+# batched kernel can inline the device bodies of every phase).
+CHAIN_PARTS = {"k_sketch.hip", "k_tall.hip", "k_small.hip", "k_lowp.hip", "k_persist.hip"}
+
+
 def build(verbose: bool = False) -> str:
-    srcs = sorted(glob.glob(os.path.join(_HERE, "csrc", "*.hip")))
+    srcs = sorted(s for s in glob.glob(os.path.join(_HERE, "csrc", "*.hip"))
+                  if os.path.basename(s) not in CHAIN_PARTS)
     bdir = os.path.join(_ROOT, "_build", "tsqr")
     os.makedirs(bdir, exist_ok=True)
     objs = [os.path.join(bdir, os.path.basename(s)[:-4] + ".o") for s in srcs]

@@ -56,18 +56,32 @@ __device__ __forceinline__ int lowp_to_f64_tile_index(int lane, int r) {
 // ===================================================================== sketch ====
 // One workgroup: a row block of A, i-tiles it0.. of B for each wavefront, JT column tiles.
 // A is staged in LDS column-major (rows contiguous) already rounded to the input type.
-// Body of workgroup (row block bx, i-group by, column group bz).
-template <int PREC, int IT, int JT, int NW>
+// Body of workgroup (row block bx, i-group by, column group bz).  EXTL: the staging buffer
+// lives at ext_lds (sketch_lowp_lds_bytes<PREC, JT>() bytes, 16-byte aligned) instead of in
+// the body's own LDS.
+template <int PREC, int JT>
+__host__ __device__ constexpr int sketch_lowp_lds_bytes() {
+  return JT * 16 * ((PREC == TSQR_LOWP_FP32) ? 65 : 72) * ((PREC == TSQR_LOWP_FP32) ? 4 : 2);
+}
+
+template <int PREC, int IT, int JT, int NW, bool EXTL = false>
 __device__ __forceinline__ void sketch_lowp_body(
     int64_t m, int n, const double* __restrict__ A, int64_t lda, uint32_t k0, uint32_t k1,
     int64_t rows_per_block, int it_total, int jt_total, double* __restrict__ part, int bx,
-    int by, int bz) {
+    int by, int bz, double* ext_lds = nullptr) {
   typedef typename LowT<PREC>::E E;
   constexpr int KC = 64;                       // rows per chunk
   constexpr int NC = JT * 16;
   constexpr int LDR = (PREC == TSQR_LOWP_FP32) ? KC + 1 : KC + 8;
   constexpr int T = NW * 64;
-  __shared__ __attribute__((aligned(16))) E lds[NC * LDR];
+  static_assert(NC * LDR * (int)sizeof(E) == sketch_lowp_lds_bytes<PREC, JT>(), "LDS size");
+  E* lds;
+  if constexpr (EXTL) {
+    lds = reinterpret_cast<E*>(ext_lds);
+  } else {
+    __shared__ __attribute__((aligned(16))) E own[NC * LDR];
+    lds = own;
+  }
 
   const int lane = lane_id(), wave = wave_id();
   const int q = lane >> 4, c16 = lane & 15;
@@ -96,6 +110,8 @@ __device__ __forceinline__ void sketch_lowp_body(
       lds[cc * LDR + rr] = LowT<PREC>::from_double(v);
     }
     __syncthreads();
+    // a wave whose row tiles all lie past the sketch's s rows only helps to stage the chunks
+    if (it0 >= it_total) continue;
     if (PREC == TSQR_LOWP_FP32) {
 #pragma unroll
       for (int g = 0; g < KC / 16; ++g) {

@@ -15,20 +15,35 @@
 namespace tsqr {
 
 // Body of one workgroup: row block bx, i-tile group by, column group bz (the kernel's
-// blockIdx; the batched kernel supplies them from its work list).
-template <int IT, int JT, int NW>
+// blockIdx; the batched kernels supply them from their work lists).  EXTL: the LDS chunk
+// buffers live at ext_lds (sketch_f64_lds_doubles<JT>() doubles, provided by a kernel that
+// hosts several bodies) instead of in the body's own LDS.
+template <int JT>
+__host__ __device__ constexpr int sketch_f64_lds_doubles() {
+  return 2 * 32 * (JT * 16 + 1);
+}
+
+template <int IT, int JT, int NW, bool EXTL = false>
 __device__ __forceinline__ void sketch_f64_body(int64_t m, int n, const double* __restrict__ A,
                                                 int64_t lda, uint32_t k0, uint32_t k1,
                                                 int64_t rows_per_block, int it_total,
                                                 int jt_total, double* __restrict__ part, int bx,
-                                                int by, int bz) {
+                                                int by, int bz, double* ext_lds = nullptr) {
   constexpr int KC = 32;          // rows of A per LDS chunk
   constexpr int NC = JT * 16;     // columns of A per workgroup
   constexpr int LDN = NC + 1;     // padded row length of the LDS chunk (doubles)
   constexpr int T = NW * 64;      // threads
   constexpr int CPP = T / (KC / 2);                 // columns loaded per pass
   constexpr int PASSES = (NC + CPP - 1) / CPP;
-  __shared__ double ldsb[2][KC * LDN];  // double buffer: one barrier per chunk
+  // double buffer: one barrier per chunk
+  double* lbase;
+  if constexpr (EXTL) {
+    lbase = ext_lds;
+  } else {
+    __shared__ double own[2 * KC * LDN];
+    lbase = own;
+  }
+  double(*ldsb)[KC * LDN] = reinterpret_cast<double(*)[KC * LDN]>(lbase);
 
   const int lane = lane_id(), wave = wave_id();
   const int q = lane >> 4, c16 = lane & 15;
@@ -76,12 +91,15 @@ __device__ __forceinline__ void sketch_f64_body(int64_t m, int n, const double* 
   }
   __syncthreads();
   int cur = 0;
+  // a wave whose row tiles all lie past the sketch's s rows (a workgroup wider than B)
+  // only helps to stage the chunks
+  const bool active = it0 < it_total;
   for (int64_t rb = r0; rb < r1; rb += KC, cur ^= 1) {
     const double* lds = ldsb[cur];
 #pragma unroll
     for (int g = 0; g < KC / 16; ++g) {
       const int64_t jbase = rb + 16 * g;
-      if (jbase >= r1) break;
+      if (jbase >= r1 || !active) break;
       float z[IT][4];
 #pragma unroll
       for (int it = 0; it < IT; ++it) {

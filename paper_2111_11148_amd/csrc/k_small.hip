@@ -77,15 +77,31 @@ __device__ __forceinline__ int block_first_bad(int n, F d) {
   return best == 0x7fffffff ? 0 : best + 1;
 }
 
-// ================================================================ Householder QR ====
+// LDS of the register-resident factorizations of the sketch (QR and LU): two column
+// buffers of 64 RPL doubles and one diagonal of 16 CPW.  EXTL bodies take it at ext_lds
+// (reg_factor_lds_doubles<RPL, CPW>() doubles) instead of in their own LDS.
 template <int RPL, int CPW>
+__host__ __device__ constexpr int reg_factor_lds_doubles() {
+  return 2 * 64 * RPL + 16 * CPW;
+}
+
+// ================================================================ Householder QR ====
+template <int RPL, int CPW, bool EXTL = false>
 __device__ __forceinline__ void geqrf_reg_body(int s, int n,
                                                              const double* __restrict__ B,
                                                              int64_t ldb, double* __restrict__ R,
-                                                             int64_t ldr, int* __restrict__ info) {
-  __shared__ double vbuf[2][64 * RPL];
+                                                             int64_t ldr, int* __restrict__ info,
+                                                             double* ext_lds = nullptr) {
+  double* lbase;
+  if constexpr (EXTL) {
+    lbase = ext_lds;
+  } else {
+    __shared__ double own[reg_factor_lds_doubles<RPL, CPW>()];
+    lbase = own;
+  }
+  double(*vbuf)[64 * RPL] = reinterpret_cast<double(*)[64 * RPL]>(lbase);
+  double* betas = lbase + 2 * 64 * RPL;
   __shared__ double tau_sh[2];
-  __shared__ double betas[16 * CPW];
   const int lane = lane_id(), wave = wave_id();
   double col[CPW][RPL];
 #pragma unroll
@@ -567,14 +583,22 @@ __device__ __forceinline__ void wave_argmax(double& v, int& idx) {
   idx = bi;
 }
 
-template <int RPL, int CPW>
+template <int RPL, int CPW, bool EXTL = false>
 __device__ __forceinline__ void getrf_reg_body(int s, int n,
                                                              const double* __restrict__ B,
                                                              int64_t ldb, double* __restrict__ R,
-                                                             int64_t ldr, int* __restrict__ info) {
-  __shared__ double lbuf[2][64 * RPL];
+                                                             int64_t ldr, int* __restrict__ info,
+                                                             double* ext_lds = nullptr) {
+  double* lbase;
+  if constexpr (EXTL) {
+    lbase = ext_lds;
+  } else {
+    __shared__ double own[reg_factor_lds_doubles<RPL, CPW>()];
+    lbase = own;
+  }
+  double(*lbuf)[64 * RPL] = reinterpret_cast<double(*)[64 * RPL]>(lbase);
+  double* ukk = lbase + 2 * 64 * RPL;
   __shared__ int piv_sh[2];
-  __shared__ double ukk[16 * CPW];
   const int lane = lane_id(), wave = wave_id();
   double col[CPW][RPL];
 #pragma unroll

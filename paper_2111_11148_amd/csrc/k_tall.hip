@@ -155,7 +155,7 @@ __device__ __forceinline__ void trsm_mfma_body(int64_t m, int n, const double* _
     const bool rok = row < m;
     g_f64* yb = (g_f64*)(Y + (rok ? row : 0) + (int64_t)(4 * q) * ldy);
     int lim = n - 4 * q;  // column 16b + 4q + r exists iff 16b + r < lim
-    int64_t cstep = ldy;
+    int64_t cstep = uniform_i64(ldy);
     asm volatile("" : "+v"(yb), "+v"(lim), "+s"(cstep));
     const int64_t back = -(int64_t)(4 * q) * cstep;  // from column 4q back to column 0
 #pragma unroll
@@ -175,7 +175,7 @@ __device__ __forceinline__ void trsm_mfma_body(int64_t m, int n, const double* _
     // opaque per-iteration bases: the tiles are loop invariant and would otherwise be
     // hoisted into registers
     lds_f64* tlp = (lds_f64*)tl;
-    const double* Pg = P;
+    const double* Pg = uniform_ptr(P);
     asm volatile("" : "+v"(tlp), "+s"(Pg));
     auto Aop = [&](int t, int kk) -> double {
       const int o = t * 256 + (4 * q + kk) * 16 + c16;
@@ -214,7 +214,7 @@ __device__ __forceinline__ void trsm_mfma_body(int64_t m, int n, const double* _
     if (rok) {
       // opaque base and uniform column offsets (per-lane column products would be hoisted)
       double* xb = X + row + (int64_t)(4 * q) * ldx;
-      int64_t xs = ldx;
+      int64_t xs = uniform_i64(ldx);
       asm volatile("" : "+v"(xb), "+s"(xs));
 #pragma unroll
       for (int b = 0; b < JT; ++b)
@@ -495,11 +495,18 @@ __device__ __forceinline__ void gram_chunk(const lds_f64* lds, int q, int c16, v
 // VEC: X is 16-byte aligned, ldx and m are even, so every in-range row pair is one
 // aligned 16-byte load (chosen on the host; the loads stay branch-free either way, so the
 // prefetch is never waited for before the MFMA work that should hide it).
-// Body of workgroup (row block bx, tile share by).
-template <int JT, int NW, int NS, bool VEC>
+// Body of workgroup (row block bx, tile share by).  EXTL: the chunk buffers live at
+// ext_lds (gram_f64_lds_doubles<JT>() doubles) instead of in the body's own LDS.
+template <int JT>
+__host__ __device__ constexpr int gram_f64_lds_doubles() {
+  return 2 * 32 * (JT * 16 + 1);
+}
+
+template <int JT, int NW, int NS, bool VEC, bool EXTL = false>
 __device__ __forceinline__ void gram_f64_body(int64_t m, int n, const double* __restrict__ X,
                                               int64_t ldx, int64_t rows_per_block, int ntiles,
-                                              double* __restrict__ part, int bx, int by) {
+                                              double* __restrict__ part, int bx, int by,
+                                              double* ext_lds = nullptr) {
   constexpr int KC = 32;
   constexpr int NC = JT * 16;
   constexpr int LDN = NC + 1;
@@ -510,7 +517,15 @@ __device__ __forceinline__ void gram_f64_body(int64_t m, int n, const double* __
   constexpr int CPP = THREADS / (KC / 2);  // columns loaded per pass
   constexpr int PASSES = (NC + CPP - 1) / CPP;
   static_assert(STRIDE <= 16, "slot dispatch covers at most 16 slots");
-  __shared__ double lds[2][KC * LDN];  // double buffer: one barrier per chunk
+  // double buffer: one barrier per chunk
+  double* lbase;
+  if constexpr (EXTL) {
+    lbase = ext_lds;
+  } else {
+    __shared__ double own[2 * KC * LDN];
+    lbase = own;
+  }
+  double(*lds)[KC * LDN] = reinterpret_cast<double(*)[KC * LDN]>(lbase);
 
   const int lane = lane_id(), wave = wave_id();
   const int q = lane >> 4, c16 = lane & 15;

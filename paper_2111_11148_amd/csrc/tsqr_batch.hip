@@ -64,6 +64,11 @@ struct tsqr_batch {
   tsqr::BProb* probs_dev = nullptr;
   tsqr::BItem* items_dev = nullptr;
   std::vector<tsqr::Launch> launches;
+  // the persistent schedule: task queue, queue head and abort flag, dynamic LDS
+  int4* ptasks_dev = nullptr;
+  int nptasks = 0;
+  int* pctl_dev = nullptr;
+  size_t plds = 0;
 };
 
 namespace tsqr {
@@ -121,9 +126,18 @@ int validate(int64_t count, const tsqr_problem* pr) {
   return 0;
 }
 
-size_t header_bytes(int64_t count, size_t nitems) {
-  return align256b((size_t)count * sizeof(BProb)) + align256b(nitems * sizeof(BItem));
+// Header of the workspace: problem descriptors, the per-phase work items, the persistent
+// task queue, its head and abort flag, and each problem's dependency counters.
+constexpr int kCntStride = 16;  // ints per problem (kPsSlots used)
+static_assert(kPsSlots <= kCntStride, "counter slots");
+
+size_t header_bytes(int64_t count, size_t nitems, size_t ntasks) {
+  return align256b((size_t)count * sizeof(BProb)) + align256b(nitems * sizeof(BItem)) +
+         align256b(ntasks * sizeof(int4)) + 256 + align256b((size_t)count * kCntStride * 4);
 }
+
+// Sketch i-groups of the persistent schedule (16 wavefronts of one 16-row tile each).
+int persist_igroups(int s) { return ((s + 15) / 16 + 15) / 16; }
 
 }  // namespace
 }  // namespace tsqr
@@ -136,7 +150,7 @@ size_t tsqr_batched_workspace_bytes(int64_t count, const tsqr_problem* problems)
   if (validate(count, problems) != 0) return 0;
   // sized for the smallest blockings, so that every tuning fits
   const tsqr_batch_tuning t{kMinRows, kMinRows, kMinTiles};
-  size_t items = 0, bufs = 0;
+  size_t items = 0, tasks = 0, bufs = 0;
   for (int64_t i = 0; i < count; ++i) {
     const tsqr_problem& q = problems[i];
     const int n = (int)q.n, s = (int)q.s;
@@ -155,9 +169,11 @@ size_t tsqr_batched_workspace_bytes(int64_t count, const tsqr_problem* problems)
     const size_t e_sk = (size_t)it_total * jt_total * 256, e_gr = (size_t)(jt_total * (jt_total + 1) / 2) * 256;
     items += 1 + (size_t)sk_k * ig * jg + (e_sk + 15) / 16 + 1 + 3 * jt + 3 * twg +
              2 * ((size_t)gr_k + (e_gr + 15) / 16) + 2 + 2 * (size_t)jt_total * jt_total + 4;
+    tasks += (size_t)sk_k * persist_igroups(s) * ((jt_total + 3) / 4) + 3 * (size_t)twg +
+             2 * (size_t)gr_k;
     bufs += align256b(problem_doubles(q.m, n, s, t) * 8);
   }
-  return header_bytes(count, items) + bufs;
+  return header_bytes(count, items, tasks) + bufs;
 }
 
 int tsqr_batched_create(int variant, int precision, int64_t count, const tsqr_problem* problems,
@@ -227,6 +243,15 @@ int tsqr_batched_create(int variant, int precision, int64_t count, const tsqr_pr
     const int64_t ntiles = (q.m + 15) / 16;
     p.trsm_wgs = (int)std::min<int64_t>(256, (ntiles + t.trsm_tiles - 1) / t.trsm_tiles);
     p.poison_wgs = 4;
+    p.jt = k.jt;
+    p.qr_rpl = k.qr_rpl;
+    p.qr_cpw = k.qr_cpw;
+    p.po_rpl = k.po_rpl;
+    p.po_cpw = k.po_cpw;
+    p.p_igroups = persist_igroups(s);
+    p.p_jgroups = precision == TSQR_BATCH_FP64 ? 1 : (jt_total + 3) / 4;
+    p.p_nsk = p.sk_kblocks * p.p_igroups * p.p_jgroups;
+    p.p_ntrsm = p.trsm_wgs;
     buf_off[(size_t)i] = bufs;
     bufs += align256b(problem_doubles(q.m, n, s, t) * 8);
 
@@ -273,14 +298,50 @@ int tsqr_batched_create(int variant, int precision, int64_t count, const tsqr_pr
     for (int w = 0; w < p.poison_wgs; ++w) add(kPoison, w, 0, 0);
   }
 
-  // workspace: [descriptors | work items | per-problem buffers]
+  // the persistent queue: phase by phase, and within a phase the problems with the most
+  // work first (their tasks are the longest), each problem's tasks together
+  std::vector<int> order((size_t)count);
+  for (int64_t i = 0; i < count; ++i) order[(size_t)i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const BProb& pa = probs[(size_t)a];
+    const BProb& pb = probs[(size_t)b];
+    return (double)pa.m * pa.n * (2.0 * pa.s + 5.0 * pa.n) >
+           (double)pb.m * pb.n * (2.0 * pb.s + 5.0 * pb.n);
+  });
+  std::vector<int4> ptasks;
+  for (int kind = 0; kind < 6; ++kind) {
+    // queue order of the kinds: sketch, solve by R0, Gram 1, solve by R1, Gram 2, solve by R2
+    const int k = kind == 0 ? 0 : kind == 1 ? 1 : kind == 2 ? 4 : kind == 3 ? 2 : kind == 4 ? 5 : 3;
+    for (int pid : order) {
+      const BProb& p = probs[(size_t)pid];
+      if (k == 0) {
+        for (int bx = 0; bx < p.sk_kblocks; ++bx)
+          for (int y = 0; y < p.p_igroups * p.p_jgroups; ++y)
+            ptasks.push_back(int4{0, pid, bx, y});
+      } else if (k <= 3) {
+        for (int w = 0; w < p.p_ntrsm; ++w) ptasks.push_back(int4{k, pid, w, 0});
+      } else {
+        for (int bx = 0; bx < p.gr_kblocks; ++bx) ptasks.push_back(int4{k, pid, bx, 0});
+      }
+    }
+  }
+
+  // workspace: [descriptors | work items | persistent tasks | head, abort | counters |
+  //             per-problem buffers]
   char* base = (char*)work;
   const size_t probs_bytes = align256b((size_t)count * sizeof(BProb));
   const size_t items_bytes = align256b(nitems * sizeof(BItem));
-  char* bufbase = base + probs_bytes + items_bytes;
-  if (probs_bytes + items_bytes + bufs > work_bytes) return TSQR_ERR_WORKSPACE;
+  const size_t tasks_bytes = align256b(ptasks.size() * sizeof(int4));
+  const size_t cnt_bytes = align256b((size_t)count * kCntStride * 4);
+  char* tasks_base = base + probs_bytes + items_bytes;
+  int* ctl_base = (int*)(tasks_base + tasks_bytes);
+  int* cnt_base = ctl_base + 64;
+  char* bufbase = (char*)cnt_base + cnt_bytes;
+  if (probs_bytes + items_bytes + tasks_bytes + 256 + cnt_bytes + bufs > work_bytes)
+    return TSQR_ERR_WORKSPACE;
   for (int64_t i = 0; i < count; ++i) {
     BProb& p = probs[(size_t)i];
+    p.cnt = cnt_base + (size_t)i * kCntStride;
     const int n = p.n, s = p.s;
     const size_t nn = (size_t)n * n;
     char* c = bufbase + buf_off[(size_t)i];
@@ -308,6 +369,14 @@ int tsqr_batched_create(int variant, int precision, int64_t count, const tsqr_pr
   plan->count = count;
   plan->probs_dev = (BProb*)base;
   plan->items_dev = (BItem*)(base + probs_bytes);
+  plan->ptasks_dev = (int4*)tasks_base;
+  plan->nptasks = (int)ptasks.size();
+  plan->pctl_dev = ctl_base;
+  {
+    int max_jt = 1;
+    for (const BProb& p : probs) max_jt = std::max(max_jt, p.jt);
+    plan->plds = persistent_lds_bytes(max_jt, 0, precision);
+  }
   std::vector<BItem> all;
   all.reserve(nitems);
   for (int ph = 0; ph < kNumPhases; ++ph)
@@ -318,7 +387,9 @@ int tsqr_batched_create(int variant, int precision, int64_t count, const tsqr_pr
   if (hipMemcpy(plan->probs_dev, probs.data(), (size_t)count * sizeof(BProb),
                 hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(plan->items_dev, all.data(), all.size() * sizeof(BItem), hipMemcpyHostToDevice) !=
-          hipSuccess) {
+          hipSuccess ||
+      hipMemcpy(plan->ptasks_dev, ptasks.data(), ptasks.size() * sizeof(int4),
+                hipMemcpyHostToDevice) != hipSuccess) {
     delete plan;
     return TSQR_ERR_HIP;
   }
@@ -366,9 +437,18 @@ int tsqr_batched_run(tsqr_batch* plan, void* stream) {
   return TSQR_OK;
 }
 
-int tsqr_batched_autotune(int variant, int precision, int64_t count,
-                          const tsqr_problem* problems, void* work, size_t work_bytes, int* d_info,
-                          void* stream, tsqr_batch_tuning* best, double* best_ms) {
+}  // extern "C"
+
+namespace tsqr {
+namespace {
+
+// Coordinate search over the sketch blocking, the Gram blocking and the solve grid of a
+// plan, each from four candidates, timing the phase-by-phase schedule or the persistent
+// launch (which prefers coarser tasks: its per-task publish and the solve's operand
+// staging are paid once per task).
+int autotune(bool persistent, int variant, int precision, int64_t count,
+             const tsqr_problem* problems, void* work, size_t work_bytes, int* d_info,
+             void* stream, tsqr_batch_tuning* best, double* best_ms) {
   if (!best) return -9;
   hipStream_t st = (hipStream_t)stream;
   hipEvent_t e0, e1;
@@ -377,15 +457,18 @@ int tsqr_batched_autotune(int variant, int precision, int64_t count,
     (void)hipEventDestroy(e0);  // best effort on the error path
     return TSQR_ERR_HIP;
   }
+  auto run = [&](tsqr_batch* plan) {
+    return persistent ? tsqr_batched_run_persistent(plan, st) : tsqr_batched_run(plan, st);
+  };
   // time of one run of the batch planned with `t` (warm-up run, then the mean of two)
   auto measure = [&](const tsqr_batch_tuning& t, double* ms) -> int {
     tsqr_batch* plan = nullptr;
     int rc = tsqr_batched_create(variant, precision, count, problems, work, work_bytes, d_info, &t,
                                  &plan);
     if (rc) return rc;
-    rc = tsqr_batched_run(plan, st);
+    rc = run(plan);
     if (!rc && hipEventRecord(e0, st) != hipSuccess) rc = TSQR_ERR_HIP;
-    for (int r = 0; r < 2 && !rc; ++r) rc = tsqr_batched_run(plan, st);
+    for (int r = 0; r < 2 && !rc; ++r) rc = run(plan);
     if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = TSQR_ERR_HIP;
     if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = TSQR_ERR_HIP;
     float f = 0.f;
@@ -394,12 +477,15 @@ int tsqr_batched_autotune(int variant, int precision, int64_t count,
     *ms = f / 2.0;
     return rc;
   };
-  // coordinate search: sketch blocking, then Gram blocking, then solve grid
-  tsqr_batch_tuning cur = kDefaultTuning;
+  tsqr_batch_tuning cur = persistent ? tsqr_batch_tuning{4096, 4096, 128} : kDefaultTuning;
   double cur_ms = 0.0;
   int rc = measure(cur, &cur_ms);
-  const int64_t rows[] = {1024, 2048, 4096, 8192};
-  const int tiles[] = {32, 64, 128, 256};
+  const int64_t rows_phase[] = {1024, 2048, 4096, 8192};
+  const int64_t rows_persist[] = {2048, 4096, 8192, 16384};
+  const int tiles_phase[] = {32, 64, 128, 256};
+  const int tiles_persist[] = {64, 128, 256, 512};
+  const int64_t* rows = persistent ? rows_persist : rows_phase;
+  const int* tiles = persistent ? tiles_persist : tiles_phase;
   for (int dim = 0; dim < 3 && !rc; ++dim)
     for (int c = 0; c < 4 && !rc; ++c) {
       tsqr_batch_tuning t = cur;
@@ -423,6 +509,42 @@ int tsqr_batched_autotune(int variant, int precision, int64_t count,
   if (best_ms) *best_ms = cur_ms;
   return TSQR_OK;
 }
+
+}  // namespace
+}  // namespace tsqr
+
+extern "C" {
+
+int tsqr_batched_autotune(int variant, int precision, int64_t count,
+                          const tsqr_problem* problems, void* work, size_t work_bytes, int* d_info,
+                          void* stream, tsqr_batch_tuning* best, double* best_ms) {
+  return autotune(false, variant, precision, count, problems, work, work_bytes, d_info, stream,
+                  best, best_ms);
+}
+
+int tsqr_batched_autotune_persistent(int variant, int precision, int64_t count,
+                                     const tsqr_problem* problems, void* work, size_t work_bytes,
+                                     int* d_info, void* stream, tsqr_batch_tuning* best,
+                                     double* best_ms) {
+  return autotune(true, variant, precision, count, problems, work, work_bytes, d_info, stream,
+                  best, best_ms);
+}
+
+int tsqr_batched_run_persistent(tsqr_batch* plan, void* stream) {
+  return tsqr_batched_run_persistent_timed(plan, nullptr, stream);
+}
+
+int tsqr_batched_run_persistent_timed(tsqr_batch* plan, unsigned long long* d_stats,
+                                      void* stream) {
+  if (!plan) return -1;
+  if (launch_b_persistent(plan->variant, plan->precision, plan->probs_dev, (int)plan->count,
+                          plan->ptasks_dev, plan->nptasks, plan->pctl_dev, plan->plds, d_stats,
+                          (hipStream_t)stream) != hipSuccess)
+    return TSQR_ERR_HIP;
+  return TSQR_OK;
+}
+
+int tsqr_batched_tasks(const tsqr_batch* plan) { return plan ? plan->nptasks : 0; }
 
 int tsqr_batched_launches(const tsqr_batch* plan) {
   return plan ? (int)plan->launches.size() : 0;

@@ -130,6 +130,19 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
+// The same (wave-uniform) value read from the first active lane, so that the compiler
+// keeps it in scalar registers: needed where it feeds an inline-assembly scalar operand in
+// a kernel whose control flow hides that it is uniform.
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  return reinterpret_cast<T*>(uniform_i64(reinterpret_cast<int64_t>(p)));
+}
+
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 // wavefront index inside the workgroup, as a uniform (scalar) value
 __device__ __forceinline__ int wave_id() {

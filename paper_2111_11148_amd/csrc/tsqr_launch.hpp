@@ -165,6 +165,20 @@ struct BProb {
   int trsm_wgs;     // workgroups of each triangular solve
   int poison_wgs;
   int pad;
+  // persistent schedule (one launch for the batch)
+  int jt;                // 16-column tiles, rounded up to a power of two (<= 8)
+  int qr_rpl, qr_cpw;    // register factorization of the sketch (rows, columns per lane)
+  int po_rpl, po_cpw;    // register Cholesky
+  int p_igroups;         // sketch i-groups per row block (groups of 16 row tiles of B)
+  int p_jgroups;         // sketch column groups per row block (low precision: 4 tiles)
+  int p_nsk;             // sketch tasks
+  int p_ntrsm;           // tasks of each solve
+  int* cnt;              // dependency counters, kPsSlots of them
+};
+// Dependency counters of a problem in the persistent schedule: tasks completed per step,
+// and flags raised once a factor and its solve operands are ready.
+enum PersistSlot {
+  kPsSketch, kPsR0, kPsTrsm0, kPsGram1, kPsR1, kPsTrsm1, kPsGram2, kPsR2, kPsTrsm2, kPsSlots
 };
 // One workgroup's share: problem index and block coordinates.
 struct BItem {
@@ -198,6 +212,13 @@ hipError_t launch_b_trmm(int which, const BItem* items, int nitems, const BProb*
                          hipStream_t st);
 hipError_t launch_b_poison(const BItem* items, int nitems, const BProb* probs, hipStream_t st);
 hipError_t launch_b_set_info(const BItem* items, int nitems, const BProb* probs, hipStream_t st);
+// The whole batch in one persistent launch (after a kernel that clears its counters).
+size_t persistent_lds_bytes(int max_jt, int max_rpl_cpw, int precision);
+// stats: null, or 18 device counters of wall-clock ticks per task kind (wait, body,
+// finishing step)
+hipError_t launch_b_persistent(int variant, int precision, const BProb* probs, int nprobs,
+                               const int4* tasks, int ntasks, int* ctl, size_t lds_bytes,
+                               unsigned long long* stats, hipStream_t st);
 
 // ---- accuracy metrics (double-double) and attainable-peak probes -------------------------
 size_t metrics_workspace_bytes(int64_t m, int n);
