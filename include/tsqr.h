@@ -186,12 +186,14 @@ int tsqr_cholqr_ws(int algo, int64_t m, int64_t n, const double* A, int64_t lda,
  * Mixed precision
  * ------------------------------------------------------------------------------------ */
 #define TSQR_LOWP_FP32 1 /* inputs rounded to FP32, FP32 matrix cores, FP32 accumulation */
-#define TSQR_LOWP_BF16 2 /* inputs rounded to BF16 (RNE of the FP32 value), FP32 accumulation */
+#define TSQR_LOWP_BF16 2 /* inputs rounded to BF16 (RNE of the FP32 value), FP32 accumulation;
+                            the sketch's A excepted (see tsqr_sketch_lowp) */
 
 /* Randomized XR-preconditioned CholeskyQR with the data-heavy preconditioning steps in low
  * precision and the orthogonalising passes in FP64 (the paper's framework, Section 2.2,
  * with an inexact preconditioner as analysed in Appendix A):
- *   B = S A in `lowp` (FP32 accumulation over at most 64 rows, FP64 partial sums);
+ *   B = S A on the `lowp` matrix cores (as tsqr_sketch_lowp: FP32 accumulation over at
+ *     most 64 rows, FP64 partial sums);
  *   R0 = R factor of B in FP64 (Householder or LU as `variant`);
  *   R0^{-1} explicitly in FP64 (triangular solve of the identity), rounded to `lowp`;
  *   A1 = A R0^{-1} and W1 = A1^T A1 in `lowp` (W1 summed in FP64);
@@ -224,9 +226,14 @@ int tsqr_rxr_cholqr_mixed_ws(int variant, int lowp, int64_t m, int64_t n, const 
                              size_t work_bytes, int* d_info, int* d_report, void* stream);
 
 /* Low-precision steps of the mixed variant (step-wise validation):
- *   tsqr_sketch_lowp: B = S A (s x n FP64, ldb >= s) with the entries of S and A rounded
- *     to `lowp`, FP32 accumulation over at most 64 rows, FP64 partial sums; workspace
- *     tsqr_sketch_workspace_bytes(m, n, s).
+ *   tsqr_sketch_lowp: B = S A (s x n FP64, ldb >= s) with the entries of S rounded to
+ *     `lowp` and those of A rounded to FP32 (both types), FP32 accumulation over at most
+ *     64 rows, FP64 partial sums; workspace tsqr_sketch_workspace_bytes(m, n, s).  With
+ *     BF16 the FP32 value of each entry of A is split exactly into three BF16 terms, each
+ *     multiplied by the BF16 normal on the BF16 matrix cores (products exact in FP32):
+ *     the sketch then costs three BF16 products per term, far below the normals'
+ *     generation, and keeps A to FP32 accuracy, so it preconditions as well as the FP32
+ *     sketch (a single BF16 rounding of A would leave cond(A R0^{-1}) near cond(A) 2^-8).
  *   tsqr_apply_rinv_lowp: X = r(Y) r(Rinv) for upper-triangular Rinv (n x n FP64, rounded
  *     inside), FP32 accumulation; X (m x n, ldx >= m) holds FP32 or BF16 elements (2-byte
  *     BF16 bit patterns); workspace tsqr_rinv_lowp_bytes(n, lowp).
@@ -253,9 +260,10 @@ int tsqr_gram_lowp(int lowp, int64_t m, int64_t n, const void* X, int64_t ldx, d
  * Limits: 1 <= n <= 128, n <= s <= 512 (s <= 256 when n > 64), m >= n; any other problem
  * makes the create call return -4.
  * Precision: TSQR_BATCH_FP64 runs every step in FP64; TSQR_LOWP_FP32 or TSQR_LOWP_BF16
- * computes the sketch S A from inputs rounded to that type with FP32 accumulation flushed
- * into FP64 every 64 rows (as tsqr_sketch_lowp) and every later step in FP64, the mixed
- * variant with the low precision in the sketch alone. */
+ * computes the sketch S A on that type's matrix cores (normals in that type, A as its
+ * FP32 rounding) with FP32 accumulation flushed into FP64 every 64 rows (as
+ * tsqr_sketch_lowp) and every later step in FP64, the mixed variant with the low
+ * precision in the sketch alone. */
 #define TSQR_BATCH_FP64 0
 typedef struct {
   int64_t m, n;        /* rows and columns of A */

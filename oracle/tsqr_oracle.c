@@ -645,7 +645,8 @@ int or_num_threads(void) {
 /* ------------------------------------------------------------------------------------
  * Mixed precision (a reading of the benchmark's mixed configuration, not in the paper):
  * the sketch, the preconditioner apply A1 = A R0^{-1} and the first Gram matrix take
- * inputs rounded to FP32 or BF16; R0, R0^{-1}, the Cholesky factors, the R products and
+ * inputs rounded to FP32 or BF16 (the sketch: its normals; A enters it as FP32 in both
+ * cases, see or_sketch_apply_lowp); R0, R0^{-1}, the Cholesky factors, the R products and
  * the final CholeskyQR passes are FP64.  Roundings: FP64 -> FP32 round to nearest even;
  * BF16 = round to nearest even of that FP32 value to 8 significant bits.  The low-precision
  * steps here are the exact (FP64-accumulated) sums of the rounded inputs; a device may
@@ -672,8 +673,11 @@ static double or_round_p(int prec, double x) {
     return prec == OR_BF16 ? or_round_bf16(x) : or_round_fp32(x);
 }
 
-/* B = (1/sqrt(s)) * sum_j r(Z(i,j)) r(A(j,c)), r = rounding to the input type; the
- * normal Z is first made an FP32 number (as the sketch defines it). */
+/* B = (1/sqrt(s)) * sum_j r(Z(i,j)) fp32(A(j,c)): the normal Z is first made an FP32
+ * number (as the sketch defines it) and then rounded to the input type r; A enters as its
+ * FP32 rounding for both input types.  (With BF16 inputs that FP32 value is carried as the
+ * exact sum of three BF16 numbers, each product of a BF16 normal with one of them exact,
+ * so the sketch loses no more of A than with FP32 inputs.) */
 void or_sketch_apply_lowp(int prec, int64_t m, int64_t n, const double *A, int64_t lda,
                           int64_t s, uint64_t seed, double *B, int64_t ldb) {
     double rs = 1.0 / sqrt((double)s);
@@ -686,7 +690,7 @@ void or_sketch_apply_lowp(int prec, int64_t m, int64_t n, const double *A, int64
                 zrow[j] = or_round_p(prec, or_round_fp32(or_sketch_normal(seed, i, j)));
             for (int64_t c = 0; c < n; ++c) {
                 double acc = 0.0;
-                for (int64_t j = 0; j < m; ++j) acc += zrow[j] * or_round_p(prec, A[IDX(j, c, lda)]);
+                for (int64_t j = 0; j < m; ++j) acc += zrow[j] * or_round_fp32(A[IDX(j, c, lda)]);
                 B[IDX(i, c, ldb)] = rs * acc;
             }
         }

@@ -635,8 +635,8 @@ class Batch:
 
     def __init__(self, As, sketch_rows, seeds, variant: int = RQR, want_r: bool = True,
                  tuning: "BatchTuning | None" = None, precision: int = 0):
-        """precision: 0 (FP64 throughout), FP32 or BF16 (the sketch's inputs rounded to that
-        type, every later step FP64)."""
+        """precision: 0 (FP64 throughout), FP32 or BF16 (the sketch on that type's matrix
+        cores: normals in that type, A as its FP32 rounding; every later step FP64)."""
         count = len(As)
         if count < 1:
             raise ValueError("empty batch")

@@ -9,13 +9,19 @@
 // D[4*(l/16) + r][l%16] in register r.
 //
 // Roundings: FP64 -> FP32 is round-to-nearest-even; BF16 is the round-to-nearest-even
-// BF16 of that FP32 value (two roundings, kept apart on purpose: see LowT).  Sketch normals are FP32 numbers (BF16 path: rounded).
+// BF16 of that FP32 value (two roundings, kept apart on purpose: see LowT).  Sketch normals
+// are FP32 numbers (BF16 path: rounded to BF16).  The sketch takes A as its FP32 rounding
+// for both input types: on the BF16 path that value is staged as three BF16 numbers whose
+// sum is exactly it (LowT<BF16>::split3), and each step issues three BF16 MFMAs on the same
+// normals, whose products are exact in the FP32 accumulator.
 #include "tsqr_device.hpp"
 #include "tsqr_launch.hpp"
 
 namespace tsqr {
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ v4f mfma_f32(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -45,6 +51,19 @@ struct LowT<TSQR_LOWP_BF16> {
     return (__bf16)f;
   }
   static __device__ __forceinline__ E from_float(float x) { return (__bf16)x; }
+  // x rounded to FP32, then written as hi + mid + lo exactly: hi is the BF16 rounding of
+  // that FP32 value, mid the BF16 rounding of the remainder, lo the remainder after that.
+  // Each remainder is an exact FP32 difference (a number minus its own rounding to fewer
+  // bits), and the last one has at most 8 significant bits, so lo is exact too.
+  static __device__ __forceinline__ void split3(double x, E& hi, E& mid, E& lo) {
+    float f = (float)x;
+    asm volatile("" : "+v"(f));
+    hi = (__bf16)f;
+    const float r1 = f - (float)hi;
+    mid = (__bf16)r1;
+    const float r2 = r1 - (float)mid;
+    lo = (__bf16)r2;
+  }
 };
 
 // value D[i][j] held at (lane, reg) in the low-precision accumulator layout goes to the
@@ -59,9 +78,10 @@ __device__ __forceinline__ int lowp_to_f64_tile_index(int lane, int r) {
 // Body of workgroup (row block bx, i-group by, column group bz).  EXTL: the staging buffer
 // lives at ext_lds (sketch_lowp_lds_bytes<PREC, JT>() bytes, 16-byte aligned) instead of in
 // the body's own LDS.
+// (BF16: three planes, the hi, mid and lo terms of A)
 template <int PREC, int JT>
 __host__ __device__ constexpr int sketch_lowp_lds_bytes() {
-  return JT * 16 * ((PREC == TSQR_LOWP_FP32) ? 65 : 72) * ((PREC == TSQR_LOWP_FP32) ? 4 : 2);
+  return JT * 16 * ((PREC == TSQR_LOWP_FP32) ? 65 : 72) * ((PREC == TSQR_LOWP_FP32) ? 4 : 6);
 }
 
 template <int PREC, int IT, int JT, int NW, bool EXTL = false>
@@ -74,12 +94,14 @@ __device__ __forceinline__ void sketch_lowp_body(
   constexpr int NC = JT * 16;
   constexpr int LDR = (PREC == TSQR_LOWP_FP32) ? KC + 1 : KC + 8;
   constexpr int T = NW * 64;
-  static_assert(NC * LDR * (int)sizeof(E) == sketch_lowp_lds_bytes<PREC, JT>(), "LDS size");
+  constexpr int PLANES = (PREC == TSQR_LOWP_FP32) ? 1 : 3;
+  constexpr int PL = NC * LDR;  // elements per plane
+  static_assert(PLANES * PL * (int)sizeof(E) == sketch_lowp_lds_bytes<PREC, JT>(), "LDS size");
   E* lds;
   if constexpr (EXTL) {
     lds = reinterpret_cast<E*>(ext_lds);
   } else {
-    __shared__ __attribute__((aligned(16))) E own[NC * LDR];
+    __shared__ __attribute__((aligned(16))) E own[PLANES * PL];
     lds = own;
   }
 
@@ -102,12 +124,31 @@ __device__ __forceinline__ void sketch_lowp_body(
 
   for (int64_t rb = r0; rb < r1; rb += KC) {
     __syncthreads();
-    for (int e = threadIdx.x; e < KC * NC; e += T) {
-      const int rr = e % KC, cc = e / KC;
-      const int64_t row = rb + rr;
-      const int col = c0 + cc;
-      const double v = (row < r1 && col < n) ? A[(int64_t)col * lda + row] : 0.0;
-      lds[cc * LDR + rr] = LowT<PREC>::from_double(v);
+    if constexpr (PREC == TSQR_LOWP_FP32) {
+      for (int e = threadIdx.x; e < KC * NC; e += T) {
+        const int rr = e % KC, cc = e / KC;
+        const int64_t row = rb + rr;
+        const int col = c0 + cc;
+        const double v = (row < r1 && col < n) ? A[(int64_t)col * lda + row] : 0.0;
+        lds[cc * LDR + rr] = LowT<PREC>::from_double(v);
+      }
+    } else {
+      // row pairs: one LDS write per plane for two elements (rr and LDR even)
+      for (int e = threadIdx.x; e < KC / 2 * NC; e += T) {
+        const int rr = 2 * (e % (KC / 2)), cc = e / (KC / 2);
+        const int64_t row = rb + rr;
+        const int col = c0 + cc;
+        const double* src = A + (int64_t)col * lda + row;
+        const double v0 = (row < r1 && col < n) ? src[0] : 0.0;
+        const double v1 = (row + 1 < r1 && col < n) ? src[1] : 0.0;
+        E h0, m0, l0, h1, m1, l1;
+        LowT<PREC>::split3(v0, h0, m0, l0);
+        LowT<PREC>::split3(v1, h1, m1, l1);
+        E* dst = lds + cc * LDR + rr;
+        *reinterpret_cast<v2bf*>(dst) = v2bf{h0, h1};
+        *reinterpret_cast<v2bf*>(dst + PL) = v2bf{m0, m1};
+        *reinterpret_cast<v2bf*>(dst + 2 * PL) = v2bf{l0, l1};
+      }
     }
     __syncthreads();
     // a wave whose row tiles all lie past the sketch's s rows only helps to stage the chunks
@@ -152,10 +193,17 @@ __device__ __forceinline__ void sketch_lowp_body(
         }
 #pragma unroll
         for (int jt = 0; jt < JT; ++jt) {
-          const v8bf b8 =
-              *reinterpret_cast<const v8bf*>(&lds[(16 * jt + c16) * LDR + 32 * g + 8 * q]);
+          const E* bp = &lds[(16 * jt + c16) * LDR + 32 * g + 8 * q];
+          const v8bf bh = *reinterpret_cast<const v8bf*>(bp);
+          const v8bf bm = *reinterpret_cast<const v8bf*>(bp + PL);
+          const v8bf bl = *reinterpret_cast<const v8bf*>(bp + 2 * PL);
+          // smallest terms first
 #pragma unroll
-          for (int it = 0; it < IT; ++it) acc[it][jt] = mfma_bf16(a8[it], b8, acc[it][jt]);
+          for (int it = 0; it < IT; ++it) {
+            acc[it][jt] = mfma_bf16(a8[it], bl, acc[it][jt]);
+            acc[it][jt] = mfma_bf16(a8[it], bm, acc[it][jt]);
+            acc[it][jt] = mfma_bf16(a8[it], bh, acc[it][jt]);
+          }
         }
       }
     }
@@ -223,7 +271,9 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_lowp_wide(
   constexpr int JT = 16, KC = 32, T = NW * 64;
   constexpr int LDR = KC + (PREC == TSQR_LOWP_FP32 ? 4 : 8);
   constexpr int PF = KC * 16 * JT / T;  // prefetched doubles per thread
-  __shared__ __attribute__((aligned(16))) E lds[16 * JT * LDR];
+  constexpr int PLANES = (PREC == TSQR_LOWP_FP32) ? 1 : 3;  // BF16: hi, mid, lo of A
+  constexpr int PL = 16 * JT * LDR;
+  __shared__ __attribute__((aligned(16))) E lds[PLANES * PL];
 
   const int G = kblocks * igroups;
   const int gp8 = (G + 7) / 8;
@@ -236,8 +286,12 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_lowp_wide(
   const int64_t r0 = (int64_t)kb * rows_per_block;
   const int64_t r1 = min(m, r0 + rows_per_block);
   const int it0 = (ig * NW + wave) * IT;
-  // staging: thread t moves row t % 32 of columns t / 32 + (T/32) k, k = 0..PF-1
-  const int srow = (int)threadIdx.x % KC, scol = (int)threadIdx.x / KC;
+  // staging: thread t moves rows srow, srow + 1 (srow = 2 (t % 16)) of columns
+  // scol + CS k (scol = t / 16, CS = T / 16), k = 0..PF/2-1, and stores each row pair into
+  // LDS with one write per plane
+  constexpr int CS = T / (KC / 2);
+  static_assert(2 * (16 * JT / CS) == PF, "staging map");
+  const int srow = 2 * ((int)threadIdx.x % (KC / 2)), scol = (int)threadIdx.x / (KC / 2);
 
   v4f acc[IT][JT];
   v4d acc64[IT][JT];
@@ -249,19 +303,22 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_lowp_wide(
       acc64[ii][jt] = v4d{0.0, 0.0, 0.0, 0.0};
     }
 
-  double pf[PF];
+  double pf[PF];  // pf[2k], pf[2k+1]: rows srow, srow + 1 of column scol + CS k
   auto fetch = [&](int64_t rb) {
     const int64_t row = rb + srow;
-    // a row past the block reads row r0 and a column past n reads column scol (< n): both
+    // a row past the block reads row r0 (the second of a pair whose first row is the
+    // block's last reads that row again) and a column past n reads column scol (< n): all
     // valid addresses, zeroed when staged
     g_f64* bp = (g_f64*)(A + (int64_t)scol * lda + (row < r1 ? row : r0));
-    int lim = n - scol;  // column scol + (T/KC) k exists iff (T/KC) k < lim
-    int64_t cstep = (int64_t)(T / KC) * lda;  // uniform: the offsets stay scalar per fetch
-    asm volatile("" : "+v"(bp), "+v"(lim), "+s"(cstep));
+    g_f64* bp2 = bp + (row + 1 < r1 ? 1 : 0);
+    int lim = n - scol;  // column scol + CS k exists iff CS k < lim
+    int64_t cstep = (int64_t)CS * lda;  // uniform: the offsets stay scalar per fetch
+    asm volatile("" : "+v"(bp), "+v"(bp2), "+v"(lim), "+s"(cstep));
 #pragma unroll
-    for (int k = 0; k < PF; ++k) {
-      const bool ok = (T / KC) * k < lim;
-      pf[k] = bp[ok ? k * cstep : 0];
+    for (int k = 0; k < PF / 2; ++k) {
+      const bool ok = CS * k < lim;
+      pf[2 * k] = bp[ok ? k * cstep : 0];
+      pf[2 * k + 1] = bp2[ok ? k * cstep : 0];
     }
   };
   fetch(r0);
@@ -272,11 +329,24 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_lowp_wide(
       const int64_t rb = rb0 + hh * KC;
       __syncthreads();
       {
-        const bool rok = rb + srow < r1;
+        const bool rok0 = rb + srow < r1, rok1 = rb + srow + 1 < r1;
 #pragma unroll
-        for (int k = 0; k < PF; ++k) {
-          const int col = scol + (T / KC) * k;
-          lds[col * LDR + srow] = LowT<PREC>::from_double((rok && col < n) ? pf[k] : 0.0);
+        for (int k = 0; k < PF / 2; ++k) {
+          const int col = scol + CS * k;
+          const double v0 = (rok0 && col < n) ? pf[2 * k] : 0.0;
+          const double v1 = (rok1 && col < n) ? pf[2 * k + 1] : 0.0;
+          E* dst = lds + col * LDR + srow;  // srow and LDR even: a 2-element aligned pair
+          if constexpr (PREC == TSQR_LOWP_FP32) {
+            *reinterpret_cast<v2f*>(dst) =
+                v2f{LowT<PREC>::from_double(v0), LowT<PREC>::from_double(v1)};
+          } else {
+            E h0, m0, l0, h1, m1, l1;
+            LowT<PREC>::split3(v0, h0, m0, l0);
+            LowT<PREC>::split3(v1, h1, m1, l1);
+            *reinterpret_cast<v2bf*>(dst) = v2bf{h0, h1};
+            *reinterpret_cast<v2bf*>(dst + PL) = v2bf{m0, m1};
+            *reinterpret_cast<v2bf*>(dst + 2 * PL) = v2bf{l0, l1};
+          }
         }
       }
       __syncthreads();
@@ -318,10 +388,18 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_lowp_wide(
 #pragma unroll
         for (int jt = 0; jt < JT; ++jt) {
           typedef __attribute__((address_space(3))) const v8bf lds_v8bf;
-          const v8bf b8 = *(lds_v8bf*)((__attribute__((address_space(3))) const E*)lds +
-                                       (16 * jt + c16) * LDR + 8 * q);
+          typedef __attribute__((address_space(3))) const E lds_e;
+          lds_e* bp = (lds_e*)lds + (16 * jt + c16) * LDR + 8 * q;
+          const v8bf bh = *(lds_v8bf*)bp;
+          const v8bf bm = *(lds_v8bf*)(bp + PL);
+          const v8bf bl = *(lds_v8bf*)(bp + 2 * PL);
+          // smallest terms first
 #pragma unroll
-          for (int ii = 0; ii < IT; ++ii) acc[ii][jt] = mfma_bf16(a8[ii], b8, acc[ii][jt]);
+          for (int ii = 0; ii < IT; ++ii) {
+            acc[ii][jt] = mfma_bf16(a8[ii], bl, acc[ii][jt]);
+            acc[ii][jt] = mfma_bf16(a8[ii], bm, acc[ii][jt]);
+            acc[ii][jt] = mfma_bf16(a8[ii], bh, acc[ii][jt]);
+          }
           if (jt % 4 == 3) __builtin_amdgcn_sched_barrier(0);
         }
       }

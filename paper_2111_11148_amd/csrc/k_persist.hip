@@ -338,7 +338,9 @@ size_t persistent_lds_bytes(int max_jt, int max_rpl_cpw, int precision) {
     upd((size_t)(jt * (jt - 1) / 2 + 2 * jt) * 256 * sizeof(double));  // solve tiles
     upd((size_t)2 * 32 * (jt * 16 + 1) * sizeof(double));               // sketch / Gram
   }
-  (void)precision;  // the low-precision sketch needs less than the FP64 one
+  if (precision == TSQR_LOWP_FP32 || precision == TSQR_LOWP_BF16)
+    for (int jt = 1; jt <= max_jt; jt <<= 1)  // the low-precision sketch's staging planes
+      upd((size_t)jt * 16 * (precision == TSQR_LOWP_FP32 ? 65 * 4 : 72 * 6));
   upd((size_t)(2 * 64 * 8 + 16 * 8) * sizeof(double));                 // register factor
   (void)max_rpl_cpw;
   return b;

@@ -89,7 +89,7 @@ def test_sketch_lowp_parity(prec, m, n, s):
     Bg = host(tsqr.sketch_lowp(dev(A), s, seed, prec))
     Bo = oracle.sketch_apply_lowp(prec, A, s, seed)
     Zo = oracle.sketch_normals(seed, 0, s, 0, m)
-    Ap = np.abs(rnd(A, prec))
+    Ap = np.abs(rnd(A, tsqr.FP32))  # A enters the sketch as FP32 for both input types
     Zp = np.abs(rnd(Zo, prec))
     Dz = normal_uncertainty(Zo, prec)
     rs = 1.0 / math.sqrt(s)
@@ -99,10 +99,10 @@ def test_sketch_lowp_parity(prec, m, n, s):
           f"{(err / tol).max():.3f}")
     assert np.all(err <= tol)
     # against the normals the device generates: only the device's FP32 product rounding
-    # and accumulation remain (GAMMA32); products of two FP32 or BF16 numbers are exact
-    # in FP64, so the reference below is exact up to its own FP64 sum (4 m u)
+    # and accumulation remain (GAMMA32); products of two FP32 numbers are exact in FP64,
+    # so the reference below is exact up to its own FP64 sum (4 m u)
     Zd = rnd(host(tsqr.sketch_normals(seed, 0, s, 0, m)), prec)
-    ref = rs * (Zd @ rnd(A, prec))
+    ref = rs * (Zd @ rnd(A, tsqr.FP32))
     tol_d = rs * GAMMA32 * (np.abs(Zd) @ Ap) + 4 * m * U * np.abs(ref)
     err_d = np.abs(Bg - ref)
     print(f"  against device normals: max err/tol {(err_d / tol_d).max():.3f}")
@@ -221,12 +221,14 @@ def test_mixed_end_to_end_fixed_passes(prec, passes, kappa):
 
 
 def test_mixed_low_precision_breakdown_falls_back():
-    """Columns equal to 1e-9 collapse in BF16; whether or not the low-precision Cholesky
+    """Two columns a BF16 number apart by a factor 1 + 2^-10 are distinct in FP32 (the
+    sketch resolves them) and equal in BF16; whether or not the low-precision Cholesky
     breaks down on the device, the FP64 passes deliver an orthonormal Q (the oracle's
     mixed method breaks down there and falls back to R0).  Three fixed passes, which always
     run the low-precision stage; the automatic mode skips it for this input."""
     A = gen_matrix(4096, 32, 1e3, 3)
-    A[:, 5] = A[:, 4] * (1 + 1e-9)
+    A[:, 4] = rnd(A[:, 4], tsqr.BF16)
+    A[:, 5] = A[:, 4] * (1 + 2.0 ** -10)
     ref = oracle.rxr_cholqr_mixed(A, 64, 7, prec=tsqr.BF16, fp64_passes=3)
     assert ref["info"] == 0 and ref["lp_info"] > 0
     Qd, Rd, info, passes = tsqr.rxr_cholqr_mixed(dev(A), 64, 7, tsqr.BF16, fp64_passes=3)
@@ -297,7 +299,7 @@ def test_mixed_full_size_sketch_sampled_rows(big_mixed, prec):
     A, Ad, s = big_mixed
     seed = 11104
     Bg = host(tsqr.sketch_lowp(Ad, s, seed, prec))
-    Ap = rnd(A, prec)
+    Ap = rnd(A, tsqr.FP32)  # A enters the sketch as FP32 for both input types
     absAp = np.abs(Ap)
     rs = 1.0 / math.sqrt(s)
     m = A.shape[0]

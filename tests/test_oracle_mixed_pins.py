@@ -92,8 +92,9 @@ def test_sketch_lowp_reduces_to_fp64_sketch_on_representable_input():
 
 
 def test_sketch_lowp_rounds_the_input():
-    """A column of 1 + 2^-30 rounds to all ones in both types: the low-precision sketch
-    of it equals the sketch of a ones column; a column of 1 + 2^-12 survives FP32 only."""
+    """A enters the low-precision sketch as its FP32 rounding for both input types: a column
+    of 1 + 2^-30 rounds to all ones, while a column of 1 + 2^-12 (which BF16 itself would
+    round to one) survives both."""
     m, s, seed = 257, 8, 3
     A = F(np.stack([np.full(m, 1 + 2.0 ** -30), np.full(m, 1 + 2.0 ** -12)], axis=1))
     ones = F(np.ones((m, 1)))
@@ -101,10 +102,45 @@ def test_sketch_lowp_rounds_the_input():
         Bl = oracle.sketch_apply_lowp(prec, A, s, seed)
         Bones = oracle.sketch_apply_lowp(prec, ones, s, seed)
         assert np.array_equal(Bl[:, :1], Bones)
-        if prec == BF16:
-            assert np.array_equal(Bl[:, 1:], Bones)
-        else:
-            assert np.allclose(Bl[:, 1:], Bones * (1 + 2.0 ** -12), rtol=1e-14, atol=0)
+        assert np.allclose(Bl[:, 1:], Bones * (1 + 2.0 ** -12), rtol=1e-14, atol=0)
+
+
+def test_sketch_lowp_general_input_is_rounded_normals_times_fp32_input():
+    """On a general A (no exact representation in either type) the low-precision sketch is
+    torch's rounding of the normals (FP32, then BF16 for BF16 inputs) times numpy's FP32
+    rounding of A, summed exactly up to FP64 rounding."""
+    m, n, s, seed = 700, 6, 12, 21104
+    A = gen_matrix(m, n, 1e6, 77)
+    Z = oracle.sketch_normals(seed, 0, s, 0, m)
+    A32 = A.astype(np.float32).astype(np.float64)
+    for prec in (FP32, BF16):
+        Bl = oracle.sketch_apply_lowp(prec, A, s, seed)
+        Zr = torch_round(Z, prec)
+        exp = (Zr @ A32) / math.sqrt(s)
+        assert np.abs(Bl - exp).max() <= 4 * m * U64 * (np.abs(Zr) @ np.abs(A32)).max()
+        # the BF16 rounding of A itself would move the sketch far outside that bound
+        Ab = torch_round(A, BF16)
+        assert np.abs(Bl - (Zr @ Ab) / math.sqrt(s)).max() > 1e3 * 4 * m * U64 * np.abs(exp).max()
+
+
+def test_three_bf16_terms_carry_an_fp32_value_exactly():
+    """The split the BF16 sketch relies on: hi = bf16(x), mid = bf16(x - hi), lo =
+    bf16(x - hi - mid), each difference taken in FP32, gives hi + mid + lo = x exactly for
+    every normal FP32 x (torch's conversions, random values over the working range and the
+    values next to BF16 rounding ties)."""
+    rng = np.random.default_rng(9)
+    x = (rng.standard_normal(200000) * 10.0 ** rng.integers(-25, 25, 200000)).astype(np.float32)
+    ties = np.array([1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, -(1 + 2.0 ** -8), 1 + 2.0 ** -8 + 2.0 ** -23,
+                     1 - 2.0 ** -24, 3.0 * 2.0 ** -20, 65535.0, -65537.0], dtype=np.float32)
+    t = torch.from_numpy(np.concatenate([x, ties]))
+    hi = t.to(torch.bfloat16).to(torch.float32)
+    r1 = t - hi
+    mid = r1.to(torch.bfloat16).to(torch.float32)
+    r2 = r1 - mid
+    lo = r2.to(torch.bfloat16).to(torch.float32)
+    assert torch.equal(lo, r2)  # the last term is exact
+    total = hi.double() + mid.double() + lo.double()
+    assert torch.equal(total, t.double())
 
 
 # ------------------------------------------------------------------------- apply ----
@@ -176,12 +212,16 @@ def test_mixed_driver_pass_counts():
 
 
 def test_mixed_driver_low_precision_breakdown_falls_back():
-    """Two columns equal to 1e-9 collapse after rounding to BF16: the low-precision
-    Cholesky breaks down, R0 alone preconditions, and the FP64 passes still give an
-    orthonormal Q.  (A fixed pass count always runs the low-precision stage; the automatic
-    mode would skip it for this cond(R0).)"""
+    """Two columns a BF16 number apart by a factor 1 + 2^-10 are distinct in FP32 (so the
+    sketch and R0 resolve them) but equal after rounding to BF16: the BF16 stage's A R0^-1
+    is far from orthonormal, its Cholesky breaks down, R0 alone preconditions, and the FP64
+    passes still give an orthonormal Q.  (A fixed pass count always runs the low-precision
+    stage; the automatic mode would skip it for this cond(R0).)"""
     A = gen_matrix(4096, 32, 1e3, 3)
-    A[:, 5] = A[:, 4] * (1 + 1e-9)
+    A[:, 4] = torch_round(A[:, 4], BF16)
+    A[:, 5] = A[:, 4] * (1 + 2.0 ** -10)
+    assert np.array_equal(torch_round(A[:, 5], BF16), A[:, 4])
+    assert not np.array_equal(torch_round(A[:, 5], FP32), A[:, 4])
     r = oracle.rxr_cholqr_mixed(F(A), 64, 7, prec=BF16, fp64_passes=3)
     assert r["lp_info"] > 0
     assert r["info"] == 0 and r["passes"] == 3
