@@ -858,6 +858,106 @@ __global__ __launch_bounds__(kSmallThreads) void k_potrf_reg(int n, const double
   potrf_reg_body<RPL, CPW>(n, W, ldw, R, ldr, stage, info, shift);
 }
 
+// Blocked Cholesky of n <= kCholLdsMax columns in one workgroup, the whole upper triangle
+// resident in LDS (n (n + 1) doubles), 16-row panels:
+//  (a) the block row [R11 R12] = R11^{-T} [W11 W12] by right-looking elimination in
+//      registers: in each of the wavefronts taking part, lanes 0..15 hold the columns of the
+//      diagonal block (the same in every such wavefront) and lanes 16..63 hold 48 columns
+//      of the panel row; row k of the factor reaches every lane by lane reads from lanes
+//      0..15, so the block needs no LDS round trip or barrier (the panel columns undergo
+//      the operations of forward substitution, in the same order);
+//  (b) the trailing update W22 -= R12^T R12 on FP64 MFMA, one wavefront per upper 16 x 16
+//      tile, operands and accumulators read from and written back to LDS.
+// Two barriers per panel; W is read once at the start and R written once at the end, so
+// R may be W itself.  A pivot that is not positive (or NaN) becomes a NaN diagonal entry,
+// which then fills the rest of the factor; info names the first such column.
+constexpr int kCholLdsMax = 128;
+
+__host__ __device__ constexpr size_t chol_lds_bytes(int n) {
+  return (size_t)n * (size_t)(n + 1) * sizeof(double);
+}
+
+__global__ __launch_bounds__(kSmallThreads) void k_potrf_lds(int n, const double* __restrict__ W,
+                                                             int64_t ldw, double* R, int64_t ldr,
+                                                             int stage, int* __restrict__ info,
+                                                             double shift,
+                                                             const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;  // gated off on the device
+  extern __shared__ double A[];     // column c at A + c * lda, rows 0..n-1
+  __shared__ int fail_sh;
+  const int lda = n + 1;
+  const int lane = lane_id(), wave = wave_id();
+  const int q = lane >> 4, c16 = lane & 15;
+  for (int e = threadIdx.x; e < n * n; e += kSmallThreads) {
+    const int c = e / n, i = e % n;
+    A[c * lda + i] = (i <= c) ? W[(int64_t)c * ldw + i] + (i == c ? shift : 0.0) : 0.0;
+  }
+  if (threadIdx.x == 0) fail_sh = -1;
+  __syncthreads();
+
+  for (int j0 = 0; j0 < n; j0 += 16) {
+    const int b = min(16, n - j0), t = n - j0 - b;
+    // (a) the block row: wavefront w takes panel columns 48 w .. 48 w + 47
+    if (wave == 0 || 48 * wave < t) {
+      const bool diag = lane < 16;
+      const int c = diag ? j0 + lane : j0 + 16 + 48 * wave + (lane - 16);
+      const bool cok = diag ? lane < b : c < n;
+      const int kmax = diag ? lane : 15;  // rows of this lane's column inside the block row
+      double col[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) col[i] = (cok && i <= kmax) ? A[c * lda + j0 + i] : 0.0;
+      // Every lane runs every step unmasked: entries below a diagonal lane's own row (and
+      // the columns of lanes past the matrix) take values that are never read or stored.
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        if (k < b) {
+          const double dkk = readlane_f64(col[k], k);
+          const bool ok = dkk > 0.0;
+          const double rkk = ok ? sqrt(dkk) : NAN;
+          if (!ok && lane == 0 && wave == 0 && fail_sh < 0) fail_sh = j0 + k;
+          const double rkc = col[k] / rkk;  // R(j0 + k, c)
+          col[k] = (diag && lane == k) ? rkk : rkc;
+#pragma unroll
+          for (int i = k + 1; i < 16; ++i)
+            col[i] -= readlane_f64(rkc, i) * rkc;  // R(j0 + k, j0 + i) from lane i
+        }
+      }
+      if (cok && (!diag || wave == 0))
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          if (i <= kmax) A[c * lda + j0 + i] = col[i];
+    }
+    __syncthreads();
+    if (t == 0) break;
+    // (b) W22 -= R12^T R12 on the upper tiles (ta, tb) of the trailing block
+    const int o = j0 + 16, tt = (t + 15) / 16, nt = tt * (tt + 1) / 2;
+    for (int u = wave; u < nt; u += kSmallWaves) {
+      int tb = 0;
+      while ((tb + 1) * (tb + 2) / 2 <= u) ++tb;
+      const int ta = u - tb * (tb + 1) / 2;
+      const int ca = o + 16 * ta + c16, cb = o + 16 * tb + c16;
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const double av = ca < n ? A[ca * lda + j0 + 4 * kk + q] : 0.0;
+        const double bv = cb < n ? A[cb * lda + j0 + 4 * kk + q] : 0.0;
+        acc = mfma_f64(av, bv, acc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = o + 16 * ta + 4 * r + q;
+        if (cb < n && row <= cb) A[cb * lda + row] -= acc[r];
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < n * n; e += kSmallThreads) {
+    const int c = e / n, i = e % n;
+    R[(int64_t)c * ldr + i] = (i <= c) ? A[c * lda + i] : 0.0;
+  }
+  if (threadIdx.x == 0 && info && fail_sh >= 0 && *info == 0) *info = 1000 * stage + fail_sh + 1;
+}
+
 // ------------------------------------------------------------------------------------
 // Blocked Cholesky (n > 64), in place in R: k_chol_init copies the upper triangle of W
 // (plus `shift` on the diagonal) to R with zeros below; then for each panel of NB columns
@@ -1454,6 +1554,11 @@ hipError_t launch_potrf(int n, const double* W, int64_t ldw, double* R, int64_t 
                         const int* gate) {
   (void)scratch;
   if (n < 1 || n > kMaxS) return hipErrorInvalidValue;
+  if (n > kPotrfMultiMin && n <= kCholLdsMax) {
+    hipLaunchKernelGGL(k_potrf_lds, dim3(1), dim3(kSmallThreads), chol_lds_bytes(n), st, n, W,
+                       ldw, R, ldr, stage, info, shift, gate);
+    return hipGetLastError();
+  }
   if (n > kPotrfMultiMin)
     return potrf_multi_t<kPotrfMultiNB>(n, W, ldw, R, ldr, stage, info, st, shift, gate);
   const int cpw = pow2_at_least((n + 15) / 16);  // n <= 64: one row of 64 lanes

@@ -275,8 +275,8 @@ def test_potrf_breakdown_and_upper_only():
 
 @pytest.mark.parametrize("n", [100, 200])
 def test_potrf_breakdown_blocked_panel(n):
-    """Breakdown inside a later panel of the blocked factorization (n = 100: the variant
-    factored in LDS, 16-column panels; n = 200: 32-column panels in place)."""
+    """Breakdown inside a later panel of the blocked factorization (n = 100: one workgroup
+    with the matrix in LDS, 16-row panels; n = 200: 32-column panels in place)."""
     W = np.eye(n)
     W[40, 40] = -1.0
     W[n - 50, 3] = 77.0  # lower garbage is ignored
