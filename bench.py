@@ -487,7 +487,7 @@ def kernel_table(m: int, n: int, s: int, variant: str) -> dict:
                  "flops": 1.0 * m * n * (n + 1), "bytes": 8.0 * m * n},
         "sketch_factor": {"symbol": "k_geqrf_reg" if variant != "rlu" else "k_getrf_reg",
                           "phases": [fac], "flops": None, "bytes": None},
-        "potrf": {"symbol": "k_chol_* / k_potrf_reg", "phases": ["potrf1", "potrf2"],
+        "potrf": {"symbol": "k_potrf_reg / k_potrf_lds / k_chol_*", "phases": ["potrf1", "potrf2"],
                   "flops": n ** 3 / 3.0, "bytes": None},
         "trsm_prep": {"symbol": "k_trsm_prep",
                       "phases": ["trsm_prep_r0", "trsm_prep_r1", "trsm_prep_r2"],

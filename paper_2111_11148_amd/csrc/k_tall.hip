@@ -122,6 +122,38 @@ __global__ __launch_bounds__(256) void k_trsm_prep(int n, int jt, const double* 
   trsm_prep_body(n, jt, T, ldt, P, (int)blockIdx.x);
 }
 
+typedef __attribute__((address_space(3))) int lds_int;
+
+// The substitution of one 16-row tile held in registers (layout above): xr holds C = Y on
+// entry and X on exit.  Aop(t, kk) is the A operand of prepared tile t at K-step kk;
+// flags[b] selects the correction step of diagonal block b.
+template <int JT, class AopF>
+__device__ __forceinline__ void trsm_tile_solve(v4d (&xr)[JT], AopF Aop, const lds_int* flags) {
+  constexpr int NOFF = JT * (JT - 1) / 2;
+#pragma unroll
+  for (int b = 0; b < JT; ++b) {
+    // diagonal block: X0 = C T^{-1}, optional correction X = X0 + (C - X0 T) T^{-1}
+    const v4d C = xr[b];
+    v4d x0 = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) x0 = mfma_f64(Aop(NOFF + JT + b, kk), C[kk], x0);
+    if (flags[b]) {
+      v4d e = C;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) e = mfma_f64(Aop(NOFF + b, kk), x0[kk], e);
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) x0 = mfma_f64(Aop(NOFF + JT + b, kk), e[kk], x0);
+    }
+    xr[b] = x0;
+    // right-looking update of the later blocks
+#pragma unroll
+    for (int bb = b + 1; bb < JT; ++bb)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+        xr[bb] = mfma_f64(Aop(off_index(b, bb), kk), xr[b][kk], xr[bb]);
+  }
+}
+
 // TRSM launch shape: 16 wavefronts per workgroup, each tile loaded at the start of its own
 // iteration (measured: loading the next tile one iteration ahead, with 8 wavefronts for
 // the registers it needs, is not faster)
@@ -187,29 +219,7 @@ __device__ __forceinline__ void trsm_mfma_body(int64_t m, int n, const double* _
     // chain over other waves' loads and stores (measured: 2^20 x 128, 0.494 -> 0.482 ms)
     __builtin_amdgcn_s_setprio(1);
 
-#pragma unroll
-    for (int b = 0; b < JT; ++b) {
-      // diagonal block: X0 = C T^{-1}, optional correction X = X0 + (C - X0 T) T^{-1}
-      const v4d C = xr[b];
-      v4d x0 = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) x0 = mfma_f64(Aop(NOFF + JT + b, kk), C[kk], x0);
-      if (flags[b]) {
-        v4d e = C;
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) e = mfma_f64(Aop(NOFF + b, kk), x0[kk], e);
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) x0 = mfma_f64(Aop(NOFF + JT + b, kk), e[kk], x0);
-      }
-      xr[b] = x0;
-      // right-looking update of the later blocks
-#pragma unroll
-      for (int bb = b + 1; bb < JT; ++bb)
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
-          xr[bb] = mfma_f64(Aop(off_index(b, bb), kk), xr[b][kk], xr[bb]);
-    }
-
+    trsm_tile_solve<JT>(xr, Aop, (const lds_int*)flags);
     __builtin_amdgcn_s_setprio(0);
     if (rok) {
       // opaque base and uniform column offsets (per-lane column products would be hoisted)
