@@ -187,7 +187,8 @@ int tsqr_cholqr_ws(int algo, int64_t m, int64_t n, const double* A, int64_t lda,
  * ------------------------------------------------------------------------------------ */
 #define TSQR_LOWP_FP32 1 /* inputs rounded to FP32, FP32 matrix cores, FP32 accumulation */
 #define TSQR_LOWP_BF16 2 /* inputs rounded to BF16 (RNE of the FP32 value), FP32 accumulation;
-                            the sketch's A excepted (see tsqr_sketch_lowp) */
+                            the sketch's A excepted (see tsqr_sketch_lowp) and, in
+                            tsqr_rxr_cholqr_mixed_ws, the stage after the sketch */
 
 /* Randomized XR-preconditioned CholeskyQR with the data-heavy preconditioning steps in low
  * precision and the orthogonalising passes in FP64 (the paper's framework, Section 2.2,
@@ -195,8 +196,9 @@ int tsqr_cholqr_ws(int algo, int64_t m, int64_t n, const double* A, int64_t lda,
  *   B = S A on the `lowp` matrix cores (as tsqr_sketch_lowp: FP32 accumulation over at
  *     most 64 rows, FP64 partial sums);
  *   R0 = R factor of B in FP64 (Householder or LU as `variant`);
- *   R0^{-1} explicitly in FP64 (triangular solve of the identity), rounded to `lowp`;
- *   A1 = A R0^{-1} and W1 = A1^T A1 in `lowp` (W1 summed in FP64);
+ *   R0^{-1} explicitly in FP64 (triangular solve of the identity), rounded to FP32;
+ *   A1 = A R0^{-1} and W1 = A1^T A1 with FP32 inputs for either `lowp` (W1 summed in FP64;
+ *     with BF16 inputs this stage could only save an FP64 pass below cond(A) ~ 1e2);
  *   R1 = chol(W1) in FP64; R01 = R1 R0 (or R0 alone if this Cholesky breaks down: the
  *     low-precision factor is then discarded and the FP64 passes start from R0);
  *   FP64 CholeskyQR passes on A R01^{-1}: Q1 = A R01^{-1} by FP64 substitution from the
@@ -207,8 +209,8 @@ int tsqr_cholqr_ws(int algo, int64_t m, int64_t n, const double* A, int64_t lda,
  *   11 (m n + n (n + 1)) u ||W||_F on the diagonal, u = 2^-52, the shifted CholeskyQR of
  *   Section 2.1), at most 3 passes.  The automatic mode also skips the low-precision
  *   A1/W1/R1 stage (R01 = R0, low precision for the sketch only) unless
- *   ||R0||_F ||R0^{-1}||_F u_p <= 1 (u_p = 2^-24 for FP32, 2^-8 for BF16): beyond that
- *   bound on cond(R0) u_p the stage cannot save an FP64 pass.  Every decision is taken on
+ *   ||R0||_F ||R0^{-1}||_F u_p <= 1 (u_p = 2^-24, the stage's FP32): beyond that bound on
+ *   cond(R0) u_p the stage cannot save an FP64 pass.  Every decision is taken on
  *   the device (the stage's and the passes' kernels are enqueued and return at once when
  *   not needed), so no mode waits on the host and every mode may be captured into a graph.
  *   If the third pass of the automatic mode still needed the shifted retry, the pass
@@ -217,8 +219,8 @@ int tsqr_cholqr_ws(int algo, int64_t m, int64_t n, const double* A, int64_t lda,
  *   run and [1] 1 if the low-precision stage ran (0 if the automatic mode skipped it).
  * lowp (arg 2): TSQR_LOWP_FP32 or TSQR_LOWP_BF16.  Other arguments as in
  * tsqr_rxr_cholqr_ws (shifted by one position); info stages 3 and 4 are the FP64 passes.
- * Workspace: tsqr_mixed_workspace_bytes(m, n, s, lowp) bytes.  n <= 256 (the
- * low-precision kernels; TSQR_ERR_UNSUPPORTED above). */
+ * Workspace: tsqr_mixed_workspace_bytes(m, n, s, lowp) bytes (the same for either lowp).
+ * n <= 256 (the low-precision kernels; TSQR_ERR_UNSUPPORTED above). */
 size_t tsqr_mixed_workspace_bytes(int64_t m, int64_t n, int64_t sketch_rows, int lowp);
 int tsqr_rxr_cholqr_mixed_ws(int variant, int lowp, int64_t m, int64_t n, const double* A,
                              int64_t lda, int64_t sketch_rows, uint64_t seed, int fp64_passes,

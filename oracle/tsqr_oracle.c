@@ -644,10 +644,12 @@ int or_num_threads(void) {
 
 /* ------------------------------------------------------------------------------------
  * Mixed precision (a reading of the benchmark's mixed configuration, not in the paper):
- * the sketch, the preconditioner apply A1 = A R0^{-1} and the first Gram matrix take
- * inputs rounded to FP32 or BF16 (the sketch: its normals; A enters it as FP32 in both
- * cases, see or_sketch_apply_lowp); R0, R0^{-1}, the Cholesky factors, the R products and
- * the final CholeskyQR passes are FP64.  Roundings: FP64 -> FP32 round to nearest even;
+ * the sketch takes its normals rounded to FP32 or BF16 and A as FP32 (see
+ * or_sketch_apply_lowp); the preconditioner apply A1 = A R0^{-1} and the first Gram
+ * matrix take inputs rounded to FP32 (either input type of the sketch; the routines also
+ * take BF16, which the method does not use); R0, R0^{-1}, the Cholesky factors, the R
+ * products and the final CholeskyQR passes are FP64.  Roundings: FP64 -> FP32 round to
+ * nearest even;
  * BF16 = round to nearest even of that FP32 value to 8 significant bits.  The low-precision
  * steps here are the exact (FP64-accumulated) sums of the rounded inputs; a device may
  * add FP32 accumulation error on top, bounded in the tests.
@@ -739,13 +741,14 @@ void or_trtri_upper(int64_t n, const double *T, int64_t ldt, double *X, int64_t 
 
 /* The mixed-precision method with a fixed number of FP64 passes (1..3):
  *   B = lowp sketch;  R0 = R factor of B (FP64);  R0inv = R0^{-1} (FP64);
- *   A1 = lowp(A R0inv);  W1 = lowp Gram of A1;  R1 = chol(W1)  (breakdown -> R01 = R0);
+ *   A1 = fp32(A R0inv);  W1 = FP32 Gram of A1;  R1 = chol(W1)  (breakdown -> R01 = R0);
  *   R01 = R1 R0;  Q = A R01^{-1};  passes: W = Q^T Q, Rk = chol(W), Q = Q Rk^{-1},
  *   R = Rk ... R01.
- * Automatic mode (fp64_passes = 0) first decides whether the low-precision stage (A1, W1,
- * R1) is run at all: only if ||R0||_F ||R0^{-1}||_F u_p <= 1 (u_p = 2^-24 for FP32 inputs,
- * 2^-8 for BF16), an upper bound of cond(R0) u_p, i.e. if the rounding of A to the input
- * type perturbs A R0^{-1} by well under one.  Otherwise R01 = R0 and *lp_info = -1.
+ * The stage (A1, W1, R1) takes FP32 inputs for both input types of the sketch: a stage with
+ * BF16 inputs could only help below cond(A) ~ 1e2.  Automatic mode (fp64_passes = 0) first
+ * decides whether the stage is run at all: only if ||R0||_F ||R0^{-1}||_F u_p <= 1
+ * (u_p = 2^-24, the stage's FP32), an upper bound of cond(R0) u_p, i.e. if the rounding of
+ * A to FP32 perturbs A R0^{-1} by well under one.  Otherwise R01 = R0 and *lp_info = -1.
  * Returns info as or_rxr_cholqr (stages 3, 4 = first, further FP64 passes); *lp_info
  * receives the low-precision Cholesky's breakdown column (0 if none, -1 if the stage was
  * not run), *passes_out the number of FP64 passes completed. */
@@ -776,13 +779,10 @@ int or_rxr_cholqr_mixed(int variant, int prec, int64_t m, int64_t n, const doubl
     if (!info) {
         or_trtri_upper(n, R0, n, R0inv, n);
         int stage = 1;
-        if (fp64_passes == 0) {
-            const double up = (prec == OR_BF16) ? 0x1p-8 : 0x1p-24;
-            stage = or_fro(n, R0, n) * or_fro(n, R0inv, n) * up <= 1.0;
-        }
+        if (fp64_passes == 0) stage = or_fro(n, R0, n) * or_fro(n, R0inv, n) * 0x1p-24 <= 1.0;
         if (stage) {
-            or_apply_rinv_lowp(prec, m, n, A, lda, R0inv, n, A1, m);
-            or_gram_lowp(prec, m, n, A1, m, W, n);
+            or_apply_rinv_lowp(OR_FP32, m, n, A, lda, R0inv, n, A1, m);
+            or_gram_lowp(OR_FP32, m, n, A1, m, W, n);
             lp = or_cholesky_upper(n, W, n, R1, n);
         } else {
             lp = -1;

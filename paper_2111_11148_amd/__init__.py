@@ -401,7 +401,8 @@ def rxr_cholqr_mixed(A: torch.Tensor, sketch_rows: int, seed: int, lowp: int = F
                      R: torch.Tensor | None = None, want_r: bool = True,
                      workspace: torch.Tensor | None = None, info: torch.Tensor | None = None,
                      report: torch.Tensor | None = None, stream=None):
-    """Mixed-precision variant (low-precision sketch, apply and first Gram; FP64 passes).
+    """Mixed-precision variant: the sketch on `lowp` (FP32 or BF16) matrix cores, the
+    preconditioner apply and first Gram matrix with FP32 inputs, FP64 passes.
 
     fp64_passes: 1-3 fixed FP64 CholeskyQR passes, or 0 for the automatic rule (decided on
     the device: the call never waits, so it may be captured into a graph).

@@ -390,8 +390,13 @@ int run_lstsq(int variant, int sketch_kind, int64_t m, int64_t n, const double* 
 }
 
 // ---- mixed precision ---------------------------------------------------------------
-// Extra workspace after the FP64 layout: A1 in the input type, R0^{-1} (FP64 and rounded),
-// identity, R01 = R1 R0, two more n x n factors and the chain's control words.
+// The input type `lowp` is that of the sketch's matrix cores.  The preconditioning stage
+// after it (A1 = A R0^{-1}, its Gram matrix) takes FP32 inputs for either type: with BF16
+// inputs it could only save an FP64 pass below cond(A) ~ 1e2.
+constexpr int kStagePrec = TSQR_LOWP_FP32;
+
+// Extra workspace after the FP64 layout: A1 in the stage's type, R0^{-1} (FP64 and
+// rounded), identity, R01 = R1 R0, two more n x n factors and the chain's control words.
 struct MixedLayout {
   Layout base;
   size_t A1, Rinv, Ri_lp, Id, R01, R3, Rt, ctl, total;
@@ -402,9 +407,10 @@ MixedLayout make_mixed_layout(int64_t m, int64_t n, int64_t s, int lowp) {
   L.base = make_layout(m, n, s);
   const size_t nn = (size_t)n * n * sizeof(double);
   size_t off = L.base.total;
-  L.A1 = off; off += align256((size_t)m * n * lowp_elem_bytes(lowp));
+  (void)lowp;  // the sketch needs no workspace of its own type
+  L.A1 = off; off += align256((size_t)m * n * lowp_elem_bytes(kStagePrec));
   L.Rinv = off; off += align256(nn);
-  L.Ri_lp = off; off += align256(rinv_lowp_bytes(lowp, (int)n));
+  L.Ri_lp = off; off += align256(rinv_lowp_bytes(kStagePrec, (int)n));
   L.Id = off; off += align256(nn);
   L.R01 = off; off += align256(nn);
   L.R3 = off; off += align256(nn);
@@ -419,11 +425,11 @@ MixedLayout make_mixed_layout(int64_t m, int64_t n, int64_t s, int lowp) {
 constexpr double kPassThresh = 0.5;
 
 // Automatic mode: the low-precision stage (A1 = A R0^{-1}, its Gram matrix and Cholesky)
-// runs only when ||R0||_F ||R0^{-1}||_F u_p <= 1, an upper bound of cond(R0) u_p: then the
-// rounding of A to the input type perturbs A R0^{-1} by well under one and the stage can
-// leave a single FP64 pass. Otherwise it could not save a pass, and the FP64 passes start
-// from A R0^{-1} (low precision for the sketch only).  u_p of each input type:
-inline double lowp_unit(int lowp) { return lowp == TSQR_LOWP_BF16 ? 0x1p-8 : 0x1p-24; }
+// runs only when ||R0||_F ||R0^{-1}||_F u_p <= 1, an upper bound of cond(R0) u_p with u_p
+// the stage's FP32 unit 2^-24: then the rounding of A to FP32 perturbs A R0^{-1} by well
+// under one and the stage can leave a single FP64 pass. Otherwise it could not save a
+// pass, and the FP64 passes start from A R0^{-1} (low precision for the sketch only).
+constexpr double kStageUnit = 0x1p-24;
 
 int run_chain_mixed(int variant, int lowp, int64_t m, int64_t n, const double* A, int64_t lda,
                     int64_t s, uint64_t seed, int fp64_passes, double* Q, int64_t ldq,
@@ -469,14 +475,15 @@ int run_chain_mixed(int variant, int lowp, int64_t m, int64_t n, const double* A
     TSQR_CHECK(launch_pass_decide(ni, R0, n, nullptr, nullptr, 0.0, c->need + 3, c->norms, st));
     TSQR_CHECK(launch_pass_decide(ni, Rinv, n, nullptr, nullptr, 0.0, c->need + 4, c->norms + 2,
                                   st));
-    TSQR_CHECK(launch_mixed_ctl(kCtlStage, 0, 0, lowp_unit(lowp), c, info, nullptr, st));
+    TSQR_CHECK(launch_mixed_ctl(kCtlStage, 0, 0, kStageUnit, c, info, nullptr, st));
   }
   // low-precision preconditioner apply, first Gram matrix and its Cholesky factor (gated:
   // in the automatic mode they return at once when the stage is not worth running)
   const int* sg = &c->stage;
-  TSQR_PHASE("rinv_round", launch_rinv_prep(lowp, ni, Rinv, n, Ri_lp, st, sg));
-  TSQR_PHASE("apply_lowp", launch_apply_rinv_lowp(lowp, m, ni, A, lda, Ri_lp, A1, m, st, sg));
-  TSQR_PHASE("gram_lowp", launch_gram_lowp(lowp, L.gp, m, ni, A1, m, part, st, sg));
+  TSQR_PHASE("rinv_round", launch_rinv_prep(kStagePrec, ni, Rinv, n, Ri_lp, st, sg));
+  TSQR_PHASE("apply_lowp",
+             launch_apply_rinv_lowp(kStagePrec, m, ni, A, lda, Ri_lp, A1, m, st, sg));
+  TSQR_PHASE("gram_lowp", launch_gram_lowp(kStagePrec, L.gp, m, ni, A1, m, part, st, sg));
   TSQR_PHASE("gram1_reduce", launch_gram_reduce(L.gp, ni, part, W, n, st, sg));
   TSQR_PHASE("potrf1", launch_potrf(ni, W, n, R1, n, 2, &c->lp_info, fac, st, 0.0, sg));
   // R01 = R1 R0, or R0 alone when the low-precision Cholesky broke down or did not run

@@ -221,26 +221,29 @@ def test_mixed_end_to_end_fixed_passes(prec, passes, kappa):
 
 
 def test_mixed_low_precision_breakdown_falls_back():
-    """Two columns a BF16 number apart by a factor 1 + 2^-10 are distinct in FP32 (the
-    sketch resolves them) and equal in BF16; whether or not the low-precision Cholesky
-    breaks down on the device, the FP64 passes deliver an orthonormal Q (the oracle's
-    mixed method breaks down there and falls back to R0).  Three fixed passes, which always
-    run the low-precision stage; the automatic mode skips it for this input."""
-    A = gen_matrix(4096, 32, 1e3, 3)
-    A[:, 4] = rnd(A[:, 4], tsqr.BF16)
-    A[:, 5] = A[:, 4] * (1 + 2.0 ** -10)
+    """Two columns an FP32 number apart by a factor 1 + 2^-30 (distinct in FP64, equal in
+    FP32, the stage's input type); whether or not the stage's Cholesky breaks down on the
+    device, the FP64 passes deliver an orthonormal Q (the oracle's mixed method breaks down
+    there with the BF16 sketch's R0 and falls back to R0).  Three fixed passes, which
+    always run the low-precision stage; the automatic mode skips it for this input."""
+    A = gen_matrix(4096, 32, 1e3, 5)
+    A[:, 4] = rnd(A[:, 4], tsqr.FP32)
+    A[:, 5] = A[:, 4] * (1 + 2.0 ** -30)
     ref = oracle.rxr_cholqr_mixed(A, 64, 7, prec=tsqr.BF16, fp64_passes=3)
     assert ref["info"] == 0 and ref["lp_info"] > 0
-    Qd, Rd, info, passes = tsqr.rxr_cholqr_mixed(dev(A), 64, 7, tsqr.BF16, fp64_passes=3)
-    assert int(info.item()) == 0 and int(passes[0].item()) == 3
-    assert oracle.orthogonality(host(Qd)) <= 1e-13
-    # automatic mode: the stage is skipped (oracle lp_info -1); this nearly singular input
-    # sits at the edge of the pass rule, so only the outcome is compared, not the count
-    Qa, Ra, infoa, pa = tsqr.rxr_cholqr_mixed(dev(A), 64, 7, tsqr.BF16, fp64_passes=0)
-    refa = oracle.rxr_cholqr_mixed(A, 64, 7, prec=tsqr.BF16, fp64_passes=0)
-    assert refa["lp_info"] == -1 and int(infoa.item()) == 0 and 1 <= int(pa[0].item()) <= 3
-    assert int(pa[1].item()) == 0
-    assert oracle.orthogonality(host(Qa)) <= 1e-13
+    for prec in PRECS:
+        print(f"prec={prec}", flush=True)
+        Qd, Rd, info, passes = tsqr.rxr_cholqr_mixed(dev(A), 64, 7, prec, fp64_passes=3)
+        assert int(info.item()) == 0 and int(passes[0].item()) == 3
+        assert oracle.orthogonality(host(Qd)) <= 1e-13
+        # automatic mode: the stage is skipped (oracle lp_info -1); this nearly singular
+        # input sits at the edge of the pass rule, so only the outcome is compared, not the
+        # count
+        Qa, Ra, infoa, pa = tsqr.rxr_cholqr_mixed(dev(A), 64, 7, prec, fp64_passes=0)
+        refa = oracle.rxr_cholqr_mixed(A, 64, 7, prec=prec, fp64_passes=0)
+        assert refa["lp_info"] == -1 and int(infoa.item()) == 0 and 1 <= int(pa[0].item()) <= 3
+        assert int(pa[1].item()) == 0
+        assert oracle.orthogonality(host(Qa)) <= 1e-13
 
 
 def test_mixed_deterministic_and_rless():

@@ -212,26 +212,30 @@ def test_mixed_driver_pass_counts():
 
 
 def test_mixed_driver_low_precision_breakdown_falls_back():
-    """Two columns a BF16 number apart by a factor 1 + 2^-10 are distinct in FP32 (so the
-    sketch and R0 resolve them) but equal after rounding to BF16: the BF16 stage's A R0^-1
-    is far from orthonormal, its Cholesky breaks down, R0 alone preconditions, and the FP64
-    passes still give an orthonormal Q.  (A fixed pass count always runs the low-precision
-    stage; the automatic mode would skip it for this cond(R0).)"""
-    A = gen_matrix(4096, 32, 1e3, 3)
-    A[:, 4] = torch_round(A[:, 4], BF16)
-    A[:, 5] = A[:, 4] * (1 + 2.0 ** -10)
-    assert np.array_equal(torch_round(A[:, 5], BF16), A[:, 4])
-    assert not np.array_equal(torch_round(A[:, 5], FP32), A[:, 4])
-    r = oracle.rxr_cholqr_mixed(F(A), 64, 7, prec=BF16, fp64_passes=3)
-    assert r["lp_info"] > 0
-    assert r["info"] == 0 and r["passes"] == 3
-    assert oracle.orthogonality(r["Q"]) <= 1e-13
+    """Two columns an FP32 number apart by a factor 1 + 2^-30 (distinct in FP64, equal in
+    FP32): the stage's A R0^-1 in FP32 is then far from orthonormal and, for this seeded
+    input with the BF16 sketch's R0, its Cholesky breaks down at column 6; R0 alone
+    preconditions, and the FP64 passes still give an orthonormal Q.  (Whether the stage
+    breaks down depends on R0, so on the sketch: with the FP32 sketch's R0 it does not, and
+    the three passes succeed as well.  A fixed pass count always runs the stage; the
+    automatic mode would skip it for this cond(R0).)"""
+    A = gen_matrix(4096, 32, 1e3, 5)
+    A[:, 4] = torch_round(A[:, 4], FP32)
+    A[:, 5] = A[:, 4] * (1 + 2.0 ** -30)
+    assert np.array_equal(torch_round(A[:, 5], FP32), A[:, 4])
+    assert not np.array_equal(A[:, 5], A[:, 4])
+    for prec, lp in ((BF16, 6), (FP32, 0)):
+        r = oracle.rxr_cholqr_mixed(F(A), 64, 7, prec=prec, fp64_passes=3)
+        assert r["lp_info"] == lp
+        assert r["info"] == 0 and r["passes"] == 3
+        assert oracle.orthogonality(r["Q"]) <= 1e-13
 
 
 @pytest.mark.parametrize("prec,kappa,runs", [(FP32, 1e4, True), (FP32, 1e10, False),
-                                             (BF16, 2.0, True), (BF16, 1e4, False)])
+                                             (BF16, 1e4, True), (BF16, 1e10, False)])
 def test_mixed_driver_auto_stage_rule(prec, kappa, runs):
-    """Automatic mode runs the low-precision stage iff ||R0||_F ||R0^-1||_F u_p <= 1.
+    """Automatic mode runs the low-precision stage iff ||R0||_F ||R0^-1||_F u_p <= 1, with
+    u_p = 2^-24 for either sketch type (the stage takes FP32 inputs in both).
     Checked on inputs far from the threshold against LAPACK's R factor of A itself (the
     sketch changes the singular values of R0 by a modest factor only): >= 10x below it the
     stage runs (lp_info 0), >= 10x above it it is skipped (lp_info -1); the result is a
@@ -239,8 +243,7 @@ def test_mixed_driver_auto_stage_rule(prec, kappa, runs):
     m, n, s = 2048, 16, 32
     A = gen_matrix(m, n, kappa, 311104)
     Rl = np.linalg.qr(A, mode="r")
-    up = 2.0 ** -24 if prec == FP32 else 2.0 ** -8
-    est = np.linalg.norm(Rl) * np.linalg.norm(np.linalg.inv(Rl)) * up
+    est = np.linalg.norm(Rl) * np.linalg.norm(np.linalg.inv(Rl)) * 2.0 ** -24
     assert (est <= 0.1) if runs else (est >= 10.0)
     r = oracle.rxr_cholqr_mixed(A, s, 11104, prec=prec, fp64_passes=0)
     assert r["info"] == 0
