@@ -30,6 +30,31 @@ __device__ __forceinline__ double col_elem(const double (&x)[RPL], int row) {
   return __shfl(v, row & 63, kWave);
 }
 
+// value at a uniform `row` of a register-distributed column (row = lane + 64 r), as a
+// scalar: every register's lane is read and the scalar selected, so that no register is
+// indexed by a run-time value (which would move the column to scratch memory)
+template <int RPL>
+__device__ __forceinline__ double col_read(const double (&x)[RPL], int row) {
+  const int l = row & 63, rr = row >> 6;
+  double v = readlane_f64(x[0], l);
+#pragma unroll
+  for (int r = 1; r < RPL; ++r) {
+    const double t = readlane_f64(x[r], l);
+    v = (rr == r) ? t : v;
+  }
+  return v;
+}
+
+// x(row) = v for a uniform `row`: one lane of one register replaced (a select in every
+// register, for the same reason)
+template <int RPL>
+__device__ __forceinline__ void col_write(double (&x)[RPL], int row, double v) {
+  const bool mine = lane_id() == (row & 63);
+  const int rr = row >> 6;
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) x[r] = (mine && rr == r) ? v : x[r];
+}
+
 template <int CPW, int RPL>
 __device__ __forceinline__ void col_select(const double (&col)[CPW][RPL], int qsel,
                                            double (&x)[RPL]) {
@@ -124,7 +149,7 @@ __device__ __forceinline__ void geqrf_reg_body(int s, int n,
         part += (i > k && i < s) ? x[r] * x[r] : 0.0;
       }
       const double xnorm2 = wave_sum(part);
-      const double alpha = col_elem(x, k);
+      const double alpha = col_read(x, k);
       double beta, tau, scal;
       house(alpha, xnorm2, beta, tau, scal);
 #pragma unroll
@@ -629,7 +654,7 @@ __device__ __forceinline__ void getrf_reg_body(int s, int n,
       }
       wave_argmax(bv, bi);
       const int p = bi;
-      const double vk = col_elem(x, k), vp = col_elem(x, p);
+      const double vk = col_read(x, k), vp = col_read(x, p);
       const double pivot = vp;
       // multipliers of the swapped column (row p now holds the old row k)
 #pragma unroll
@@ -648,21 +673,18 @@ __device__ __forceinline__ void getrf_reg_body(int s, int n,
     double l[RPL];
 #pragma unroll
     for (int r = 0; r < RPL; ++r) l[r] = lbuf[buf][lane + 64 * r];
-    // swap rows k and p in columns >= k; eliminate below row k in columns > k
+    // swap rows k and p in columns >= k (two lane writes); eliminate below row k in
+    // columns > k (the multipliers are zero in rows <= k)
 #pragma unroll
     for (int qc = 0; qc < CPW; ++qc) {
       const int c = wave + kSmallWaves * qc;
       if (c >= k && c < n) {
-        const double vk = col_elem(col[qc], k), vp = col_elem(col[qc], p);
+        const double vk = col_read(col[qc], k), vp = col_read(col[qc], p);
+        col_write(col[qc], p, vk);
+        col_write(col[qc], k, vp);
+        if (c > k)
 #pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-          const int i = lane + 64 * r;
-          double v = col[qc][r];
-          if (i == k) v = vp;
-          else if (i == p) v = vk;
-          if (c > k && i > k) v -= l[r] * vp;
-          col[qc][r] = v;
-        }
+          for (int r = 0; r < RPL; ++r) col[qc][r] -= l[r] * vp;
       }
     }
   }
