@@ -433,21 +433,29 @@ def batched_comparison(args):
           f"{ms_loop:.3f} ms", file=sys.stderr, flush=True)
     del works
 
-    # the FP32 variant: the sketch from FP32-rounded inputs, every later step FP64
+    # the low-precision variants: the sketch on FP32 or BF16 matrix cores (A as its FP32
+    # rounding), every later step FP64
     del g
-    b32 = tsqr.Batch(As, ss, seeds, precision=tsqr.FP32)
-    tuning32, tuned32 = b32.autotune()
-    g32 = torch.cuda.CUDAGraph()
-    with torch.cuda.stream(st):
-        b32.run(stream=st)
-    torch.cuda.synchronize()
-    with torch.cuda.graph(g32, stream=st):
-        b32.run(stream=st)
-    ms32 = timed(g32.replay, args.batch_steps, 2)
-    info32 = bool(torch.all(b32.info == 0).item())
-    worst32 = max(gpu_metrics(As[i], b32.Q[i], b32.R[i])[0] for i in range(len(descs)))
-    print(f"# batched fp32 sketch: {ms32:.3f} ms per batch ({len(descs) / ms32 * 1e3:.0f} "
-          f"problems/s)", file=sys.stderr, flush=True)
+    lowp_res = {}
+    for name, prec in (("fp32", tsqr.FP32), ("bf16", tsqr.BF16)):
+        bl = tsqr.Batch(As, ss, seeds, precision=prec)
+        tuning_l, _ = bl.autotune()
+        gl = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(st):
+            bl.run(stream=st)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(gl, stream=st):
+            bl.run(stream=st)
+        ms_l = timed(gl.replay, args.batch_steps, 2)
+        info_l = bool(torch.all(bl.info == 0).item())
+        worst_l = max(gpu_metrics(As[i], bl.Q[i], bl.R[i])[0] for i in range(len(descs)))
+        print(f"# batched {name} sketch: {ms_l:.3f} ms per batch "
+              f"({len(descs) / ms_l * 1e3:.0f} problems/s)", file=sys.stderr, flush=True)
+        lowp_res[name] = {"problems_per_s": round(len(descs) / ms_l * 1e3, 1),
+                          "ms_per_batch": round(ms_l, 4), "tuning": tuning_l.as_dict(),
+                          "all_info_zero": info_l, "worst_ortho": worst_l,
+                          "speedup_vs_fp64_batch": round(ms / ms_l, 3)}
+        del gl, bl
     return {"workload": f"{len(descs)} uneven problems, m in [4096, 65536], n in {{16,32,64,128}}, "
                         "kappa 1e2..1e10, s = 2n, rqr + 1 pass, fp64",
             "problems_per_s": round(len(descs) / ms * 1e3, 1), "ms_per_batch": round(ms, 4),
@@ -463,11 +471,7 @@ def batched_comparison(args):
                            "speedup_vs_phase_graph": round(ms / ms_pg, 3),
                            "all_info_zero": info_p, "worst_ortho": worst_p},
             "autotune_ms": round(tuned_ms, 4), "graph": True, "all_info_zero": info_ok,
-            "worst_ortho": worst,
-            "fp32": {"problems_per_s": round(len(descs) / ms32 * 1e3, 1),
-                     "ms_per_batch": round(ms32, 4), "tuning": tuning32.as_dict(),
-                     "all_info_zero": info32, "worst_ortho": worst32,
-                     "speedup_vs_fp64_batch": round(ms / ms32, 3)}}
+            "worst_ortho": worst, "fp32": lowp_res["fp32"], "bf16": lowp_res["bf16"]}
 
 
 # Kernels of the FP64 chain: the phases (library event names) each one runs under, the
