@@ -106,7 +106,10 @@ def test_sketch_leading_dimension_and_determinism():
                                        (300, 150, 1e5), (512, 256, 1e6), (130, 65, 1e2),
                                        (1000, 100, 1e5), (1536, 700, 1e4), (512, 200, 1e12),
                                        (2048, 1024, 1e8), (700, 333, 1e6),
-                                       (3000, 200, 1e6), (8192, 64, 1e4), (4100, 300, 1e8)])
+                                       (3000, 200, 1e6), (8192, 64, 1e4), (4100, 300, 1e8),
+                                       (200, 100, 1e10), (256, 65, 1e6), (129, 128, 1e3),
+                                       (250, 127, 1e12), (128, 64, 1e8), (256, 50, 1e10),
+                                       (500, 60, 1e6)])
 def test_sketch_factor_parity(variant, s, n, kappa):
     """R0 is the unique (sign-normalised) R or U factor: ||dR0||/||R0|| <= c n u kappa(B)."""
     B = gen_matrix(s, n, kappa, 17 + s)
@@ -133,10 +136,13 @@ def test_sketch_factor_breakdown():
 
 
 @pytest.mark.parametrize("variant", [tsqr.RQR, tsqr.RLU])
-@pytest.mark.parametrize("s,n,col", [(512, 200, 100), (1024, 300, 257), (2048, 600, 599)])
+@pytest.mark.parametrize("s,n,col", [(512, 200, 100), (1024, 300, 257), (2048, 600, 599),
+                                     (256, 128, 70), (130, 65, 64), (200, 100, 31),
+                                     (128, 64, 40), (300, 60, 59)])
 def test_sketch_factor_breakdown_later_panel(variant, s, n, col):
-    """A zero column inside a later panel of the blocked factorizations: the code names that
-    column, as the oracle's does, and R0 carries a NaN there."""
+    """A zero column inside a later panel of the blocked factorizations (or of a later
+    row block or column half of the one-column-per-lane QR): the code names that column,
+    as the oracle's does, and R0 carries a NaN there."""
     B = gen_matrix(s, n, 10.0, 5 + col)
     B[:, col] = 0.0
     R0, info = tsqr.sketch_factor(dev(B), variant)
