@@ -76,13 +76,19 @@ __device__ __forceinline__ void trsm_prep_body(int n, int jt, const double* __re
     P[(size_t)(noff + b) * 256 + i * 16 + sigma16(j)] = -v;
   }
   __syncthreads();
-  if (threadIdx.x < 16) {  // column j of the inverse by back substitution
+  if (threadIdx.x < 16) {  // column j of the inverse by back substitution, in registers
+    // (x[k] = 0 for k > j, so the terms past j add exact zeros after the same sum)
     const int j = threadIdx.x;
+    double x[16];
+#pragma unroll
     for (int i = 15; i >= 0; --i) {
       double acc = (i == j) ? 1.0 : 0.0;
-      for (int k = i + 1; k <= j; ++k) acc -= tb[i][k] * ti[k][j];
-      ti[i][j] = (i <= j) ? acc / tb[i][i] : 0.0;
+#pragma unroll
+      for (int k = i + 1; k < 16; ++k) acc -= tb[i][k] * x[k];
+      x[i] = (i <= j) ? acc / tb[i][i] : 0.0;
     }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) ti[i][j] = x[i];
   }
   __syncthreads();
   for (int e = threadIdx.x; e < 256; e += blockDim.x) {
