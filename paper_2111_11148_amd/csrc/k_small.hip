@@ -112,16 +112,20 @@ __host__ __device__ constexpr int reg_factor_lds_doubles() {
 
 // ================================================================ Householder QR ====
 // Update of column slots Q0 .. CPW-1 of one wavefront by the step's reflector, with the
-// CPW - Q0 dot products summed over the 64 lanes together: each lane's partial products
-// go to LDS (one padded row per lane, in the wavefront's own region xw of 64 * 9 doubles),
-// lane l reads back the partials of slot l / G from lanes g, g + G, ... (G = 64 / slots,
-// g = l % G) in that order, the G lanes of a slot add their values by DPP (pairs that
-// differ in lane bit 0, then bit 1, then the mirrored halves of 8 and of 16 lanes; each
-// lane ends with the same sum), and slot q's total is read from lane G q (with 32 lanes a
-// slot, the two rows of 16 are read and added).  One LDS round
-// trip and a few DPP stages replace a 64-lane reduction per column, and no barrier is
-// needed (only this wavefront touches xw, and its LDS operations complete in order).
-// Only columns c > kdone change: a slot with c <= kdone gets w = 0 and is left as it is.
+// CPW - Q0 dot products summed over the 64 lanes together:
+//   * each lane's partial products go to LDS (one padded row per lane, in the
+//     wavefront's own region xw of 64 * 9 doubles);
+//   * lane l reads back the partials of slot l / G from lanes g, g + G, ... in that order
+//     (G = 64 / slots, g = l % G);
+//   * the G lanes of a slot add their values by DPP: pairs that differ in lane bit 0, then
+//     bit 1, then the mirrored halves of 8 and of 16 lanes, so that each lane ends with
+//     the same sum;
+//   * slot q's total is read from lane G q (with 32 lanes a slot, the sums of its two rows
+//     of 16 are read and added).
+// One LDS round trip and a few DPP stages replace a 64-lane reduction per column, and no
+// barrier is needed (only this wavefront touches xw, and its LDS operations complete in
+// order).  Only columns c > kdone change: a slot with c <= kdone gets w = 0 and is left as
+// it is.
 template <int RPL, int CPW, int Q0>
 __device__ __forceinline__ void qr_slots_update(double (&col)[CPW][RPL], const double (&v)[RPL],
                                                 double tau, int kdone, int wave, int lane,
