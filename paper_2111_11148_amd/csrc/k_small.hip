@@ -641,11 +641,10 @@ __global__ __launch_bounds__(256) void k_copy_cols(int s, int n, const double* _
 // ========================================================== partial-pivot LU =========
 // Pivot: first row index of the largest |b_ik| among rows i >= k (NaN counts as largest).
 __device__ __forceinline__ bool piv_better(double a, int ia, double b, int ib) {
-  // is (a, ia) preferred over (b, ib)?
-  const bool an = isnan(a), bn = isnan(b);
-  if (an != bn) return an;
-  if (!an && a != b) return a > b;
-  return ia < ib;
+  // is (a, ia) preferred over (b, ib)?  (bitwise operators, no short-circuit: compares and
+  // selects rather than branches inside the reductions)
+  const bool an = isnan(a), bn = isnan(b), first = ia < ib, gt = a > b, eq = a == b;
+  return (an & !bn) | (an & bn & first) | (!an & !bn & (gt | (eq & first)));
 }
 
 // The preferred (value, index) pair of the wavefront, in every lane.  piv_better is a total
@@ -793,6 +792,137 @@ __global__ __launch_bounds__(kSmallThreads) void k_getrf_reg(int s, int n,
                                                              int64_t ldb, double* __restrict__ R,
                                                              int64_t ldr, int* __restrict__ info) {
   getrf_reg_body<RPL, CPW>(s, n, B, ldb, R, ldr, info);
+}
+
+// Partial-pivot LU with implicit row interchanges, for s <= 256 rows and four or eight
+// column slots per wavefront (layout as in getrf_reg_body).  Rows are never moved: pos (in
+// registers, the same in every wavefront) gives the logical position of each physical row
+// and perm (LDS) its inverse.  Step k:
+//   * the owner of column k takes the pivot among the rows at positions >= k (largest
+//     |a|, first position on ties, exactly as with explicit swaps), exchanges positions k
+//     and p, and publishes the multipliers of the rows now past position k by physical
+//     row, with the pivot's physical row and the exchanged rows;
+//   * after the barrier every wavefront updates its positions and its columns c > k by
+//     a -= l u, where u is the pivot row's entry of the column: the one lane holding the
+//     pivot row writes all its registers to the wavefront's LDS region and every lane
+//     reads the register it needs (no lane selects, no barrier: one wavefront's LDS
+//     operations complete in order).
+// Each entry sees the same operations in the same order as with explicit swaps, so the
+// factor is the same; the pivot row of step k keeps its values from then on and is row k
+// of U, which the output writes at its logical position.
+template <int RPL, int CPW>
+__global__ __launch_bounds__(kSmallThreads) void k_getrf_ip(int s, int n,
+                                                            const double* __restrict__ B,
+                                                            int64_t ldb, double* __restrict__ R,
+                                                            int64_t ldr, int* __restrict__ info) {
+  __shared__ double lbuf[2][64 * RPL];             // multipliers by physical row
+  __shared__ double ukk[kSmallWaves * CPW];        // pivots by step
+  __shared__ int perm[64 * RPL];                   // logical position -> physical row
+  __shared__ int piv_sh[2][3];                     // pivot row, row at position k, position p
+  __shared__ double rowb[kSmallWaves][CPW * RPL];  // the pivot lane's registers, per wavefront
+  const int lane = lane_id(), wave = wave_id();
+  double col[CPW][RPL];
+  int pos[RPL];
+#pragma unroll
+  for (int qc = 0; qc < CPW; ++qc)
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int c = wave + kSmallWaves * qc, i = lane + 64 * r;
+      col[qc][r] = (c < n && i < s) ? B[(int64_t)c * ldb + i] : 0.0;
+    }
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) pos[r] = lane + 64 * r;
+  for (int i = threadIdx.x; i < 64 * RPL; i += kSmallThreads) perm[i] = i;
+  __syncthreads();
+
+  for (int k = 0; k < n; ++k) {
+    const int buf = k & 1;
+    if (wave == k % kSmallWaves) {
+      double x[RPL];
+      col_select(col, k / kSmallWaves, x);
+      double bv = -1.0;
+      int bi = 0x7fffffff;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int i = lane + 64 * r;
+        if (pos[r] >= k && i < s) {
+          const double a = fabs(x[r]);
+          if (piv_better(a, pos[r], bv, bi)) {
+            bv = a;
+            bi = pos[r];
+          }
+        }
+      }
+      wave_argmax(bv, bi);
+      const int pl = bi;                        // position of the pivot
+      const int pp = perm[pl], pk = perm[k];    // physical rows at positions p and k
+      const double pivot = col_read(x, pp);
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int i = lane + 64 * r;
+        const int np = (i == pp) ? k : ((i == pk) ? pl : pos[r]);
+        lbuf[buf][i] = (np > k && i < s) ? x[r] / pivot : 0.0;
+      }
+      if (lane == 0) {
+        piv_sh[buf][0] = pp;
+        piv_sh[buf][1] = pk;
+        piv_sh[buf][2] = pl;
+        ukk[k] = pivot;
+        perm[pl] = pk;
+        perm[k] = pp;
+      }
+    }
+    __syncthreads();
+    const int pp = piv_sh[buf][0], pk = piv_sh[buf][1], pl = piv_sh[buf][2];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lane + 64 * r;
+      pos[r] = (i == pp) ? k : ((i == pk) ? pl : pos[r]);
+    }
+    double l[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) l[r] = lbuf[buf][lane + 64 * r];
+    double* rw = rowb[wave];
+    if (lane == (pp & 63)) {
+#pragma unroll
+      for (int qc = 0; qc < CPW; ++qc)
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) rw[qc * RPL + r] = col[qc][r];
+    }
+    const int rp = pp >> 6;
+#pragma unroll
+    for (int qc = 0; qc < CPW; ++qc) {
+      const int c = wave + kSmallWaves * qc;
+      const double u = (c > k) ? rw[qc * RPL + rp] : 0.0;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) col[qc][r] -= l[r] * u;
+    }
+  }
+  __syncthreads();
+  // sign-normalised R0 = diag(sign u_kk) U: the entries of physical row i go to its
+  // logical position (rows of one column stay inside that column's n doubles)
+#pragma unroll
+  for (int qc = 0; qc < CPW; ++qc) {
+    const int c = wave + kSmallWaves * qc;
+    if (c >= n) continue;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = pos[r];
+      if (i >= n || lane + 64 * r >= s) continue;
+      double v = 0.0;
+      if (i <= c) {
+        const double ui = ukk[i];
+        const double sg = (ui < 0.0) ? -1.0 : 1.0;
+        v = (i == c) ? fabs(ui) : sg * col[qc][r];
+        if (i == c && !(ui != 0.0)) v = NAN;
+      }
+      R[(int64_t)c * ldr + i] = v;
+    }
+  }
+  if (info) {
+    const int bad = block_first_bad(n, [&](int k) { return ukk[k]; });
+    if (threadIdx.x == 0 && bad && *info == 0) *info = 1000 + bad;
+  }
 }
 
 __global__ __launch_bounds__(kSmallThreads) void k_getrf_glb(int s, int n,
@@ -1603,8 +1733,22 @@ hipError_t launch_sketch_factor(int variant, int s, int n, const double* B, int6
                                 hipStream_t st) {
   const int rpl = pow2_at_least((s + 63) / 64), cpw = pow2_at_least((n + 15) / 16);
   dim3 grid(1), block(kSmallThreads);
-  // LU of 64+ columns: the blocked form is faster than the register kernel from n = 64
-  // (measured: 256 x 128, 0.40 -> 0.38 ms)
+  // LU with implicit interchanges from two rows per lane up to 256 rows, 33..128 columns
+  // (measured against the blocked form: 256 x 128, 360 -> 325 us; 256 x 64, 184 -> 127 us;
+  // 128 x 64, 180 -> 88 us)
+  if (variant == 1 && (rpl == 2 || rpl == 4) && (cpw == 4 || cpw == 8)) {
+    if (rpl == 2 && cpw == 4)
+      hipLaunchKernelGGL((k_getrf_ip<2, 4>), grid, block, 0, st, s, n, B, ldb, R, ldr, info);
+    else if (rpl == 2)
+      hipLaunchKernelGGL((k_getrf_ip<2, 8>), grid, block, 0, st, s, n, B, ldb, R, ldr, info);
+    else if (cpw == 4)
+      hipLaunchKernelGGL((k_getrf_ip<4, 4>), grid, block, 0, st, s, n, B, ldb, R, ldr, info);
+    else
+      hipLaunchKernelGGL((k_getrf_ip<4, 8>), grid, block, 0, st, s, n, B, ldb, R, ldr, info);
+    return hipGetLastError();
+  }
+  // LU of 64+ columns over 257..512 rows: the blocked form (it was faster than the
+  // explicit-interchange register kernel from n = 64: 256 x 128, 0.40 -> 0.38 ms)
   if (variant == 1 && n >= 64 && s <= 512)
     return lu_blocked_t<16, 1>(s, n, B, ldb, R, ldr, info, scratch, st);
 #define TSQR_FAC(RPL_, CPW_)                                                                  \
