@@ -489,7 +489,8 @@ def kernel_table(m: int, n: int, s: int, variant: str) -> dict:
                  "flops": 1.0 * m * n * n, "bytes": 16.0 * m * n},
         "gram": {"symbol": "k_gram_f64", "phases": ["gram1", "gram2"],
                  "flops": 1.0 * m * n * (n + 1), "bytes": 8.0 * m * n},
-        "sketch_factor": {"symbol": "k_geqrf_reg" if variant != "rlu" else "k_getrf_reg",
+        "sketch_factor": {"symbol": ("k_geqrf_reg / k_qr_*" if variant != "rlu"
+                                     else "k_getrf_ip / k_getrf_reg / k_lu_*"),
                           "phases": [fac], "flops": None, "bytes": None},
         "potrf": {"symbol": "k_potrf_reg / k_potrf_lds / k_chol_*", "phases": ["potrf1", "potrf2"],
                   "flops": n ** 3 / 3.0, "bytes": None},
