@@ -11,4 +11,5 @@ from .matrices import (  # noqa: F401
     colmajor_padded,
     sigma_logspaced,
     gen_matrix,
+    gen_ternary,
 )

@@ -41,6 +41,13 @@ def gen_matrix(m: int, n: int, kappa: float, seed: int, dtype=np.float64) -> np.
     return np.asfortranarray(A, dtype=dtype)
 
 
+def gen_ternary(m: int, n: int, seed: int) -> np.ndarray:
+    """Column-major m x n FP64 matrix with independent entries drawn uniformly from
+    {-1, 0, 1} (many equal magnitudes: ties in a pivot search)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.asfortranarray(rng.integers(-1, 2, (m, n)).astype(np.float64))
+
+
 def colmajor_padded(A: np.ndarray, lda: int) -> np.ndarray:
     """Copy of A inside a column-major buffer with leading dimension ``lda`` (>= m).
 

@@ -12,7 +12,7 @@ import torch
 
 import oracle
 import paper_2111_11148_amd as tsqr
-from inputs import gen_matrix
+from inputs import gen_matrix, gen_ternary
 from gpu_helpers import gpu_orthogonality, gpu_residual, host, rel_fro
 from sketch_bounds import fp64_sketch_tol
 
@@ -124,6 +124,21 @@ def test_sketch_factor_parity(variant, s, n, kappa):
     assert np.all(np.tril(R0g, -1) == 0) and np.all(np.diag(R0g) > 0)
     growth = 1.0 if variant == tsqr.RQR else 10.0
     assert rel_fro(R0g, R0o) <= 50 * n * EPS * kappa * growth
+
+
+@pytest.mark.parametrize("s,n,seed", [(128, 64, 1), (256, 128, 2), (64, 32, 3), (512, 100, 4),
+                                      (200, 100, 5)])
+def test_sketch_lu_ties_first_position(s, n, seed):
+    """Entries from {-1, 0, 1} keep the eliminated values small integers early on, so
+    several steps see distinct rows with equal |a| in the pivot column (4-6 such steps for
+    these seeds).  The pivot is the first of them in the current row order, as in the
+    oracle's explicit interchanges; another choice would change rows of U by O(1), while
+    the same choices leave only rounding (the matrices have cond <= 7)."""
+    B = gen_ternary(s, n, seed)
+    R0g, info = tsqr.sketch_factor(dev(B), tsqr.RLU)
+    R0o, _, inf_o = oracle.lu_r(B)
+    assert inf_o == 0 and int(info.item()) == 0
+    assert rel_fro(host(R0g), R0o) <= 1e-12
 
 
 def test_sketch_factor_breakdown():

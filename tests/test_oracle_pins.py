@@ -14,7 +14,7 @@ import scipy.linalg
 import scipy.stats
 
 import oracle
-from inputs import sigma_logspaced, gen_matrix
+from inputs import sigma_logspaced, gen_matrix, gen_ternary
 from paper_claims import paper_claims
 
 U64 = 2.0 ** -53  # unit roundoff
@@ -212,6 +212,21 @@ def test_lu_tie_break_first_max():
     assert info == 0 and piv[0] == 0
     lu, ipiv = scipy.linalg.lu_factor(B)
     assert ipiv[0] == 0
+
+
+@pytest.mark.parametrize("s,n,seed", [(128, 64, 1), (256, 128, 2), (200, 100, 5)])
+def test_lu_ties_at_later_steps_match_lapack(s, n, seed):
+    """Entries from {-1, 0, 1}: several steps, after earlier interchanges, see equal
+    magnitudes in the pivot column.  The oracle's whole pivot sequence equals LAPACK's
+    (first maximum in the current row order), and U agrees to rounding."""
+    B = gen_ternary(s, n, seed)
+    R, piv, info = oracle.lu_r(B)
+    assert info == 0
+    lu, ipiv = scipy.linalg.lu_factor(B)
+    assert np.array_equal(piv, ipiv[:n])
+    U = np.triu(lu[:n, :n])
+    d = np.sign(np.diag(U))
+    assert np.allclose(R, d[:, None] * U, rtol=0, atol=1e-13 * np.abs(U).max())
 
 
 def test_lu_zero_pivot_info():
