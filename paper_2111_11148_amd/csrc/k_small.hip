@@ -1935,7 +1935,8 @@ template <int RPL, int CPW>
 __global__ __launch_bounds__(kSmallThreads) void k_b_geqrf(const BItem* __restrict__ items,
                                                            const BProb* __restrict__ probs) {
   const BProb& p = probs[items[blockIdx.x].pid];
-  geqrf_reg_body<RPL, CPW>(p.s, p.n, p.B, p.s, p.R0, p.n, p.info);
+  geqrf_reg_body<RPL, CPW, false, RPL >= 2 && (CPW == 8 || CPW == 4)>(p.s, p.n, p.B, p.s,
+                                                                      p.R0, p.n, p.info);
 }
 
 template <int RPL, int CPW>
