@@ -81,9 +81,7 @@ template <class Put>
 __device__ __forceinline__ void reduce_partials(int kblocks, size_t E,
                                                 const double* __restrict__ part, Put put) {
   for (size_t e = threadIdx.x; e < E; e += blockDim.x) {
-    double acc = 0.0;
-    for (int kb = 0; kb < kblocks; ++kb) acc += part[(size_t)kb * E + e];
-    put(e, acc);
+    put(e, strided_sum(part, E, e, 0, 1, kblocks));
   }
 }
 

@@ -646,8 +646,7 @@ __device__ __forceinline__ void gram_reduce_body(int kblocks, int ntiles, int n,
   const int g = threadIdx.x / 16, o = threadIdx.x % 16;
   const size_t e = (size_t)bx * 16 + o;
   double acc = 0.0;
-  if (e < E)
-    for (int kb = g; kb < kblocks; kb += 16) acc += part[(size_t)kb * E + e];
+  if (e < E) acc = strided_sum(part, E, e, g, 16, kblocks);
   red[g][o] = acc;
   __syncthreads();
   if (g == 0 && e < E) {
@@ -761,8 +760,7 @@ __global__ __launch_bounds__(256) void k_gram_wide_reduce(int kblocks, int npair
   const int g = threadIdx.x / 16, o = threadIdx.x % 16;
   const size_t e = (size_t)blockIdx.x * 16 + o;
   double acc = 0.0;
-  if (e < E)
-    for (int kb = g; kb < kblocks; kb += 16) acc += part[(size_t)kb * E + e];
+  if (e < E) acc = strided_sum(part, E, e, g, 16, kblocks);
   red[g][o] = acc;
   __syncthreads();
   if (g == 0 && e < E) {

@@ -130,6 +130,24 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
+// sum over kb = k0, k0 + stride, ... < kblocks of part[kb E + e], in increasing kb, with
+// eight loads in flight: the adds keep the order of the plain loop (so the result is the
+// same), but the loads no longer wait for one another
+__device__ __forceinline__ double strided_sum(const double* __restrict__ part, size_t E,
+                                              size_t e, int k0, int stride, int kblocks) {
+  double acc = 0.0;
+  int kb = k0;
+  for (; kb + 7 * stride < kblocks; kb += 8 * stride) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(kb + u * stride) * E + e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
+  for (; kb < kblocks; kb += stride) acc += part[(size_t)kb * E + e];
+  return acc;
+}
+
 // The same (wave-uniform) value read from the first active lane, so that the compiler
 // keeps it in scalar registers: needed where it feeds an inline-assembly scalar operand in
 // a kernel whose control flow hides that it is uniform.
