@@ -1331,25 +1331,38 @@ static hipError_t potrf_multi_t(int n, const double* W, int64_t ldw, double* R, 
 }
 
 // ============================================================ small products =========
-// C = A B for upper-triangular A, B: one 16x16 output tile per workgroup, operands
-// staged through LDS in 16-wide chunks of the inner index (only k in [i0, j0+16)).
+// C = A B for upper-triangular A, B: one 16x16 output tile per workgroup.  The operands of
+// the inner indices k in [i0, j0+16) (at most 128 of them) are loaded together, eight
+// 16-wide chunks per thread in flight, and staged in LDS behind one barrier; each entry then
+// sums over k in increasing order (the entries outside the triangles are zeros).
+constexpr int kTrmmMaxK = 128;
 __device__ __forceinline__ void trmm_upper_body(int n, const double* __restrict__ A,
                                                     int64_t lda, const double* __restrict__ B,
                                                     int64_t ldb, double* __restrict__ C,
                                                     int64_t ldc, int bx, int by) {
-  __shared__ double as[16][17], bs[16][17];
+  __shared__ double as[16][kTrmmMaxK + 1], bs[kTrmmMaxK][17];
   const int i0 = 16 * by, j0 = 16 * bx;
   const int ti = threadIdx.x % 16, tj = threadIdx.x / 16;
   const int i = i0 + ti, j = j0 + tj;
   double acc = 0.0;
   if (i0 <= j0 + 15) {
-    for (int k0 = i0; k0 < j0 + 16 && k0 < n; k0 += 16) {
-      const int ka = k0 + tj, kb = k0 + ti;
-      as[ti][tj] = (i < n && ka < n && ka >= i) ? A[(int64_t)ka * lda + i] : 0.0;
-      bs[ti][tj] = (kb < n && j < n && kb <= j) ? B[(int64_t)j * ldb + kb] : 0.0;
-      __syncthreads();
+    const int kend = min(j0 + 16, n);
+    for (int kc = i0; kc < kend; kc += kTrmmMaxK) {  // one round for n <= 128
+      double va[kTrmmMaxK / 16], vb[kTrmmMaxK / 16];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) acc += as[ti][k] * bs[k][tj];
+      for (int u = 0; u < kTrmmMaxK / 16; ++u) {
+        const int ka = kc + 16 * u + tj, kb = kc + 16 * u + ti;
+        va[u] = (i < n && ka < kend && ka >= i) ? A[(int64_t)ka * lda + i] : 0.0;
+        vb[u] = (kb < kend && j < n && kb <= j) ? B[(int64_t)j * ldb + kb] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kTrmmMaxK / 16; ++u) {
+        as[ti][16 * u + tj] = va[u];
+        bs[16 * u + ti][tj] = vb[u];
+      }
+      __syncthreads();
+      const int nk = min(kTrmmMaxK, ((kend - kc + 15) / 16) * 16);
+      for (int k = 0; k < nk; ++k) acc += as[ti][k] * bs[k][tj];
       __syncthreads();
     }
   }
@@ -1824,7 +1837,8 @@ hipError_t launch_trmm_upper(int n, const double* A, int64_t lda, const double* 
 
 hipError_t launch_poison(const int* info, int64_t m, int n, double* Q, int64_t ldq, double* R,
                          int64_t ldr, hipStream_t st) {
-  hipLaunchKernelGGL(k_poison, dim3(1024), dim3(256), 0, st, info, m, n, Q, ldq, R, ldr);
+  // grid-strided fill: a small grid costs little when nothing broke down (the usual case)
+  hipLaunchKernelGGL(k_poison, dim3(256), dim3(256), 0, st, info, m, n, Q, ldq, R, ldr);
   return hipGetLastError();
 }
 
