@@ -475,8 +475,8 @@ def batched_comparison(args):
 
 
 # Kernels of the FP64 chain: the phases (library event names) each one runs under, the
-# algorithmic work of one launch, and the roof that bounds it (SURVEY-style per-unit
-# figures: sketch 2smn flops over 8mn bytes, TRSM mn^2 flops over 16mn bytes, Gram
+# algorithmic work of one launch, and the roof that bounds it (per-unit figures:
+# sketch 2smn flops over 8mn bytes, TRSM mn^2 flops over 16mn bytes, Gram
 # mn(n+1) flops over 8mn bytes; at n = 128 the TRSM's 8 flop/B is below the FP64 ridge of
 # 78.6 TFLOP/s / 8 TB/s = 9.8 flop/B, so it is HBM-bound, while the sketch (64 flop/B) and
 # the Gram (16 flop/B) are FP64-bound).
