@@ -83,7 +83,8 @@ __device__ __forceinline__ void house(double alpha, double xnorm2, double& beta,
   }
 }
 
-// 1 + the smallest k < n with !(d(k) != 0.0) (a zero or NaN diagonal), 0 if there is none;
+// 1 + the smallest k < n with a zero or NaN d(k) (neither d > 0 nor d < 0; note that
+// NaN != 0 holds, so a test of d != 0 would miss NaN), 0 if there is none;
 // the same value in every thread.  Every thread of the workgroup must call it (it has
 // barriers); each thread scans a strided share, so no thread walks the whole diagonal.
 template <class F>
@@ -92,11 +93,13 @@ __device__ __forceinline__ int block_first_bad(int n, F d) {
   if (threadIdx.x == 0) best = 0x7fffffff;
   __syncthreads();
   int mine = 0x7fffffff;
-  for (int k = (int)threadIdx.x; k < n; k += (int)blockDim.x)
-    if (!(d(k) != 0.0)) {
+  for (int k = (int)threadIdx.x; k < n; k += (int)blockDim.x) {
+    const double dk = d(k);
+    if (!(dk > 0.0 || dk < 0.0)) {
       mine = k;  // strided scan: a thread's first hit is its smallest
       break;
     }
+  }
   if (mine != 0x7fffffff) atomicMin(&best, mine);
   __syncthreads();
   return best == 0x7fffffff ? 0 : best + 1;
@@ -647,38 +650,51 @@ __device__ __forceinline__ bool piv_better(double a, int ia, double b, int ib) {
   return (an & !bn) | (an & bn & first) | (!an & !bn & (gt | (eq & first)));
 }
 
-// The preferred (value, index) pair of the wavefront, in every lane.  piv_better is a total
-// order on pairs with distinct indices, so the result does not depend on the order of the
-// combinations: DPP within rows of 16 lanes (as in wave_sum), then the four row winners
-// read into scalars.  All lanes must be active.
-template <int CTRL>
-__device__ __forceinline__ void argmax_dpp_step(double& v, int& idx) {
-  const double ov = dpp_f64<CTRL>(v);
-  const int oi = __builtin_amdgcn_update_dpp(0, idx, CTRL, 0xF, 0xF, false);
-  if (piv_better(ov, oi, v, idx)) {
-    v = ov;
-    idx = oi;
-  }
+// Maximum of a double over the 64 lanes, the same in every lane: DPP within rows of 16
+// lanes (swap pairs, swap halves of quads, rotate by 4 and by 8), then the four row maxima.
+// No lane may hold a NaN; all lanes must be active.
+__device__ __forceinline__ double wave_max_f64(double v) {
+  v = fmax(v, dpp_f64<0xB1>(v));   // quad_perm [1,0,3,2]
+  v = fmax(v, dpp_f64<0x4E>(v));   // quad_perm [2,3,0,1]
+  v = fmax(v, dpp_f64<0x124>(v));  // row_ror:4
+  v = fmax(v, dpp_f64<0x128>(v));  // row_ror:8
+  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)),
+              fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
 }
 
+// Minimum of an int over the 64 lanes (same pattern), the same in every lane.
+template <int CTRL>
+__device__ __forceinline__ int dpp_min_i32(int x) {
+  return min(x, __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ int wave_min_i32(int x) {
+  x = dpp_min_i32<0xB1>(x);
+  x = dpp_min_i32<0x4E>(x);
+  x = dpp_min_i32<0x124>(x);
+  x = dpp_min_i32<0x128>(x);
+  return min(min(__builtin_amdgcn_readlane(x, 0), __builtin_amdgcn_readlane(x, 16)),
+             min(__builtin_amdgcn_readlane(x, 32), __builtin_amdgcn_readlane(x, 48)));
+}
+
+// The preferred (value, index) pair of the wavefront, in every lane.  piv_better is a total
+// order on pairs with distinct indices, so the winner is unique and any way of finding it
+// gives the same pair: if some lane holds a NaN, the smallest index among those lanes;
+// otherwise the largest value, and the smallest index among the lanes that hold it (a
+// maximum and a minimum by DPP, no pairwise comparisons).  The value is read from the
+// winning lane.  All lanes must be active.
 __device__ __forceinline__ void wave_argmax(double& v, int& idx) {
-  argmax_dpp_step<0xB1>(v, idx);   // quad_perm [1,0,3,2]
-  argmax_dpp_step<0x4E>(v, idx);   // quad_perm [2,3,0,1]
-  argmax_dpp_step<0x124>(v, idx);  // row_ror:4
-  argmax_dpp_step<0x128>(v, idx);  // row_ror:8
-  double bv = readlane_f64(v, 0);
-  int bi = __builtin_amdgcn_readlane(idx, 0);
-#pragma unroll
-  for (int row = 1; row < 4; ++row) {
-    const double rv = readlane_f64(v, 16 * row);
-    const int ri = __builtin_amdgcn_readlane(idx, 16 * row);
-    if (piv_better(rv, ri, bv, bi)) {
-      bv = rv;
-      bi = ri;
-    }
+  const bool nan = isnan(v);
+  int cand;
+  if (__ballot(nan) != 0ull) {  // uniform
+    cand = nan ? idx : 0x7fffffff;
+  } else {
+    const double m = wave_max_f64(v);
+    cand = (v == m) ? idx : 0x7fffffff;
   }
-  v = bv;
-  idx = bi;
+  const int best = wave_min_i32(cand);
+  const int src = __builtin_ctzll(__ballot(cand == best));  // some lane holds best
+  v = readlane_f64(v, src);
+  idx = best;
 }
 
 template <int RPL, int CPW, bool EXTL = false>

@@ -141,6 +141,37 @@ def test_sketch_lu_ties_first_position(s, n, seed):
     assert rel_fro(host(R0g), R0o) <= 1e-12
 
 
+@pytest.mark.parametrize("s,n,seed", [(128, 64, 1), (256, 128, 2), (64, 32, 3), (512, 100, 4),
+                                      (200, 100, 5)])
+def test_sketch_lu_nan_pivot_reported(s, n, seed):
+    """The device takes NaN as the largest pivot candidate (a reading of its own: the
+    oracle follows LAPACK's comparison, under which a lone NaN below the diagonal never
+    wins).  A NaN in column 5 then always surfaces at step 5: it is the pivot there, or an
+    earlier pivot row carried it into every row of column 5.  So every LU kernel class must
+    report column 6 (1-based) and put NaN on R0's diagonal there."""
+    B = gen_matrix(s, n, 10.0, seed)
+    B[s // 3, 5] = np.nan
+    R0g, info = tsqr.sketch_factor(dev(B), tsqr.RLU)
+    assert int(info.item()) == 1000 + 6
+    assert np.isnan(host(R0g)[5, 5])
+
+
+@pytest.mark.parametrize("variant", [tsqr.RQR, tsqr.RLU])
+@pytest.mark.parametrize("s,n", [(128, 64), (256, 128), (64, 32), (512, 100), (3000, 200)])
+def test_sketch_factor_nan_diagonal_reported(variant, s, n):
+    """A NaN column of the sketch (what a NaN column of A gives) makes that column's
+    diagonal entry NaN in either factorization; like the oracle (which flags a zero or NaN
+    pivot), every kernel class reports it in info rather than leaving the breakdown to
+    a later stage."""
+    B = gen_matrix(s, n, 10.0, 7)
+    B[:, 9] = np.nan
+    R0g, info = tsqr.sketch_factor(dev(B), variant)
+    _, inf_o = (oracle.householder_r(B) if variant == tsqr.RQR else oracle.lu_r(B)[::2])
+    assert inf_o == 1000 + 10
+    assert int(info.item()) == inf_o
+    assert np.isnan(host(R0g)[9, 9])
+
+
 def test_sketch_factor_breakdown():
     B = gen_matrix(64, 8, 10.0, 1)
     B[:, 3] = 0.0
