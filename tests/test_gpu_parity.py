@@ -172,6 +172,20 @@ def test_sketch_factor_nan_diagonal_reported(variant, s, n):
     assert np.isnan(host(R0g)[9, 9])
 
 
+@pytest.mark.parametrize("variant", [tsqr.RQR, tsqr.RLU])
+def test_nan_entry_of_a_reported_at_the_sketch_factor(variant):
+    """One NaN entry of A fills its column of the sketch with NaN, so the factorization of
+    the sketch breaks down at that column: the device reports the oracle's info (stage 1)
+    and poisons Q and R."""
+    A = gen_matrix(3000, 40, 1e4, 11)
+    A[1234, 17] = np.nan
+    ref = oracle.rxr_cholqr(A, 80, 5, variant=variant)
+    assert ref["info"] == 1000 + 18
+    Q, R, info = tsqr.rxr_cholqr(dev(A), 80, 5, variant=variant)
+    assert int(info.item()) == ref["info"]
+    assert torch.isnan(Q).all() and torch.isnan(R).all()
+
+
 def test_sketch_factor_breakdown():
     B = gen_matrix(64, 8, 10.0, 1)
     B[:, 3] = 0.0
