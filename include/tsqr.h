@@ -466,7 +466,8 @@ int tsqr_probe_stream(int kind, const void* src, void* dst, size_t bytes, int wg
 /* Attainable matrix-core rate probe: `chains` (4, 8, 16) independent accumulator chains
  * per wavefront, `iters` MFMAs each, on waves_per_simd (1, 2, 4, 8) workgroups of four
  * wavefronts per compute unit.  kind 0: FP64 16x16x4, 1: FP32 16x16x4, 2: BF16 16x16x32,
- * 3: BF16 32x32x16 (FP32 accumulation for the BF16 forms).  *flops (host) is set to the
+ * 3: BF16 32x32x16 (FP32 accumulation for the BF16 forms), 4: FP64 16x16x4 with random
+ * operands drawn afresh at every step (kinds 0-3 keep their operands fixed).  *flops (host) is set to the
  * flops of the launch (2 per multiply-add).  Errors: -1 kind, -2 waves_per_simd, -3 chains,
  * -4 iters < 1, -5 d_sink NULL, -6 flops NULL. */
 int tsqr_probe_mfma(int kind, int waves_per_simd, int chains, int64_t iters, double* d_sink,

@@ -232,7 +232,7 @@ def metrics(Q: torch.Tensor, A: torch.Tensor | None = None, R: torch.Tensor | No
 
 
 PROBE_READ, PROBE_WRITE, PROBE_COPY = 0, 1, 2
-PROBE_FP64, PROBE_FP32, PROBE_BF16, PROBE_BF16_32 = 0, 1, 2, 3
+PROBE_FP64, PROBE_FP32, PROBE_BF16, PROBE_BF16_32, PROBE_FP64_RANDOM = 0, 1, 2, 3, 4
 
 
 def probe_stream(kind: int, src: torch.Tensor | None, dst: torch.Tensor | None, nbytes: int,

@@ -67,16 +67,32 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_stream(int kind,
 // kind 0: FP64 16x16x4 (2048 flops), 1: FP32 16x16x4 (2048), 2: BF16 16x16x32 (16384),
 // 3: BF16 32x32x16 (32768).  C independent accumulator chains per wavefront, `iters`
 // steps of each.
-template <int C>
-__global__ __launch_bounds__(kProbeThreads) void k_probe_mfma_f64(int64_t iters, double seed,
-                                                                 double* sink) {
+// (the occupancy hint keeps the accumulators in VGPRs: without it the compiler held them
+// in AGPRs and copied all of them out and back on every iteration, so the loop measured
+// the copies, 51 TFLOP/s, rather than the matrix core)
+// RND: the operands change at every step, to random doubles in [0.5, 1) (52 varying
+// mantissa bits from a linear congruential sequence per lane), as the operands of the
+// method's kernels do; the matrix core's sustained rate depends on its data.
+template <int C, bool RND = false>
+__global__ __launch_bounds__(kProbeThreads) __attribute__((amdgpu_waves_per_eu(2))) void
+k_probe_mfma_f64(int64_t iters, double seed, double* sink) {
   v4d acc[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
-  const double a = seed + threadIdx.x, b = 1.0 / (1.0 + threadIdx.x);
-  for (int64_t it = 0; it < iters; ++it)
+  double a = seed + threadIdx.x, b = 1.0 / (1.0 + threadIdx.x);
+  uint32_t h = 2654435761u * (threadIdx.x + 1u) + blockIdx.x;
+  for (int64_t it = 0; it < iters; ++it) {
+    if constexpr (RND) {
+      h = h * 1664525u + 1013904223u;
+      const uint32_t h2 = h * 22695477u + 1u;
+      a = __builtin_bit_cast(double, 0x3FE0000000000000ull |
+                                         ((unsigned long long)(h & 0xFFFFFu) << 32) | h2);
+      b = __builtin_bit_cast(double, 0x3FE0000000000000ull |
+                                         ((unsigned long long)(h2 & 0xFFFFFu) << 32) | h);
+    }
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = mfma_f64(a, b, acc[c]);
+  }
   double s = 0.0;
 #pragma unroll
   for (int c = 0; c < C; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
@@ -161,6 +177,9 @@ hipError_t probe_mfma_t(int kind, int blocks, int64_t iters, double* sink, hipSt
   else if (kind == 2)
     hipLaunchKernelGGL(k_probe_mfma_bf16<C>, dim3(blocks), dim3(kProbeThreads), 0, st, iters,
                        0.5, sink);
+  else if (kind == 4)
+    hipLaunchKernelGGL((k_probe_mfma_f64<C, true>), dim3(blocks), dim3(kProbeThreads), 0, st,
+                       iters, 0.5, sink);
   else
     hipLaunchKernelGGL(k_probe_mfma_bf16_32<C>, dim3(blocks), dim3(kProbeThreads), 0, st, iters,
                        0.5, sink);

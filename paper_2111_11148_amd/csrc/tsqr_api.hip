@@ -1064,7 +1064,7 @@ int tsqr_probe_stream(int kind, const void* src, void* dst, size_t bytes, int wg
 
 int tsqr_probe_mfma(int kind, int waves_per_simd, int chains, int64_t iters, double* d_sink,
                     double* flops, void* stream) {
-  if (kind < 0 || kind > 3) return -1;
+  if (kind < 0 || kind > 4) return -1;
   if (waves_per_simd != 1 && waves_per_simd != 2 && waves_per_simd != 4 && waves_per_simd != 8)
     return -2;
   if (chains != 4 && chains != 8 && chains != 16) return -3;

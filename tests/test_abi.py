@@ -212,7 +212,8 @@ def test_metrics_and_probe_argument_codes(lib):
     assert g(2, A, Q, 1 << 20, 16, 4, 0, None, None) == -8
     h = lib.tsqr_probe_mfma
     fl = ctypes.c_double()
-    assert h(4, 2, 8, 10, out, ctypes.byref(fl), None) == -1
+    assert h(5, 2, 8, 10, out, ctypes.byref(fl), None) == -1  # kinds 0..4
+    assert h(-1, 2, 8, 10, out, ctypes.byref(fl), None) == -1
     assert h(0, 3, 8, 10, out, ctypes.byref(fl), None) == -2
     assert h(0, 2, 5, 10, out, ctypes.byref(fl), None) == -3
     assert h(0, 2, 8, 0, out, ctypes.byref(fl), None) == -4
