@@ -492,7 +492,7 @@ def kernel_table(m: int, n: int, s: int, variant: str) -> dict:
         "sketch_factor": {"symbol": ("k_geqrf_reg / k_qr_*" if variant != "rlu"
                                      else "k_getrf_ip / k_getrf_reg / k_lu_*"),
                           "phases": [fac], "flops": None, "bytes": None},
-        "potrf": {"symbol": "k_potrf_reg / k_potrf_lds / k_chol_*", "phases": ["potrf1", "potrf2"],
+        "potrf": {"symbol": "k_potrf_lds / k_chol_*", "phases": ["potrf1", "potrf2"],
                   "flops": n ** 3 / 3.0, "bytes": None},
         "trsm_prep": {"symbol": "k_trsm_prep",
                       "phases": ["trsm_prep_r0", "trsm_prep_r1", "trsm_prep_r2"],

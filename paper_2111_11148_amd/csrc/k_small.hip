@@ -1089,17 +1089,6 @@ __device__ __forceinline__ void potrf_reg_body(int n, const double* __restrict__
   if (threadIdx.x == 0 && info && fail_sh >= 0 && *info == 0) *info = 1000 * stage + fail_sh + 1;
 }
 
-template <int RPL, int CPW>
-__global__ __launch_bounds__(kSmallThreads) void k_potrf_reg(int n, const double* __restrict__ W,
-                                                             int64_t ldw, double* __restrict__ R,
-                                                             int64_t ldr, int stage,
-                                                             int* __restrict__ info,
-                                                             double shift,
-                                                             const int* __restrict__ gate) {
-  if (gate && *gate == 0) return;  // gated off on the device
-  potrf_reg_body<RPL, CPW>(n, W, ldw, R, ldr, stage, info, shift);
-}
-
 // Blocked Cholesky of n <= kCholLdsMax columns in one workgroup, the whole upper triangle
 // resident in LDS (n (n + 1) doubles), 16-row panels:
 //  (a) the block row [R11 R12] = R11^{-T} [W11 W12] by right-looking elimination in
@@ -1811,36 +1800,25 @@ hipError_t launch_sketch_factor(int variant, int s, int n, const double* B, int6
   return hipGetLastError();
 }
 
-#ifndef TSQR_POTRF_MULTI_MIN
-#define TSQR_POTRF_MULTI_MIN 64
+#ifndef TSQR_POTRF_MULTI_NB
 #define TSQR_POTRF_MULTI_NB 32
 #endif
-constexpr int kPotrfMultiMin = TSQR_POTRF_MULTI_MIN;  // larger n: one launch per phase
-constexpr int kPotrfMultiNB = TSQR_POTRF_MULTI_NB;
+constexpr int kPotrfMultiNB = TSQR_POTRF_MULTI_NB;  // n > kCholLdsMax: one launch per phase
 
 hipError_t launch_potrf(int n, const double* W, int64_t ldw, double* R, int64_t ldr, int stage,
                         int* info, double* scratch, hipStream_t st, double shift,
                         const int* gate) {
   (void)scratch;
   if (n < 1 || n > kMaxS) return hipErrorInvalidValue;
-  if (n > kPotrfMultiMin && n <= kCholLdsMax) {
+  // one workgroup with the matrix in LDS up to 128 columns (measured against the
+  // column-at-a-time register factorization, one barrier per column, that the batched
+  // kernels use: n = 32, 13.4 -> 10.8 us; n = 64, 33.5 -> 21.5 us; n = 128, 144 -> 49 us)
+  if (n <= kCholLdsMax) {
     hipLaunchKernelGGL(k_potrf_lds, dim3(1), dim3(kSmallThreads), chol_lds_bytes(n), st, n, W,
                        ldw, R, ldr, stage, info, shift, gate);
     return hipGetLastError();
   }
-  if (n > kPotrfMultiMin)
-    return potrf_multi_t<kPotrfMultiNB>(n, W, ldw, R, ldr, stage, info, st, shift, gate);
-  const int cpw = pow2_at_least((n + 15) / 16);  // n <= 64: one row of 64 lanes
-  dim3 grid(1), block(kSmallThreads);
-#define TSQR_POTRF(CPW_)                                                                      \
-  if (cpw == CPW_) {                                                                          \
-    hipLaunchKernelGGL((k_potrf_reg<1, CPW_>), grid, block, 0, st, n, W, ldw, R, ldr, stage, \
-                       info, shift, gate);                                                    \
-    return hipGetLastError();                                                                 \
-  }
-  TSQR_POTRF(1) TSQR_POTRF(2) TSQR_POTRF(4)
-#undef TSQR_POTRF
-  return hipErrorInvalidValue;
+  return potrf_multi_t<kPotrfMultiNB>(n, W, ldw, R, ldr, stage, info, st, shift, gate);
 }
 
 hipError_t launch_trmm_upper(int n, const double* A, int64_t lda, const double* B, int64_t ldb,
