@@ -354,6 +354,29 @@ def test_potrf_breakdown_blocked_panel(n):
     assert np.all(np.tril(Rh, -1) == 0)
 
 
+@pytest.mark.parametrize("n", [6, 40, 64, 100, 128, 200])
+@pytest.mark.parametrize("where", ["diagonal", "off_diagonal"])
+def test_potrf_nan_entry_reported(n, where):
+    """A NaN in W is a breakdown at the first pivot it reaches (a NaN pivot is not
+    positive): a NaN diagonal entry at its own column, an off-diagonal one W(i, j), i < j,
+    at column j.  The device names the column the oracle names (its 1-based index plus
+    1000 stage)."""
+    X = gen_matrix(3 * n + 4, n, 10.0, 31 + n)
+    W = np.asfortranarray(X.T @ X)
+    j = n - 2 if n < 10 else (2 * n) // 3
+    if where == "diagonal":
+        W[j, j] = np.nan
+    else:
+        W[1, j] = W[j, 1] = np.nan
+    _, io = oracle.cholesky_upper(W)
+    assert io == j + 1
+    R, info = tsqr.potrf(dev(W), stage=3)
+    assert int(info.item()) == 3000 + j + 1
+    Rh = host(R)
+    assert np.all(np.isfinite(Rh[:, :j]))
+    assert np.isnan(Rh[j, j])
+
+
 def test_trmm_parity():
     rng = np.random.default_rng(0)
     for n in (1, 7, 32, 128, 200):
